@@ -1,0 +1,239 @@
+"""Benchmark of the token-aware clustering build path on one MI355X.
+
+One step = one pass of the whole hot path over the resident synthetic input:
+group by token + budget, seeded initial centroids, 10 Lloyd iterations
+(assign + update, replayed from one captured HIP graph), the final assignment,
+PQ training on the normalised residuals of a seeded sample and the fused
+residual + PQ encoding of every vector.
+
+Metric (vectors assigned per second per Lloyd iteration) = N * iters / Lloyd
+time, Lloyd time measured with HIP events around the graph replay inside each
+step.  The BF16 screen is the headline; the FP32 screen runs the same graph
+for comparison and must give identical assignments.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"bf16": 2500.0, "fp32": 157.3}   # dense MFMA TFLOP/s of an MI355X
+HBM_PEAK = 8000.0                         # GB/s
+
+WORKLOAD_TEXT = {
+    "c1": "10M token vectors x 128 fp32 (L2-normalised), Zipf(1.0) token ids over 30,522, 4 sub-centres per "
+          "token (sigma 0.25), K=262,144 centroids, 10 Lloyd iterations, PQ M=32 x 256 trained on a 1M "
+          "residual sample, all 10M encoded",
+    "c3": "50M token vectors x 128 fp32, Zipf(1.0) over 30,522 ids, K=2,097,152 centroids, 10 Lloyd iterations, "
+          "PQ M=32 x 256 on a 1M sample, all 50M encoded",
+    "c0": "200k token vectors x 128 fp32, Zipf(1.1) over 2,000 ids, K=8,192, 10 Lloyd iterations",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(x, tok, w, sample_rows: int, seed: int = 0):
+    """Time the oracle's float64 assignment of a uniform row sample (a row's
+    assignment depends only on its token's centroids) on the host cores."""
+    import datagen
+    import oracle
+    from oracle.budget import BudgetParams
+
+    t0 = time.time()
+    perm, seg_off, counts = oracle.group_by_token(tok, w.vocab)
+    xs = x[perm]
+    spread = oracle.spreads(xs, seg_off)
+    kappa = oracle.budget(counts, spread, w.k, BudgetParams())
+    cent_off = oracle.cent_offsets(kappa)
+    picks = datagen.init_picks(counts, kappa, w.seed)
+    C0 = oracle.init_centroids(xs, seg_off, cent_off, picks)
+    log(f"cpu_baseline: oracle preparation {time.time() - t0:.1f}s")
+    rows = np.sort(np.random.default_rng([seed, 11]).choice(xs.shape[0], sample_rows, replace=False))
+    t0 = time.perf_counter()
+    oracle.assign_rows(xs, rows, seg_off, C0, cent_off, decide="fp64")
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": sample_rows / dt, "unit": "vectors/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample_rows} uniformly sampled rows of the same workload assigned by the float64 oracle "
+                      f"against their tokens' initial centroids ({dt:.1f}s on {threads} threads)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c1", choices=["c0", "c1", "c3"])
+    ap.add_argument("--iters", type=int, default=10)
+    ap.add_argument("--cpu-sample", type=int, default=50_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
+              f"described but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import datagen
+    import paper_2604_28142_amd as tac
+    from paper_2604_28142_amd import index as IX
+
+    w = datagen.WORKLOADS[args.config]
+    t0 = time.time()
+    x_h, tok_h = datagen.make(w)
+    N = x_h.shape[0]
+    log(f"data: {N} x 128 generated in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(x_h).to(dev)
+    tok = torch.from_numpy(tok_h).to(dev)
+    ctx = tac.Context(0)
+    stream = torch.cuda.current_stream(dev)
+
+    # one eager pass sizes the workspace and gives the budget for the plan
+    idx = IX.group_and_budget(ctx, x, tok, w.vocab, w.k)
+    counts, kappa = idx.host["counts"], idx.host["kappa"]
+    picks = datagen.init_picks(counts, kappa, w.seed)
+    sample = datagen.pq_sample(N, w.pq_sample, w.seed)
+    init_rows = datagen.pq_init_rows(sample.shape[0], w.pq_ksub, w.seed)
+    IX.init_centroids(ctx, idx, picks)
+    C0 = idx.C.clone()
+    screen = kappa > 4
+    F = 2.0 * 128 * float((counts[screen] * kappa[screen]).sum())   # algorithmic contraction flops per assign
+    log(f"budget: K={int(kappa.sum())}, max kappa={int(kappa.max())}, screen flops/assign={F:.3e}")
+
+    loops = {}
+    for name, prec in (("bf16", tac.TAC_BF16), ("fp32", tac.TAC_FP32)):
+        if name == "fp32" and args.no_fp32:
+            continue
+        lp = IX.LloydLoop(ctx, idx, iters=args.iters, precision=prec)
+        idx.C.copy_(C0)
+        lp.run()                       # eager: sizes the workspace, sets kernel attributes
+        torch.cuda.synchronize()
+        lp.capture()
+        loops[name] = lp
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def lloyd_ms(lp):
+        idx.C.copy_(C0)
+        ev[0].record(stream)
+        lp.replay()
+        ev[1].record(stream)
+        ev[1].synchronize()
+        return ev[0].elapsed_time(ev[1])
+
+    def step(lp):
+        """One pass of the whole path; returns (step ms, Lloyd ms)."""
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = tac.tac_budget(ctx, x, tok, w.vocab, w.k, perm=idx.perm, xs=idx.xs, seg_off=idx.seg_off,
+                             cent_off=idx.cent_off)
+        assert np.array_equal(out["kappa"], kappa)
+        IX.init_centroids(ctx, idx, picks)
+        ev[0].record(stream)
+        lp.replay()
+        ev[1].record(stream)
+        IX.final_assign(ctx, idx, precision=lp.precision)
+        IX.train_pq(ctx, idx, sample, init_rows, M=w.pq_m, ksub=w.pq_ksub, iters=10)
+        IX.encode_all(ctx, idx)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, ev[0].elapsed_time(ev[1])
+
+    head = loops["bf16"]
+    for _ in range(args.warmup):
+        step(head)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    res = [step(head) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t_start) * 1e3
+    step_ms = [r[0] for r in res]
+    lloyd = [r[1] for r in res]
+    final_bf16 = idx.assign.clone()
+    lloyd_med = float(np.median(lloyd))
+    value = N * args.iters / (lloyd_med / 1e3)
+    log(f"bf16: steps {['%.1f' % s for s in step_ms]} ms, Lloyd {['%.2f' % l for l in lloyd]} ms")
+
+    extra = {}
+    if "fp32" in loops:
+        fp32_ms = lloyd_ms(loops["fp32"])
+        IX.final_assign(ctx, idx, precision=tac.TAC_FP32)
+        same = bool(torch.equal(idx.assign, final_bf16))
+        extra["fp32"] = {"lloyd_ms_per_iter": fp32_ms / args.iters,
+                         "value": N * args.iters / (fp32_ms / 1e3)}
+        extra["bf16_over_fp32"] = fp32_ms / lloyd_med
+        extra["final_argmin_identical"] = same
+        log(f"fp32: Lloyd {fp32_ms:.1f} ms; identical final assignments: {same}")
+
+    # dominant kernel: the persistent assignment kernel, timed with HIP events on its stream
+    ctx.enable_timing(True)
+    idx.C.copy_(C0)
+    kms = {}
+    for name, prec in (("bf16", tac.TAC_BF16), ("fp32", tac.TAC_FP32)):
+        if name not in loops:
+            continue
+        vals = []
+        for _ in range(3):
+            tac.tac_assign(ctx, idx.xs, idx.C, idx.cent_off, idx.assign, seg_off=idx.seg_off, precision=prec)
+            vals.append(ctx.kernel_ms(tac._lib.TAC_SLOT_ASSIGN))
+        kms[name] = float(np.mean(vals))
+    stats = tac.tac_assign_stats(ctx)
+    tac.tac_update(ctx, idx.xs, idx.seg_off, idx.assign, idx.C, loops["bf16"].other)
+    upd_ms = ctx.kernel_ms(tac._lib.TAC_SLOT_UPDATE)
+    IX.encode_all(ctx, idx)
+    enc_ms = ctx.kernel_ms(tac._lib.TAC_SLOT_ENCODE)
+    ctx.enable_timing(False)
+    achieved = F / (kms["bf16"] / 1e3) / 1e12
+    extra["kernels_ms"] = {"assign_bf16": kms.get("bf16"), "assign_fp32": kms.get("fp32"), "update_means": upd_ms,
+                           "pq_encode": enc_ms}
+    extra["assign_counters"] = stats
+    extra["lloyd_ms_per_iter"] = lloyd_med / args.iters
+    extra["screen_flops_per_assign"] = F
+    extra["mfma_executed_tflops_bf16x3"] = 3 * achieved
+    if "fp32" in kms:
+        extra["fp32_roofline_frac"] = F / (kms["fp32"] / 1e3) / 1e12 / PEAK["fp32"]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        n_cpu = min(args.cpu_sample, N)
+        cpu = cpu_baseline(x_h, tok_h, w, n_cpu)
+        cpu["value"] = float(cpu["value"])
+
+    line = {
+        "metric": "vectors assigned/sec per Lloyd iter (bf16 screen, identical argmins to fp32)",
+        "value": value,
+        "unit": "vectors/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": float(np.mean(step_ms)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {WORKLOAD_TEXT[args.config]}", "vectors": N, "tokens": w.vocab,
+                   "centroids": w.k, "lloyd_iters": args.iters, "budget": "mu=128 tau=256 eps=4 theta=39",
+                   "timed_region_ms": wall},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["bf16"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK["bf16"], "traffic": None,
+                     "kernel": "assign_main<bf16> (persistent screen + top-4 + certificate)"},
+        "cpu_baseline": cpu,
+        **extra,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

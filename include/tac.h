@@ -1,0 +1,216 @@
+/*
+ * tac.h -- C ABI of libtac, the MI355X (gfx950) token-aware clustering library.
+ *
+ * The library computes the index-build path of Token-Aware Clustering
+ * (Sect. 2.1 of the paper): group token vectors by token id, give every token a
+ * centroid budget from its frequency and spread (Phases 1-4), run Lloyd's
+ * k-means independently inside every token's vectors, and compress the
+ * normalised residuals with product quantisation (Sect. 2.1, "Residuals
+ * Compression"; M = 32 subspaces of 8-bit codes in Sect. 3.1).
+ *
+ * Conventions shared by every call
+ *  - Pointers ending in _d are device pointers (HIP device memory of the
+ *    context's device); pointers ending in _h are host pointers.  Arrays are
+ *    dense and row-major; vectors are float32 rows of d = 128 values.
+ *  - The caller owns every input and output buffer.  The context owns only its
+ *    workspace, which grows on demand up to max_workspace_bytes and is freed
+ *    by tac_ctx_destroy.  No call keeps a caller pointer after it returns.
+ *  - Every call except tac_budget, tac_init_centroids and tac_assign_stats only
+ *    enqueues work on the context's HIP stream and returns; the caller keeps
+ *    buffers alive until that stream has finished the work.  These calls may
+ *    be captured into a HIP graph once one eager call of the same sizes has
+ *    grown the workspace (growth is refused during capture).
+ *  - Arguments are checked on the host before anything is launched; on any
+ *    error nothing is enqueued and the call returns a negative status, with a
+ *    message in tac_last_error().  No call aborts or throws.
+ *  - Results are deterministic: the same inputs give bitwise-identical
+ *    outputs, independent of launch shapes and of what else is in a batch.
+ *  - Assignments and PQ codes are the argmin of a canonical FP32 squared
+ *    distance over the candidate set, lowest index on equal values:
+ *        acc = 0; for i in 0..d-1: t = x_i - c_i; acc = acc + t*t
+ *    with every operation rounded to float32 and no fused multiply-add.
+ *    Matrix-core screens only nominate candidates; a rigorous error bound
+ *    certifies that no other candidate can win, else the vector is rescored
+ *    exhaustively.  TAC_FP32 and TAC_BF16 therefore return identical argmins.
+ *  - One context per host thread, or external locking.
+ */
+#ifndef TAC_H
+#define TAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tac_ctx_s* tac_ctx;
+
+typedef enum {
+    TAC_OK = 0,
+    TAC_E_INVAL = -1,       /* bad argument (sizes, NULL, d != 128, ...) */
+    TAC_E_INFEASIBLE = -2,  /* no budget satisfies the bounds for this K */
+    TAC_E_NOMEM = -3,       /* workspace would exceed max_workspace_bytes, or growth during capture */
+    TAC_E_HIP = -4,         /* a HIP runtime call failed; the HIP error string is in tac_last_error() */
+    TAC_E_UNSEEN_TOKEN = -5 /* a token with vectors has no centroids (reported by tac_assign_stats) */
+} tac_status;
+
+typedef enum {
+    TAC_FP32 = 0,  /* FP32 matrix-core screen (v_mfma_f32_16x16x4f32) */
+    TAC_BF16 = 1   /* BF16 matrix-core screen, FP32 accumulation: x.c from three BF16
+                      products of hi/lo splits (v_mfma_f32_16x16x32_bf16) */
+} tac_precision;
+
+typedef enum {
+    TAC_THETA_FILL_THEN_RELAX = 0, /* fill up to the theta caps, then relax theta to n_j */
+    TAC_THETA_SOFT = 1             /* drop theta from the start when the caps cannot hold B */
+} tac_theta_policy;
+
+/* Budget parameters (Sect. 2.1, Phases 1-3; values of Sect. 3.1: 128, 256, 4, 39). */
+typedef struct {
+    int64_t mu;            /* micro tokens: n < mu get 1 centroid */
+    int64_t tau;           /* small tokens: mu <= n < tau get 2; n >= tau are active */
+    int64_t eps;           /* floor: every active token gets at least eps */
+    double theta;          /* cap: n_j / kappa_j >= theta (theta <= 0: no cap) */
+    int32_t theta_policy;  /* tac_theta_policy */
+} tac_budget_params;
+
+/* Counters of the last tac_assign on a context (see tac_assign_stats). */
+typedef struct {
+    int64_t rows;          /* rows assigned */
+    int64_t screened;      /* rows decided by a matrix-core screen plus certificate */
+    int64_t fallback;      /* screened rows whose certificate failed -> exhaustive rescoring */
+    int64_t unassigned;    /* rows whose token has no centroid (assign = -1) */
+} tac_assign_counters;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  The workspace may grow to
+ * max_workspace_bytes (0 = no limit).  On success *out holds the context. */
+tac_status tac_ctx_create(int device, void* hip_stream, size_t max_workspace_bytes, tac_ctx* out);
+
+/* Switch the stream later calls enqueue on.  The caller orders it after any
+ * work still in flight on the previous stream that uses the workspace. */
+tac_status tac_ctx_set_stream(tac_ctx ctx, void* hip_stream);
+
+/* Kernel timing (measurement aid).  When enabled, each entry point records HIP
+ * events on the context's stream around its dominant kernel, one slot each:
+ *  TAC_SLOT_ASSIGN  the persistent assignment kernel of tac_assign
+ *  TAC_SLOT_UPDATE  the centroid-mean kernel of tac_update
+ *  TAC_SLOT_ENCODE  the fused residual + PQ encode kernel of pq_encode
+ * tac_kernel_ms waits for the slot's stop event and returns the elapsed time of
+ * its last recording (TAC_E_INVAL if never recorded).  Keep timing disabled
+ * while capturing a graph. */
+#define TAC_KERNEL_SLOTS 3
+enum { TAC_SLOT_ASSIGN = 0, TAC_SLOT_UPDATE = 1, TAC_SLOT_ENCODE = 2 };
+tac_status tac_ctx_enable_timing(tac_ctx ctx, int enable);
+tac_status tac_kernel_ms(tac_ctx ctx, int slot, float* ms);
+
+/* Wait for the context's stream, then free the workspace and the context. */
+void tac_ctx_destroy(tac_ctx ctx);
+
+/* Message of the last non-OK status returned on this host thread ("" if none). */
+const char* tac_last_error(void);
+
+/* Group by token and budget (Sect. 2.1, Phases 1-4).  Synchronous.
+ *  x_d      [N, d] float32 token vectors; tok_d [N] int32 token ids in [0, T).
+ *  K        total number of centroids (sum of kappa).
+ *  params   NULL = the defaults of Sect. 3.1 (128, 256, 4, 39, fill-then-relax).
+ *  spread_override_h  [T] float64 or NULL: when given, the budget uses these
+ *           spreads instead of the ones computed on the GPU (spread_h still
+ *           receives the GPU values).
+ * Outputs (each may be NULL unless noted):
+ *  perm_d   [N] int32: sorted row i is input row perm_d[i]; segments ascend by
+ *           token id and keep input order inside a token (stable).  Required.
+ *  xs_d     [N, d] float32: the token-sorted rows x[perm].
+ *  seg_off_d/_h [T+1] int64: token j owns sorted rows [seg_off[j], seg_off[j+1]).
+ *  count_h  [T] int64 vectors per token;  spread_h [T] float64 spread
+ *           s_j = (1/n_j) sum ||x - mean_j||^2 (two-pass, float64).
+ *  kappa_h  [T] int64 centroids per token (sum = K).
+ *  cent_off_d/_h [T+1] int64: token j owns centroids [cent_off[j], cent_off[j+1]).
+ * Errors: TAC_E_INVAL for token ids outside [0, T) or bad sizes,
+ * TAC_E_INFEASIBLE when K is below the tail plus eps per active token or above
+ * the number of active vectors. */
+tac_status tac_budget(tac_ctx ctx, const float* x_d, const int32_t* tok_d, int64_t N, int32_t d,
+                      int32_t T, int64_t K, const tac_budget_params* params,
+                      const double* spread_override_h, int32_t* perm_d, float* xs_d,
+                      int64_t* seg_off_d, int64_t* seg_off_h, int64_t* count_h, double* spread_h,
+                      int64_t* kappa_h, int64_t* cent_off_d, int64_t* cent_off_h);
+
+/* The budget alone (Phases 1-4 of Sect. 2.1) from per-token statistics, on the
+ * host: counts_h [T] int64 vectors per token, spread_h [T] float64 spreads.
+ * kappa_h [T] int64 output (sum = K); tier2_h (nullable) receives the number
+ * of units placed after the theta caps were relaxed.  This is the budget
+ * tac_budget applies after computing the statistics on the GPU; it needs no
+ * device.  Errors as for tac_budget. */
+tac_status tac_budget_from_stats(const int64_t* counts_h, const double* spread_h, int32_t T, int64_t K,
+                                 const tac_budget_params* params, int64_t* kappa_h, int64_t* tier2_h);
+
+/* Seeded initial centroids (the paper states none): centroid k of token j is
+ * sorted row seg_off[j] + picks_d[k], with picks_d[k] in [0, n_j).
+ * picks_d [K] int32; C_d [K, d] float32 output.  Synchronous (validates picks). */
+tac_status tac_init_centroids(tac_ctx ctx, const float* xs_d, const int64_t* seg_off_d,
+                              const int64_t* cent_off_d, int32_t T, int32_t d,
+                              const int32_t* picks_d, int64_t K, float* C_d);
+
+/* Assignment step of per-token Lloyd (Sect. 2.1): every row goes to the
+ * nearest centroid of its own token (canonical FP32 distance, lowest index on
+ * ties).  Asynchronous.
+ * Segments are given either by seg_off_d (rows of x_d token-sorted) or by tok_d
+ * (rows in any order, grouped internally; the serving path); exactly one of
+ * the two is non-NULL.
+ *  C_d [K, d] float32 centroids, cent_off_d [T+1] int64.
+ *  assign_d [N] int32 output: global centroid id, or -1 for a row whose token
+ *           has no centroid (or, with tok_d, an id outside [0, T)).
+ *  dist_d   [N] float32 output or NULL: canonical distance to that centroid.
+ *  inertia_d device float64 scalar or NULL: sum of dist over assigned rows,
+ *           summed in float64 in a fixed order (within-cluster sum of squares). */
+tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* seg_off_d, const int32_t* tok_d,
+                      int64_t N, int32_t d, int32_t T, const float* C_d, const int64_t* cent_off_d,
+                      int64_t K, int32_t precision, int32_t* assign_d, float* dist_d,
+                      double* inertia_d);
+
+/* Counters of the last tac_assign on this context.  Synchronises the stream. */
+tac_status tac_assign_stats(tac_ctx ctx, tac_assign_counters* out);
+
+/* Update step of Lloyd (Sect. 2.1): each centroid becomes the mean of the rows
+ * assigned to it; a centroid with no rows keeps C_old.  Asynchronous.
+ *  xs_d [N, d] token-sorted rows; seg_off_d [T+1]; assign_d [N] (rows with -1
+ *  are ignored); C_old_d, C_new_d [K, d] float32 (may not alias);
+ *  count_d [K] int64 output or NULL.
+ * Sums run in a fixed order: compensated float32 for tokens with at most
+ * 65,536 rows, float64 above; the mean is rounded to float32. */
+tac_status tac_update(tac_ctx ctx, const float* xs_d, const int64_t* seg_off_d, int32_t T, int64_t N,
+                      int32_t d, const int32_t* assign_d, const float* C_old_d, int64_t K,
+                      float* C_new_d, int64_t* count_d);
+
+/* Residuals (Sect. 2.1, "Residuals Compression"): for i < n, with
+ * row = rows_d ? rows_d[i] : i, r = x[row] - C[assign[row]], rho = ||r||,
+ * u = r / rho (u = 0 when rho = 0; normalize = 0 keeps u = r).  Asynchronous.
+ *  R_d [n, d] float32 output; rnorm_d [n] float32 output or NULL.
+ *  rows_d [n] int64 or NULL.  Rows with assign -1 give u = 0, rho = 0. */
+tac_status tac_residuals(tac_ctx ctx, const float* x_d, const int32_t* assign_d, const float* C_d,
+                         int64_t K, const int64_t* rows_d, int64_t n, int32_t d, int normalize,
+                         float* R_d, float* rnorm_d);
+
+/* PQ codebook training (Sect. 3.1: M subspaces, 8-bit codes): `iters` Lloyd
+ * iterations per subspace on the rows R_d [n, d], subspace m = coordinates
+ * [m*d/M, (m+1)*d/M).  init_d and codebooks_d are [M, ksub, d/M] float32
+ * (may alias).  Empty codes keep their value.  Asynchronous.
+ * Requires d % M == 0, d/M == 4, ksub <= 256. */
+tac_status pq_train(tac_ctx ctx, const float* R_d, int64_t n, int32_t d, int32_t M, int32_t ksub,
+                    int32_t iters, const float* init_d, float* codebooks_d);
+
+/* Residual + normalise + PQ encode, fused (Sect. 2.1): codes_d [n, M] uint8,
+ * code m = argmin over the ksub codes of the canonical distance between the
+ * subvector m of u and the code vector.  rnorm_d [n] float32 or NULL.
+ * assign_d [n] int32 (the row's centroid; -1 gives codes 0 and rho 0).
+ * normalize = 0 encodes r itself.  Asynchronous. */
+tac_status pq_encode(tac_ctx ctx, const float* x_d, const int32_t* assign_d, const float* C_d,
+                     int64_t K, int64_t n, int32_t d, const float* codebooks_d, int32_t M,
+                     int32_t ksub, int normalize, uint8_t* codes_d, float* rnorm_d);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TAC_H */

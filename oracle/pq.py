@@ -95,13 +95,17 @@ def pq_encode(u, codebooks, decide="fp64", topk=0, chunk=8192):
     return codes
 
 
-def pq_train(R, M, ksub, iters, init_rows, decide="fp64"):
+def pq_train(R, M, ksub, iters, init_rows=None, decide="fp64", init_codebooks=None):
     """Codebooks float32[M, ksub, d/M]: Lloyd per subspace on the training rows
-    R (float32[n, d]), starting from the slices of rows ``init_rows``."""
+    R (float32[n, d]), starting from the slices of rows ``init_rows`` (or from
+    ``init_codebooks`` when given)."""
     n, d = R.shape
     dsub = d // M
     R = np.asarray(R)
-    cb = np.stack([_sub(R[np.asarray(init_rows)], m, dsub) for m in range(M)]).astype(np.float32)
+    if init_codebooks is not None:
+        cb = np.asarray(init_codebooks, dtype=np.float32).copy()
+    else:
+        cb = np.stack([_sub(R[np.asarray(init_rows)], m, dsub) for m in range(M)]).astype(np.float32)
     for _ in range(iters):
         codes = pq_encode(R, cb, decide=decide)
         new = cb.copy()

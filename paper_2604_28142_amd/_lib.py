@@ -1,0 +1,251 @@
+"""ctypes binding of libtac (C ABI declared in include/tac.h).
+
+Argument marshalling only: device arrays are torch tensors on the context's
+GPU (their ``data_ptr()`` is passed), host arrays are NumPy arrays, and every
+computation happens in the HIP kernels of libtac.so.  A missing or unloadable
+library raises immediately; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtac.so")
+
+TAC_OK, TAC_E_INVAL, TAC_E_INFEASIBLE, TAC_E_NOMEM, TAC_E_HIP, TAC_E_UNSEEN_TOKEN = 0, -1, -2, -3, -4, -5
+TAC_FP32, TAC_BF16 = 0, 1
+TAC_THETA_FILL_THEN_RELAX, TAC_THETA_SOFT = 0, 1
+
+_STATUS = {TAC_E_INVAL: "TAC_E_INVAL", TAC_E_INFEASIBLE: "TAC_E_INFEASIBLE", TAC_E_NOMEM: "TAC_E_NOMEM",
+           TAC_E_HIP: "TAC_E_HIP", TAC_E_UNSEEN_TOKEN: "TAC_E_UNSEEN_TOKEN"}
+
+EXPORTS = ["tac_ctx_create", "tac_ctx_set_stream", "tac_ctx_destroy", "tac_last_error", "tac_budget",
+           "tac_budget_from_stats",
+           "tac_init_centroids", "tac_assign", "tac_assign_stats", "tac_update", "tac_residuals", "pq_train",
+           "pq_encode", "tac_ctx_enable_timing", "tac_kernel_ms"]
+TAC_SLOT_ASSIGN, TAC_SLOT_UPDATE, TAC_SLOT_ENCODE = 0, 1, 2
+
+
+class TacError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class BudgetParams(C.Structure):
+    _fields_ = [("mu", C.c_int64), ("tau", C.c_int64), ("eps", C.c_int64), ("theta", C.c_double),
+                ("theta_policy", C.c_int32)]
+
+
+class AssignCounters(C.Structure):
+    _fields_ = [("rows", C.c_int64), ("screened", C.c_int64), ("fallback", C.c_int64), ("unassigned", C.c_int64)]
+
+
+_P = C.c_void_p
+_I64 = C.c_int64
+_I32 = C.c_int32
+
+_SIGS = {
+    "tac_ctx_create": (C.c_int, [C.c_int, _P, C.c_size_t, C.POINTER(_P)]),
+    "tac_ctx_set_stream": (C.c_int, [_P, _P]),
+    "tac_ctx_destroy": (None, [_P]),
+    "tac_ctx_enable_timing": (C.c_int, [_P, C.c_int]),
+    "tac_kernel_ms": (C.c_int, [_P, C.c_int, C.POINTER(C.c_float)]),
+    "tac_last_error": (C.c_char_p, []),
+    "tac_budget": (C.c_int, [_P, _P, _P, _I64, _I32, _I32, _I64, C.POINTER(BudgetParams), _P, _P, _P, _P, _P, _P,
+                             _P, _P, _P, _P]),
+    "tac_budget_from_stats": (C.c_int, [_P, _P, _I32, _I64, C.POINTER(BudgetParams), _P, _P]),
+    "tac_init_centroids": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _P, _I64, _P]),
+    "tac_assign": (C.c_int, [_P, _P, _P, _P, _I64, _I32, _I32, _P, _P, _I64, _I32, _P, _P, _P]),
+    "tac_assign_stats": (C.c_int, [_P, C.POINTER(AssignCounters)]),
+    "tac_update": (C.c_int, [_P, _P, _P, _I32, _I64, _I32, _P, _P, _I64, _P, _P]),
+    "tac_residuals": (C.c_int, [_P, _P, _P, _P, _I64, _P, _I64, _I32, C.c_int, _P, _P]),
+    "pq_train": (C.c_int, [_P, _P, _I64, _I32, _I32, _I32, _I32, _P, _P]),
+    "pq_encode": (C.c_int, [_P, _P, _P, _P, _I64, _I64, _I32, _P, _I32, _I32, C.c_int, _P, _P]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load libtac.so (torch is imported first so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2604_28142_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != TAC_OK:
+        raise TacError(status, load().tac_last_error().decode())
+
+
+def _dptr(t):
+    """Device pointer of a contiguous torch tensor on the GPU (None -> NULL)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("device arguments must be torch tensors on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("device tensors must be contiguous")
+    return t.data_ptr()
+
+
+def _hptr(a, dtype):
+    """Host pointer of a contiguous NumPy array of the given dtype (None -> NULL)."""
+    if a is None:
+        return None
+    if not (isinstance(a, np.ndarray) and a.dtype == dtype and a.flags.c_contiguous):
+        raise TypeError(f"host arguments must be C-contiguous numpy {np.dtype(dtype).name} arrays")
+    return a.ctypes.data
+
+
+def _check_dtype(t, dtype, name):
+    if t is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+
+
+class Context:
+    """A libtac context on one GPU, enqueueing on a torch stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None, max_workspace: int = 0):
+        lib = load()
+        torch.cuda.init()
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = _P()
+        _check(lib.tac_ctx_create(device, self.stream.cuda_stream, max_workspace, C.byref(h)))
+        self.handle = h
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        _check(load().tac_ctx_set_stream(self.handle, stream.cuda_stream))
+        self.stream = stream
+
+    def enable_timing(self, on: bool = True):
+        _check(load().tac_ctx_enable_timing(self.handle, int(on)))
+
+    def kernel_ms(self, slot: int) -> float:
+        """Elapsed ms of the last recording of a timing slot (HIP events on the context's stream)."""
+        v = C.c_float()
+        _check(load().tac_kernel_ms(self.handle, slot, C.byref(v)))
+        return float(v.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().tac_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def tac_budget(ctx: Context, x, tok, T: int, K: int, params: BudgetParams | None = None, spread_override=None,
+               perm=None, xs=None, seg_off=None, cent_off=None):
+    """Group by token and budget.  Returns a dict of host arrays
+    (seg_off, counts, spread, kappa, cent_off); device outputs are written in place."""
+    N, d = x.shape
+    _check_dtype(x, torch.float32, "x")
+    _check_dtype(tok, torch.int32, "tok")
+    _check_dtype(perm, torch.int32, "perm")
+    _check_dtype(seg_off, torch.int64, "seg_off")
+    _check_dtype(cent_off, torch.int64, "cent_off")
+    out = {"seg_off": np.zeros(T + 1, np.int64), "counts": np.zeros(T, np.int64),
+           "spread": np.zeros(T, np.float64), "kappa": np.zeros(T, np.int64), "cent_off": np.zeros(T + 1, np.int64)}
+    so = None
+    if spread_override is not None:
+        spread_override = np.ascontiguousarray(spread_override, dtype=np.float64)
+        so = _hptr(spread_override, np.float64)
+    _check(load().tac_budget(ctx.handle, _dptr(x), _dptr(tok), N, d, T, K, C.byref(params) if params else None, so,
+                             _dptr(perm), _dptr(xs), _dptr(seg_off), _hptr(out["seg_off"], np.int64),
+                             _hptr(out["counts"], np.int64), _hptr(out["spread"], np.float64),
+                             _hptr(out["kappa"], np.int64), _dptr(cent_off), _hptr(out["cent_off"], np.int64)))
+    return out
+
+
+def tac_budget_from_stats(counts, spread, K: int, params: BudgetParams | None = None):
+    """Host-only budget from per-token counts and spreads; returns (kappa int64[T], tier-2 units)."""
+    counts = np.ascontiguousarray(counts, dtype=np.int64)
+    spread = np.ascontiguousarray(spread, dtype=np.float64)
+    T = counts.shape[0]
+    kappa = np.zeros(T, np.int64)
+    tier2 = np.zeros(1, np.int64)
+    _check(load().tac_budget_from_stats(_hptr(counts, np.int64), _hptr(spread, np.float64), T, K,
+                                        C.byref(params) if params else None, _hptr(kappa, np.int64),
+                                        _hptr(tier2, np.int64)))
+    return kappa, int(tier2[0])
+
+
+def tac_init_centroids(ctx: Context, xs, seg_off, cent_off, picks, C_out):
+    T = seg_off.shape[0] - 1
+    _check_dtype(picks, torch.int32, "picks")
+    _check(load().tac_init_centroids(ctx.handle, _dptr(xs), _dptr(seg_off), _dptr(cent_off), T, xs.shape[1],
+                                     _dptr(picks), C_out.shape[0], _dptr(C_out)))
+
+
+def tac_assign(ctx: Context, x, C_cent, cent_off, assign, seg_off=None, tok=None, precision: int = TAC_FP32,
+               dist=None, inertia=None):
+    N, d = x.shape
+    T = cent_off.shape[0] - 1
+    _check_dtype(assign, torch.int32, "assign")
+    _check_dtype(dist, torch.float32, "dist")
+    _check_dtype(inertia, torch.float64, "inertia")
+    _check_dtype(tok, torch.int32, "tok")
+    _check(load().tac_assign(ctx.handle, _dptr(x), _dptr(seg_off), _dptr(tok), N, d, T, _dptr(C_cent),
+                             _dptr(cent_off), C_cent.shape[0], precision, _dptr(assign), _dptr(dist),
+                             _dptr(inertia)))
+
+
+def tac_assign_stats(ctx: Context) -> dict:
+    c = AssignCounters()
+    _check(load().tac_assign_stats(ctx.handle, C.byref(c)))
+    return {"rows": c.rows, "screened": c.screened, "fallback": c.fallback, "unassigned": c.unassigned}
+
+
+def tac_update(ctx: Context, xs, seg_off, assign, C_old, C_new, count=None):
+    N, d = xs.shape
+    T = seg_off.shape[0] - 1
+    _check_dtype(count, torch.int64, "count")
+    _check(load().tac_update(ctx.handle, _dptr(xs), _dptr(seg_off), T, N, d, _dptr(assign), _dptr(C_old),
+                             C_old.shape[0], _dptr(C_new), _dptr(count)))
+
+
+def tac_residuals(ctx: Context, x, assign, C_cent, R, rows=None, normalize: bool = True, rnorm=None):
+    n = R.shape[0]
+    _check_dtype(rows, torch.int64, "rows")
+    _check(load().tac_residuals(ctx.handle, _dptr(x), _dptr(assign), _dptr(C_cent), C_cent.shape[0], _dptr(rows),
+                                n, x.shape[1], int(normalize), _dptr(R), _dptr(rnorm)))
+
+
+def pq_train(ctx: Context, R, init, codebooks, iters: int = 10):
+    n, d = R.shape
+    M, ksub, _ = init.shape
+    _check(load().pq_train(ctx.handle, _dptr(R), n, d, M, ksub, iters, _dptr(init), _dptr(codebooks)))
+
+
+def pq_encode(ctx: Context, x, assign, C_cent, codebooks, codes, normalize: bool = True, rnorm=None):
+    n, d = x.shape
+    M, ksub, _ = codebooks.shape
+    _check_dtype(codes, torch.uint8, "codes")
+    _check(load().pq_encode(ctx.handle, _dptr(x), _dptr(assign), _dptr(C_cent), C_cent.shape[0], n, d,
+                            _dptr(codebooks), M, ksub, int(normalize), _dptr(codes), _dptr(rnorm)))

@@ -1,0 +1,788 @@
+// Assignment step of per-token Lloyd (Sect. 2.1): every vector of token j goes
+// to the nearest of token j's centroids.
+//
+// One persistent launch serves every token.  The work list holds one item per
+// (token, 256-row tile); items of tokens with many centroids come first, so the
+// longest items start early.  Each item takes one of two routes:
+//
+// * direct (kappa_j <= 4): every centroid is a candidate, so each row computes
+//   the canonical FP32 distance to all of them;
+// * screen (kappa_j > 4): the distance contraction ||c||^2 - 2 x.c runs on the
+//   matrix cores (FP32 v_mfma_f32_16x16x4f32, or BF16 v_mfma_f32_16x16x32_bf16
+//   on hi/lo splits of both operands), centroid tiles are staged through LDS,
+//   and every lane keeps a running top-4 of packed (screen value, index) keys
+//   with one min and three med3 per distance.  The four nominees of each row
+//   are rescored with the canonical FP32 distance; a rigorous bound on the
+//   screen error certifies that no other centroid can win, and rows whose
+//   certificate fails are queued for an exhaustive rescoring kernel.
+//
+// The canonical distance is acc = 0; for i: t = x_i - c_i; acc = acc + t*t,
+// each operation rounded to float32 without fusion, so the result is the same
+// for the FP32 and BF16 screens and independent of tile shapes.
+#include <cfloat>
+
+#include "tac_internal.h"
+
+namespace tac {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kNB = 4;                          // 16-row column blocks per wave
+constexpr int kTileRows = kWaves * kNB * 16;    // rows per work item
+constexpr int kStage = 64;                      // centroids per LDS stage
+constexpr int kRowWords = 132;                  // LDS row stride (512 B + 16 B pad)
+constexpr int kEpochBlocks = 64;                // 16-centroid blocks per packed-index epoch
+constexpr int kDirectMax = 4;                   // tokens with at most this many centroids skip the screen
+constexpr int kHeavy = 1024;                    // tokens with this many centroids are scheduled first
+constexpr float kInvalid = 3.0e38f;             // screen value of padding centroids
+constexpr unsigned kCntRows = 0, kCntScreened = 1, kCntFallback = 2, kCntUnassigned = 3;
+
+__device__ __forceinline__ float dist32_rows(const float* __restrict__ x, const float* __restrict__ c, float* xx) {
+    const float4* xv = reinterpret_cast<const float4*>(x);
+    const float4* cv = reinterpret_cast<const float4*>(c);
+    float acc = 0.f, sx = 0.f;
+#pragma unroll 4
+    for (int i = 0; i < kDim / 4; ++i) {
+        const float4 a = xv[i];
+        const float4 b = cv[i];
+        float t;
+        t = __fsub_rn(a.x, b.x); acc = __fadd_rn(acc, __fmul_rn(t, t)); sx = __fadd_rn(sx, __fmul_rn(a.x, a.x));
+        t = __fsub_rn(a.y, b.y); acc = __fadd_rn(acc, __fmul_rn(t, t)); sx = __fadd_rn(sx, __fmul_rn(a.y, a.y));
+        t = __fsub_rn(a.z, b.z); acc = __fadd_rn(acc, __fmul_rn(t, t)); sx = __fadd_rn(sx, __fmul_rn(a.z, a.z));
+        t = __fsub_rn(a.w, b.w); acc = __fadd_rn(acc, __fmul_rn(t, t)); sx = __fadd_rn(sx, __fmul_rn(a.w, a.w));
+    }
+    if (xx) *xx = sx;
+    return acc;
+}
+
+__device__ __forceinline__ unsigned short bf16_rne(float v) {
+    const unsigned u = __float_as_uint(v);
+    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// ---- per-call reset of the work counter, statistics and max centroid norm ----
+__global__ void reset_call(unsigned long long* __restrict__ work, unsigned long long* __restrict__ counters,
+                           unsigned* __restrict__ cstat) {
+    work[0] = 0;
+    for (int i = 0; i < 4; ++i) counters[i] = 0;
+    cstat[0] = 0;
+}
+
+// ---- plan: item counts per (class, token) ----
+__global__ void plan_count(const int64_t* __restrict__ seg_off, const int64_t* __restrict__ cent_off, int32_t T,
+                           int64_t* __restrict__ cnt) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= T) return;
+    const int64_t n = seg_off[j + 1] - seg_off[j];
+    const int64_t k = cent_off[j + 1] - cent_off[j];
+    const int64_t tiles = (n + kTileRows - 1) / kTileRows;
+    const int cls = k <= kDirectMax ? 2 : (k >= kHeavy ? 0 : 1);
+    for (int c = 0; c < 3; ++c) cnt[(int64_t)c * T + j] = c == cls ? tiles : 0;
+}
+
+// ---- centroid preparation: squared norms, max norm, BF16 hi/lo splits ----
+__global__ void prep_centroids(const float* __restrict__ C, int64_t K, float* __restrict__ cn,
+                               unsigned* __restrict__ cstat, unsigned short* __restrict__ chl) {
+    const int sub = threadIdx.x & 31;
+    for (int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5; k < K;
+         k += ((int64_t)gridDim.x * blockDim.x) >> 5) {
+        const float4 v = reinterpret_cast<const float4*>(C + k * kDim)[sub];
+        float s = v.x * v.x;
+        s = s + v.y * v.y;
+        s = s + v.z * v.z;
+        s = s + v.w * v.w;
+        for (int m = 16; m > 0; m >>= 1) s += __shfl_xor(s, m, 32);
+        if (sub == 0) {
+            cn[k] = s;
+            atomicMax(cstat, __float_as_uint(s));
+        }
+        if (chl) {
+            const float e[4] = {v.x, v.y, v.z, v.w};
+            unsigned short hi[4], lo[4];
+            for (int i = 0; i < 4; ++i) {
+                hi[i] = bf16_rne(e[i]);
+                lo[i] = bf16_rne(e[i] - bf16_to_f(hi[i]));
+            }
+            unsigned short* row = chl + k * (2 * kDim);
+            uint2 h, l;
+            h.x = hi[0] | ((unsigned)hi[1] << 16);
+            h.y = hi[2] | ((unsigned)hi[3] << 16);
+            l.x = lo[0] | ((unsigned)lo[1] << 16);
+            l.y = lo[2] | ((unsigned)lo[3] << 16);
+            reinterpret_cast<uint2*>(row)[sub] = h;
+            reinterpret_cast<uint2*>(row + kDim)[sub] = l;
+        }
+    }
+}
+
+struct Params {
+    const float* x;
+    const int32_t* rowmap;       // sorted position -> physical row (NULL: identity)
+    const int64_t* seg_off;
+    const int64_t* cent_off;
+    int32_t T;
+    const float* C;
+    const void* cstage;          // rows staged into LDS: C (FP32) or hi/lo BF16 pairs
+    const float* cn;
+    const unsigned* cstat;       // [0] = bits of max ||c||^2
+    const int64_t* item_off;     // [3T + 1]
+    unsigned long long* work;
+    int32_t* assign;
+    float* dist;
+    int32_t* fb;                 // fallback queue: (sorted position, token) pairs
+    unsigned long long* counters;
+};
+
+__device__ __forceinline__ void list_insert(float (&l)[4], float p) {
+    l[3] = __builtin_amdgcn_fmed3f(l[2], l[3], p);
+    l[2] = __builtin_amdgcn_fmed3f(l[1], l[2], p);
+    l[1] = __builtin_amdgcn_fmed3f(l[0], l[1], p);
+    l[0] = fminf(l[0], p);
+}
+
+// Insert (t, i) into the ascending list (G, I); `lex` breaks value ties by index.
+__device__ __forceinline__ void glist_insert(float (&G)[4], int (&I)[4], float t, int i, bool lex) {
+    bool c[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) c[e] = t < G[e] || (lex && t == G[e] && (unsigned)i < (unsigned)I[e]);
+    G[3] = c[2] ? G[2] : (c[3] ? t : G[3]);
+    I[3] = c[2] ? I[2] : (c[3] ? i : I[3]);
+    G[2] = c[1] ? G[1] : (c[2] ? t : G[2]);
+    I[2] = c[1] ? I[1] : (c[2] ? i : I[2]);
+    G[1] = c[0] ? G[0] : (c[1] ? t : G[1]);
+    I[1] = c[0] ? I[0] : (c[1] ? i : I[1]);
+    G[0] = c[0] ? t : G[0];
+    I[0] = c[0] ? i : I[0];
+}
+
+template <int PREC>
+struct Frag;
+
+template <>
+struct Frag<TAC_FP32> {
+    float x[kNB][32];
+    float c[32];
+};
+
+template <>
+struct Frag<TAC_BF16> {
+    bf8 xh[kNB][4];
+    bf8 xl[kNB][4];
+    bf8 ch[4];
+    bf8 cl[4];
+};
+
+__device__ __forceinline__ bf8 pack_bf8(const unsigned short* h) {
+    bf8 r;
+    unsigned short* p = reinterpret_cast<unsigned short*>(&r);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) p[e] = h[e];
+    return r;
+}
+
+template <int PREC>
+__device__ __forceinline__ void direct_item(const Params& P, int32_t j, int64_t tile) {
+    const int64_t s0 = P.seg_off[j], s1 = P.seg_off[j + 1];
+    const int64_t k0 = P.cent_off[j];
+    const int kc = (int)(P.cent_off[j + 1] - k0);
+    const int64_t row0 = s0 + tile * kTileRows;
+    const int64_t v = row0 + threadIdx.x;
+    const bool valid = v < s1;
+    if (valid) {
+        const int64_t r = P.rowmap ? (int64_t)P.rowmap[v] : v;
+        if (kc == 0) {
+            P.assign[r] = -1;
+            P.dist[r] = 0.f;
+        } else {
+            const float4* xv = reinterpret_cast<const float4*>(P.x + r * kDim);
+            float acc[kDirectMax] = {0.f, 0.f, 0.f, 0.f};
+            for (int i = 0; i < kDim / 4; ++i) {
+                const float4 a = xv[i];
+#pragma unroll
+                for (int k = 0; k < kDirectMax; ++k) {
+                    if (k < kc) {
+                        const float4 b = reinterpret_cast<const float4*>(P.C + (k0 + k) * kDim)[i];
+                        float t;
+                        t = __fsub_rn(a.x, b.x); acc[k] = __fadd_rn(acc[k], __fmul_rn(t, t));
+                        t = __fsub_rn(a.y, b.y); acc[k] = __fadd_rn(acc[k], __fmul_rn(t, t));
+                        t = __fsub_rn(a.z, b.z); acc[k] = __fadd_rn(acc[k], __fmul_rn(t, t));
+                        t = __fsub_rn(a.w, b.w); acc[k] = __fadd_rn(acc[k], __fmul_rn(t, t));
+                    }
+                }
+            }
+            int best = 0;
+#pragma unroll
+            for (int k = 1; k < kDirectMax; ++k)
+                if (k < kc && acc[k] < acc[best]) best = k;
+            P.assign[r] = (int32_t)(k0 + best);
+            P.dist[r] = acc[best];
+        }
+    }
+    const unsigned long long nval = __popcll(__ballot(valid));
+    if ((threadIdx.x & 63) == 0 && nval) {
+        atomicAdd(&P.counters[kCntRows], nval);
+        if (kc == 0) atomicAdd(&P.counters[kCntUnassigned], nval);
+    }
+}
+
+template <int PREC>
+__device__ __forceinline__ void screen_item(const Params& P, int32_t j, int64_t tile, unsigned* lds) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int col = lane & 15;
+    const int64_t s0 = P.seg_off[j], s1 = P.seg_off[j + 1];
+    const int64_t k0 = P.cent_off[j];
+    const int kc = (int)(P.cent_off[j + 1] - k0);
+    const int64_t row0 = s0 + tile * kTileRows + wave * (kNB * 16);
+    const float cnmax = __uint_as_float(P.cstat[0]) * (1.0f + 1e-5f);
+    const float cmax = sqrtf(cnmax) * (1.0f + 1e-6f);
+
+    // LDS: two stages of kStage rows (kRowWords words each) and their norms
+    unsigned* stage_rows = lds;                                  // [2][kStage][kRowWords]
+    float* stage_cn = reinterpret_cast<float*>(lds + 2 * kStage * kRowWords);  // [2][kStage]
+
+    Frag<PREC> F;
+    float beta[kNB];
+    int64_t rowv[kNB];
+#pragma unroll
+    for (int nb = 0; nb < kNB; ++nb) {
+        const int64_t v = row0 + nb * 16 + col;
+        rowv[nb] = v;
+        const bool valid = v < s1;
+        const int64_t r = valid ? (P.rowmap ? (int64_t)P.rowmap[v] : v) : 0;
+        const float4* xv = reinterpret_cast<const float4*>(P.x + r * kDim + 32 * g);
+        float xs[32];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float4 a = valid ? xv[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+            xs[4 * q + 0] = a.x;
+            xs[4 * q + 1] = a.y;
+            xs[4 * q + 2] = a.z;
+            xs[4 * q + 3] = a.w;
+        }
+        float xx = 0.f;
+#pragma unroll
+        for (int i = 0; i < 32; ++i) xx += xs[i] * xs[i];
+        xx += __shfl_xor(xx, 16);
+        xx += __shfl_xor(xx, 32);
+        beta[nb] = xx * (1.0f + 0.00390625f) + 0.00390625f * cnmax + 1e-30f;
+        if constexpr (PREC == TAC_FP32) {
+#pragma unroll
+            for (int i = 0; i < 32; ++i) F.x[nb][i] = -2.0f * xs[i];
+        } else {
+            unsigned short h[32], l[32];
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                const float m2 = -2.0f * xs[i];
+                h[i] = bf16_rne(m2);
+                l[i] = bf16_rne(m2 - bf16_to_f(h[i]));
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                F.xh[nb][s] = pack_bf8(h + 8 * s);
+                F.xl[nb][s] = pack_bf8(l + 8 * s);
+            }
+        }
+    }
+
+    float el[kNB][4];
+    float G[kNB][4];
+    int I[kNB][4];
+#pragma unroll
+    for (int nb = 0; nb < kNB; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            el[nb][e] = FLT_MAX;
+            G[nb][e] = kInvalid;
+            I[nb][e] = -1;
+        }
+
+    const char* csrc = static_cast<const char*>(P.cstage);
+    const int nst = (kc + kStage - 1) / kStage;
+    // stage loader: 64 rows x 512 B = 2048 float4; thread t moves 8 of them
+    auto load_stage = [&](int st, u4 (&reg)[8], float& rcn) {
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+            const int chunk = it * kThreads + threadIdx.x;
+            const int row = chunk >> 5;
+            const int c16 = chunk & 31;
+            const int kk = st * kStage + row;
+            reg[it] = kk < kc ? reinterpret_cast<const u4*>(csrc + (k0 + kk) * 512)[c16] : u4{0u, 0u, 0u, 0u};
+        }
+        const int kk = st * kStage + (threadIdx.x & 63);
+        rcn = kk < kc ? P.cn[k0 + kk] : kInvalid;
+    };
+    auto store_stage = [&](int buf, const u4 (&reg)[8], float rcn) {
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+            const int chunk = it * kThreads + threadIdx.x;
+            const int row = chunk >> 5;
+            const int c16 = chunk & 31;
+            *reinterpret_cast<u4*>(stage_rows + (buf * kStage + row) * kRowWords + c16 * 4) = reg[it];
+        }
+        if (threadIdx.x < kStage) stage_cn[buf * kStage + threadIdx.x] = rcn;
+    };
+
+    u4 pf[8];
+    float pcn;
+    load_stage(0, pf, pcn);
+    store_stage(0, pf, pcn);
+    __syncthreads();
+
+    int epoch_first = 0;  // first 16-block of the current epoch (segment-relative)
+    for (int st = 0; st < nst; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nst) load_stage(st + 1, pf, pcn);
+#pragma unroll 1
+        for (int b = 0; b < kStage / 16; ++b) {
+            const int blk16 = st * (kStage / 16) + b;  // segment-relative 16-block
+            if (blk16 * 16 >= kc) break;
+            const unsigned* crow = stage_rows + (buf * kStage + b * 16 + col) * kRowWords;
+            const f4 cinit = *reinterpret_cast<const f4*>(stage_cn + buf * kStage + b * 16 + 4 * g);
+            if constexpr (PREC == TAC_FP32) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const f4 v = *reinterpret_cast<const f4*>(crow + 32 * g + 4 * q);
+                    F.c[4 * q + 0] = v.x;
+                    F.c[4 * q + 1] = v.y;
+                    F.c[4 * q + 2] = v.z;
+                    F.c[4 * q + 3] = v.w;
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    F.ch[s] = *reinterpret_cast<const bf8*>(crow + 16 * g + 4 * s);
+                    F.cl[s] = *reinterpret_cast<const bf8*>(crow + 64 + 16 * g + 4 * s);
+                }
+            }
+            f4 acc[kNB];
+#pragma unroll
+            for (int nb = 0; nb < kNB; ++nb) acc[nb] = cinit + beta[nb];
+            if constexpr (PREC == TAC_FP32) {
+#pragma unroll
+                for (int s = 0; s < 32; ++s)
+#pragma unroll
+                    for (int nb = 0; nb < kNB; ++nb)
+                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(F.c[s], F.x[nb][s], acc[nb], 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int nb = 0; nb < kNB; ++nb)
+                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.ch[s], F.xh[nb][s], acc[nb], 0, 0, 0);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int nb = 0; nb < kNB; ++nb)
+                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.cl[s], F.xh[nb][s], acc[nb], 0, 0, 0);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int nb = 0; nb < kNB; ++nb)
+                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.ch[s], F.xl[nb][s], acc[nb], 0, 0, 0);
+            }
+            const unsigned lb = (unsigned)(blk16 - epoch_first) * 4u;
+#pragma unroll
+            for (int nb = 0; nb < kNB; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float p = __uint_as_float((__float_as_uint(acc[nb][r]) & ~0xFFu) | (lb + r));
+                    list_insert(el[nb], p);
+                }
+            const bool last = (blk16 + 1) * 16 >= kc;
+            if (blk16 - epoch_first == kEpochBlocks - 1 || last) {
+                const int64_t ebase = k0 + (int64_t)epoch_first * 16 + 4 * g;
+#pragma unroll
+                for (int nb = 0; nb < kNB; ++nb) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const unsigned bits = __float_as_uint(el[nb][e]);
+                        const float t = __uint_as_float(bits & ~0xFFu);
+                        const unsigned loc = bits & 0xFFu;
+                        const int gi = (int)(ebase + (int64_t)(loc >> 2) * 16 + (loc & 3u));
+                        if (t < 1.0e38f) glist_insert(G[nb], I[nb], t, gi, false);
+                        el[nb][e] = FLT_MAX;
+                    }
+                }
+                epoch_first = blk16 + 1;
+            }
+        }
+        if (st + 1 < nst) store_stage(buf ^ 1, pf, pcn);
+        __syncthreads();
+    }
+
+    // merge the four lanes that share a row (lane groups g = 0..3)
+#pragma unroll
+    for (int m = 16; m <= 32; m <<= 1) {
+#pragma unroll
+        for (int nb = 0; nb < kNB; ++nb) {
+            float pt[4];
+            int pi[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                pt[e] = __shfl_xor(G[nb][e], m);
+                pi[e] = __shfl_xor(I[nb][e], m);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) glist_insert(G[nb], I[nb], pt[e], pi[e], true);
+        }
+    }
+
+    // rescore nominee g of each row with the canonical distance, then certify
+    const double u = 5.9604644775390625e-8;  // 2^-24
+    const double g130 = 130.0 * u / (1.0 - 130.0 * u);
+    const double g386 = 386.0 * u / (1.0 - 386.0 * u);
+    int nscreen = 0;
+#pragma unroll 1
+    for (int nb = 0; nb < kNB; ++nb) {
+        const int64_t v = rowv[nb];
+        const bool valid = v < s1;
+        const int64_t r = valid ? (P.rowmap ? (int64_t)P.rowmap[v] : v) : 0;
+        const int nom = g == 0 ? I[nb][0] : g == 1 ? I[nb][1] : g == 2 ? I[nb][2] : I[nb][3];
+        float d32 = INFINITY, xxc = 0.f;
+        if (valid && nom >= 0) d32 = dist32_rows(P.x + r * kDim, P.C + (int64_t)nom * kDim, &xxc);
+        if (valid && nom < 0) dist32_rows(P.x + r * kDim, P.x + r * kDim, &xxc);
+        float bd = d32;
+        int bi = nom < 0 ? INT32_MAX : nom;
+#pragma unroll
+        for (int m = 16; m <= 32; m <<= 1) {
+            const float od = __shfl_xor(bd, m);
+            const int oi = __shfl_xor(bi, m);
+            if (od < bd || (od == bd && oi < bi)) {
+                bd = od;
+                bi = oi;
+            }
+        }
+        const float xxs = __shfl(xxc, col);  // lane group 0 holds the canonical ||x||^2
+        if (valid && g == 0) {
+            ++nscreen;
+            const double tau = (double)G[nb][3];
+            bool ok = tau >= 1.0e38;
+            if (!ok) {
+                const double xx_hi = (double)xxs * (1.0 + g130);
+                const double xx_lo = (double)xxs * (1.0 - g130);
+                const double xn = sqrt(xx_hi);
+                const double bt = (double)beta[nb];
+                const double cm = (double)cmax, cn2 = (double)cnmax;
+                double E;
+                if constexpr (PREC == TAC_FP32)
+                    E = 1.1 * (g130 * (2.0 * (cn2 + bt) + 2.0 * xn * cm));
+                else
+                    E = 1.1 * (g386 * (2.0 * (cn2 + bt) + 2.2 * xn * cm) + 6.2 * 1.52587890625e-5 * xn * cm);
+                E += 1e-30;
+                const double L = (tau - E - bt + xx_lo) * (1.0 - g130);
+                ok = L > (double)bd;
+            }
+            if (ok) {
+                P.assign[r] = bi;
+                P.dist[r] = bd;
+            } else {
+                const unsigned long long q = atomicAdd(&P.counters[kCntFallback], 1ull);
+                P.fb[2 * q] = (int32_t)v;
+                P.fb[2 * q + 1] = j;
+            }
+        }
+    }
+    // per-wave counts (lanes of group 0 counted the valid rows)
+    for (int m = 32; m > 0; m >>= 1) nscreen += __shfl_xor(nscreen, m);
+    if (lane == 0 && nscreen) {
+        atomicAdd(&P.counters[kCntRows], (unsigned long long)nscreen);
+        atomicAdd(&P.counters[kCntScreened], (unsigned long long)nscreen);
+    }
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(kThreads) assign_main(Params P) {
+    extern __shared__ unsigned lds[];
+    __shared__ unsigned long long s_item;
+    const int64_t nclass = 3 * (int64_t)P.T;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(P.work, 1ull);
+        __syncthreads();
+        const int64_t item = (int64_t)s_item;
+        __syncthreads();
+        if (item >= P.item_off[nclass]) break;
+        int64_t lo = 0, hi = nclass;  // largest idx with item_off[idx] <= item
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (P.item_off[mid] <= item) lo = mid; else hi = mid;
+        }
+        const int cls = (int)(lo / P.T);
+        const int32_t j = (int32_t)(lo % P.T);
+        const int64_t tile = item - P.item_off[lo];
+        if (cls == 2)
+            direct_item<PREC>(P, j, tile);
+        else
+            screen_item<PREC>(P, j, tile, lds);
+    }
+}
+
+// Exhaustive canonical rescoring of the rows whose certificate failed: one
+// wavefront per row, lanes stride over the token's centroids.
+__global__ void __launch_bounds__(256) assign_fallback(const float* __restrict__ x, const int32_t* __restrict__ rowmap,
+                                                       const int64_t* __restrict__ cent_off, const float* __restrict__ C,
+                                                       const int32_t* __restrict__ fb,
+                                                       const unsigned long long* __restrict__ counters,
+                                                       int32_t* __restrict__ assign, float* __restrict__ dist) {
+    __shared__ float xrow[4][kDim];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t nfb = (int64_t)counters[kCntFallback];
+    for (int64_t q = (int64_t)blockIdx.x * 4 + wave; q < nfb; q += (int64_t)gridDim.x * 4) {
+        const int64_t v = fb[2 * q];
+        const int32_t j = fb[2 * q + 1];
+        const int64_t r = rowmap ? (int64_t)rowmap[v] : v;
+        xrow[wave][lane] = x[r * kDim + lane];
+        xrow[wave][lane + 64] = x[r * kDim + lane + 64];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        const int64_t k0 = cent_off[j];
+        const int kc = (int)(cent_off[j + 1] - k0);
+        float bd = INFINITY;
+        int bi = INT32_MAX;
+        for (int k = lane; k < kc; k += 64) {
+            const float d = dist32_rows(xrow[wave], C + (k0 + k) * kDim, nullptr);
+            if (d < bd) {
+                bd = d;
+                bi = (int)(k0 + k);
+            }
+        }
+        for (int m = 32; m > 0; m >>= 1) {
+            const float od = __shfl_xor(bd, m);
+            const int oi = __shfl_xor(bi, m);
+            if (od < bd || (od == bd && oi < bi)) {
+                bd = od;
+                bi = oi;
+            }
+        }
+        if (lane == 0) {
+            assign[r] = bi;
+            dist[r] = bd;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+constexpr int kRedThreads = 256;
+constexpr int kRedItems = 16;
+
+__global__ void __launch_bounds__(kRedThreads) inertia_partial(const float* __restrict__ dist, int64_t n,
+                                                               double* __restrict__ part) {
+    __shared__ double lds[kRedThreads];
+    const int64_t base = (int64_t)blockIdx.x * kRedThreads * kRedItems;
+    double s = 0.0;
+    for (int i = 0; i < kRedItems; ++i) {
+        const int64_t k = base + (int64_t)i * kRedThreads + threadIdx.x;
+        if (k < n) s += (double)dist[k];
+    }
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) lds[threadIdx.x] += lds[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = lds[0];
+}
+
+__global__ void __launch_bounds__(kRedThreads) inertia_final(const double* __restrict__ part, int64_t nb,
+                                                             double* __restrict__ out) {
+    __shared__ double lds[kRedThreads];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < nb; i += kRedThreads) s += part[i];
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) lds[threadIdx.x] += lds[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = lds[0];
+}
+
+// serving path: token ids -> sort keys; invalid ids sort last (key T) and are marked unassigned
+__global__ void serve_keys(const int32_t* __restrict__ tok, int64_t n, int32_t T, uint32_t* __restrict__ keys,
+                           int32_t* __restrict__ assign, float* __restrict__ dist,
+                           unsigned long long* __restrict__ counters) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t t = tok[i];
+        if (t < 0 || t >= T) {
+            keys[i] = (uint32_t)T;
+            assign[i] = -1;
+            dist[i] = 0.f;
+            atomicAdd(&counters[kCntUnassigned], 1ull);
+        } else {
+            keys[i] = (uint32_t)t;
+        }
+    }
+}
+
+__global__ void serve_offsets(const uint32_t* __restrict__ keys, int64_t n, int32_t T, int64_t* __restrict__ seg_off) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t prev = i == 0 ? -1 : (int64_t)keys[i - 1];
+        const int64_t cur = i == n ? (int64_t)T + 1 : (int64_t)keys[i];
+        for (int64_t t = prev + 1; t <= cur; ++t) seg_off[t] = i;
+    }
+}
+
+unsigned grid_for(int64_t work, int per_block) {
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (unsigned)g;
+}
+
+constexpr size_t kLdsBytes = (size_t)2 * kStage * kRowWords * 4 + (size_t)2 * kStage * 4;
+
+}  // namespace
+
+}  // namespace tac
+
+using namespace tac;
+
+extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* seg_off_d, const int32_t* tok_d,
+                                 int64_t N, int32_t d, int32_t T, const float* C_d, const int64_t* cent_off_d,
+                                 int64_t K, int32_t precision, int32_t* assign_d, float* dist_d, double* inertia_d) {
+    if (!ctx) return set_error(TAC_E_INVAL, "tac_assign: ctx is NULL");
+    if (d != kDim) return set_error(TAC_E_INVAL, "tac_assign: d must be 128");
+    if (N < 0 || N > INT32_MAX) return set_error(TAC_E_INVAL, "tac_assign: N out of range");
+    if (T < 1 || T > (1 << 24)) return set_error(TAC_E_INVAL, "tac_assign: T must be in [1, 2^24]");
+    if (K < 0 || K > INT32_MAX) return set_error(TAC_E_INVAL, "tac_assign: K out of range");
+    if ((seg_off_d == nullptr) == (tok_d == nullptr))
+        return set_error(TAC_E_INVAL, "tac_assign: pass exactly one of seg_off_d and tok_d");
+    if (precision != TAC_FP32 && precision != TAC_BF16) return set_error(TAC_E_INVAL, "tac_assign: bad precision");
+    if (!cent_off_d || (N > 0 && (!x_d || !assign_d)) || (K > 0 && !C_d))
+        return set_error(TAC_E_INVAL, "tac_assign: NULL pointer");
+    TAC_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+
+    const bool serve = tok_d != nullptr;
+    const int64_t ncls = 3 * (int64_t)T;
+    Carve cv;
+    const size_t o_cnt = cv.take<int64_t>(ncls + 1);
+    const size_t o_scan = cv.take<char>(scan_scratch_bytes(ncls));
+    const size_t o_work = cv.take<unsigned long long>(1);
+    const size_t o_cstat = cv.take<unsigned>(4);
+    const size_t o_cn = cv.take<float>(K + 1);
+    const size_t o_chl = precision == TAC_BF16 ? cv.take<unsigned short>((K + 1) * 2 * kDim) : 0;
+    const size_t o_fb = cv.take<int32_t>(2 * (N + 1));
+    const size_t o_dist = dist_d ? 0 : cv.take<float>(N + 1);
+    const int64_t nred = (N + kRedThreads * kRedItems - 1) / (kRedThreads * kRedItems);
+    const size_t o_red = cv.take<double>(nred + 1);
+    size_t o_k0 = 0, o_v0 = 0, o_k1 = 0, o_v1 = 0, o_sort = 0, o_seg = 0;
+    if (serve) {
+        o_k0 = cv.take<uint32_t>(N + 1);
+        o_v0 = cv.take<int32_t>(N + 1);
+        o_k1 = cv.take<uint32_t>(N + 1);
+        o_v1 = cv.take<int32_t>(N + 1);
+        o_sort = cv.take<char>(radix_sort_scratch_bytes(N));
+        o_seg = cv.take<int64_t>((int64_t)T + 2);
+    }
+    tac_status st = ws_reserve(ctx, cv.off);
+    if (st != TAC_OK) return st;
+    float* dist = dist_d ? dist_d : ws_at<float>(ctx, o_dist);
+    unsigned* cstat = ws_at<unsigned>(ctx, o_cstat);
+    float* cn = ws_at<float>(ctx, o_cn);
+    unsigned short* chl = precision == TAC_BF16 ? ws_at<unsigned short>(ctx, o_chl) : nullptr;
+    int64_t* cnt = ws_at<int64_t>(ctx, o_cnt);
+    unsigned long long* work = ws_at<unsigned long long>(ctx, o_work);
+
+    const int64_t* seg = seg_off_d;
+    const int32_t* rowmap = nullptr;
+    reset_call<<<1, 1, 0, s>>>(work, ctx->counters, cstat);
+    TAC_LAUNCH_CHECK("reset_call");
+    if (serve) {
+        int64_t* sseg = ws_at<int64_t>(ctx, o_seg);
+        uint32_t* k0 = ws_at<uint32_t>(ctx, o_k0);
+        int32_t* v0 = ws_at<int32_t>(ctx, o_v0);
+        uint32_t* k1 = ws_at<uint32_t>(ctx, o_k1);
+        int32_t* v1 = ws_at<int32_t>(ctx, o_v1);
+        if (N > 0) {
+            serve_keys<<<grid_for(N, 256), 256, 0, s>>>(tok_d, N, T, k0, assign_d, dist, ctx->counters);
+            TAC_LAUNCH_CHECK("serve_keys");
+        }
+        int bits = 1;
+        while (bits < 31 && (int64_t(1) << bits) < (int64_t)T + 1) ++bits;
+        int in1 = 0;
+        st = radix_sort(s, N, bits, k0, v0, k1, v1, nullptr, ws_at<void>(ctx, o_sort), &in1);
+        if (st != TAC_OK) return st;
+        serve_offsets<<<grid_for(N + 1, 256), 256, 0, s>>>(in1 ? k1 : k0, N, T, sseg);
+        TAC_LAUNCH_CHECK("serve_offsets");
+        seg = sseg;
+        rowmap = in1 ? v1 : v0;
+    }
+    plan_count<<<grid_for(T, 256), 256, 0, s>>>(seg, cent_off_d, T, cnt);
+    TAC_LAUNCH_CHECK("plan_count");
+    st = exclusive_scan_i64(s, cnt, cnt, ncls, ws_at<void>(ctx, o_scan));
+    if (st != TAC_OK) return st;
+    if (K > 0) {
+        prep_centroids<<<grid_for(K * 32, 256), 256, 0, s>>>(C_d, K, cn, cstat, chl);
+        TAC_LAUNCH_CHECK("prep_centroids");
+    }
+    Params P;
+    P.x = x_d;
+    P.rowmap = rowmap;
+    P.seg_off = seg;
+    P.cent_off = cent_off_d;
+    P.T = T;
+    P.C = C_d;
+    P.cstage = precision == TAC_BF16 ? (const void*)chl : (const void*)C_d;
+    P.cn = cn;
+    P.cstat = cstat;
+    P.item_off = cnt;
+    P.work = work;
+    P.assign = assign_d;
+    P.dist = dist;
+    P.fb = ws_at<int32_t>(ctx, o_fb);
+    P.counters = ctx->counters;
+    const unsigned grid = (unsigned)ctx->props_cu * 2;
+    static bool lds_attr_set = false;
+    if (!lds_attr_set) {
+        TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_FP32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kLdsBytes));
+        TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_BF16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kLdsBytes));
+        lds_attr_set = true;
+    }
+    time_start(ctx, TAC_SLOT_ASSIGN);
+    if (precision == TAC_FP32) {
+        assign_main<TAC_FP32><<<grid, kThreads, kLdsBytes, s>>>(P);
+        TAC_LAUNCH_CHECK("assign_main<fp32>");
+    } else {
+        assign_main<TAC_BF16><<<grid, kThreads, kLdsBytes, s>>>(P);
+        TAC_LAUNCH_CHECK("assign_main<bf16>");
+    }
+    time_stop(ctx, TAC_SLOT_ASSIGN);
+    assign_fallback<<<(unsigned)ctx->props_cu * 4, 256, 0, s>>>(x_d, rowmap, cent_off_d, C_d, P.fb, ctx->counters,
+                                                                 assign_d, dist);
+    TAC_LAUNCH_CHECK("assign_fallback");
+    if (inertia_d) {
+        double* part = ws_at<double>(ctx, o_red);
+        if (nred > 0) {
+            inertia_partial<<<(unsigned)nred, kRedThreads, 0, s>>>(dist, N, part);
+            TAC_LAUNCH_CHECK("inertia_partial");
+        }
+        inertia_final<<<1, kRedThreads, 0, s>>>(part, nred, inertia_d);
+        TAC_LAUNCH_CHECK("inertia_final");
+    }
+    return TAC_OK;
+}
+
+extern "C" tac_status tac_assign_stats(tac_ctx ctx, tac_assign_counters* out) {
+    if (!ctx || !out) return set_error(TAC_E_INVAL, "tac_assign_stats: NULL argument");
+    TAC_HIP(hipSetDevice(ctx->device));
+    unsigned long long c[4];
+    TAC_HIP(hipMemcpyAsync(c, ctx->counters, sizeof(c), hipMemcpyDeviceToHost, ctx->stream));
+    TAC_HIP(hipStreamSynchronize(ctx->stream));
+    out->rows = (int64_t)c[0];
+    out->screened = (int64_t)c[1];
+    out->fallback = (int64_t)c[2];
+    out->unassigned = (int64_t)c[3];
+    return TAC_OK;
+}

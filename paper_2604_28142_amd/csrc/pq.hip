@@ -1,0 +1,315 @@
+// Residual compression with product quantisation (Sect. 2.1, "Residuals
+// Compression"; M = 32 subspaces with 8-bit codes in Sect. 3.1).
+//
+// r = x - c_{a(x)}, rho = ||r||, u = r / rho (u = 0 for rho = 0), then for each
+// subspace m (coordinates 4m..4m+3) the code is the argmin over the codebook
+// of the canonical FP32 distance, lowest code on ties.  The codebooks
+// (M x 256 x 4 floats = 128 KiB) stay resident in LDS while a block encodes
+// its rows.  Training runs Lloyd per subspace: encode, stably sort the rows of
+// each subspace by code, and average every code's members in float64 in that
+// fixed order (codes with no member keep their value).
+#include <algorithm>
+
+#include "tac_internal.h"
+
+namespace tac {
+
+namespace {
+
+constexpr int kDsub = 4;
+constexpr int kMaxCodebookFloats = 32 * 256 * kDsub;
+
+// Canonical residual of one row: r_i = x_i - c_i, rho = sqrt(sum r_i * r_i), each op rounded.
+__device__ __forceinline__ float residual_norm(const float* __restrict__ x, const float* __restrict__ c) {
+    const float4* xv = reinterpret_cast<const float4*>(x);
+    const float4* cv = reinterpret_cast<const float4*>(c);
+    float acc = 0.f;
+    for (int i = 0; i < kDim / 4; ++i) {
+        const float4 a = xv[i], b = cv[i];
+        float t;
+        t = __fsub_rn(a.x, b.x); acc = __fadd_rn(acc, __fmul_rn(t, t));
+        t = __fsub_rn(a.y, b.y); acc = __fadd_rn(acc, __fmul_rn(t, t));
+        t = __fsub_rn(a.z, b.z); acc = __fadd_rn(acc, __fmul_rn(t, t));
+        t = __fsub_rn(a.w, b.w); acc = __fadd_rn(acc, __fmul_rn(t, t));
+    }
+    return sqrtf(acc);  // correctly rounded (HIP default for sqrtf); __fsqrt_rn may map to the native approximation
+}
+
+__device__ __forceinline__ int nearest_code(const float4 u, const float4* __restrict__ cb, int ksub) {
+    float best = INFINITY;
+    int bi = 0;
+    for (int b = 0; b < ksub; ++b) {
+        const float4 v = cb[b];
+        float t, acc;
+        t = __fsub_rn(u.x, v.x); acc = __fmul_rn(t, t);
+        t = __fsub_rn(u.y, v.y); acc = __fadd_rn(acc, __fmul_rn(t, t));
+        t = __fsub_rn(u.z, v.z); acc = __fadd_rn(acc, __fmul_rn(t, t));
+        t = __fsub_rn(u.w, v.w); acc = __fadd_rn(acc, __fmul_rn(t, t));
+        if (acc < best) {
+            best = acc;
+            bi = b;
+        }
+    }
+    return bi;
+}
+
+__global__ void __launch_bounds__(256) residuals_kernel(const float* __restrict__ x, const int32_t* __restrict__ assign,
+                                                        const float* __restrict__ C, int64_t K,
+                                                        const int64_t* __restrict__ rows, int64_t n, int normalize,
+                                                        float* __restrict__ R, float* __restrict__ rnorm) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = rows ? rows[i] : i;
+        const int32_t a = assign[row];
+        float4* out = reinterpret_cast<float4*>(R + i * kDim);
+        if (a < 0 || a >= K) {
+            for (int q = 0; q < kDim / 4; ++q) out[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (rnorm) rnorm[i] = 0.f;
+            continue;
+        }
+        const float* xr = x + row * kDim;
+        const float* cr = C + (int64_t)a * kDim;
+        const float rho = residual_norm(xr, cr);
+        const bool scale = normalize && rho > 0.f;
+        for (int q = 0; q < kDim / 4; ++q) {
+            const float4 xa = reinterpret_cast<const float4*>(xr)[q];
+            const float4 cb = reinterpret_cast<const float4*>(cr)[q];
+            float4 r;
+            r.x = __fsub_rn(xa.x, cb.x);
+            r.y = __fsub_rn(xa.y, cb.y);
+            r.z = __fsub_rn(xa.z, cb.z);
+            r.w = __fsub_rn(xa.w, cb.w);
+            if (scale) {
+                r.x = __fdiv_rn(r.x, rho);
+                r.y = __fdiv_rn(r.y, rho);
+                r.z = __fdiv_rn(r.z, rho);
+                r.w = __fdiv_rn(r.w, rho);
+            } else if (normalize) {
+                r = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            out[q] = r;
+        }
+        if (rnorm) rnorm[i] = rho;
+    }
+}
+
+__device__ void load_codebooks(const float* __restrict__ cb, int M, int ksub, float* lds) {
+    const int nf4 = M * ksub;  // float4 entries
+    for (int i = threadIdx.x; i < nf4; i += blockDim.x)
+        reinterpret_cast<float4*>(lds)[i] = reinterpret_cast<const float4*>(cb)[i];
+    __syncthreads();
+}
+
+// Fused residual + normalisation + encoding, one row per thread.
+__global__ void __launch_bounds__(256) encode_kernel(const float* __restrict__ x, const int32_t* __restrict__ assign,
+                                                     const float* __restrict__ C, int64_t K, int64_t n, int normalize,
+                                                     const float* __restrict__ cb, int M, int ksub,
+                                                     uint8_t* __restrict__ codes, float* __restrict__ rnorm) {
+    extern __shared__ float lcb[];
+    load_codebooks(cb, M, ksub, lcb);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = assign[i];
+        uint8_t* out = codes + i * M;
+        if (a < 0 || a >= K) {
+            for (int m = 0; m < M; ++m) out[m] = 0;
+            if (rnorm) rnorm[i] = 0.f;
+            continue;
+        }
+        const float* xr = x + i * kDim;
+        const float* cr = C + (int64_t)a * kDim;
+        const float rho = residual_norm(xr, cr);
+        const bool scale = normalize && rho > 0.f;
+        for (int m = 0; m < M; ++m) {
+            const float4 xa = reinterpret_cast<const float4*>(xr)[m];
+            const float4 cv = reinterpret_cast<const float4*>(cr)[m];
+            float4 u;
+            u.x = __fsub_rn(xa.x, cv.x);
+            u.y = __fsub_rn(xa.y, cv.y);
+            u.z = __fsub_rn(xa.z, cv.z);
+            u.w = __fsub_rn(xa.w, cv.w);
+            if (scale) {
+                u.x = __fdiv_rn(u.x, rho);
+                u.y = __fdiv_rn(u.y, rho);
+                u.z = __fdiv_rn(u.z, rho);
+                u.w = __fdiv_rn(u.w, rho);
+            } else if (normalize) {
+                u = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            out[m] = (uint8_t)nearest_code(u, reinterpret_cast<const float4*>(lcb) + m * ksub, ksub);
+        }
+        if (rnorm) rnorm[i] = rho;
+    }
+}
+
+// Codes of training rows R (already normalised residuals), one row per thread.
+__global__ void __launch_bounds__(256) train_encode(const float* __restrict__ R, int64_t n,
+                                                    const float* __restrict__ cb, int M, int ksub,
+                                                    uint32_t* __restrict__ codes /* [M][n] */) {
+    extern __shared__ float lcb[];
+    load_codebooks(cb, M, ksub, lcb);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        for (int m = 0; m < M; ++m) {
+            const float4 u = reinterpret_cast<const float4*>(R + i * kDim)[m];
+            codes[(int64_t)m * n + i] = (uint32_t)nearest_code(u, reinterpret_cast<const float4*>(lcb) + m * ksub, ksub);
+        }
+    }
+}
+
+// off[b] = first sorted position with code >= b, b in [0, ksub]
+__global__ void code_offsets(const uint32_t* __restrict__ keys, int64_t n, int ksub, int64_t* __restrict__ off) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t prev = i == 0 ? -1 : (int64_t)keys[i - 1];
+        const int64_t cur = i == n ? ksub : (int64_t)keys[i];
+        for (int64_t t = prev + 1; t <= cur; ++t) off[t] = i;
+    }
+}
+
+// New code vectors of subspace m: one wavefront per code, lanes stride over its
+// members in sorted order, float64 partials combined by a fixed butterfly.
+__global__ void __launch_bounds__(256) code_means(const float* __restrict__ R, const int32_t* __restrict__ rows,
+                                                  const int64_t* __restrict__ off, int m, int ksub,
+                                                  const float* __restrict__ cb_old, float* __restrict__ cb_new) {
+    const int lane = threadIdx.x & 63;
+    const int b = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (b >= ksub) return;
+    const int64_t s = off[b], e = off[b + 1];
+    double acc[kDsub] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t p = s + lane; p < e; p += 64) {
+        const float4 v = reinterpret_cast<const float4*>(R + (int64_t)rows[p] * kDim)[m];
+        acc[0] += (double)v.x;
+        acc[1] += (double)v.y;
+        acc[2] += (double)v.z;
+        acc[3] += (double)v.w;
+    }
+    for (int k = 32; k > 0; k >>= 1)
+        for (int i = 0; i < kDsub; ++i) acc[i] += __shfl_xor(acc[i], k);
+    if (lane == 0) {
+        float4* out = reinterpret_cast<float4*>(cb_new) + (int64_t)m * ksub + b;
+        const int64_t cnt = e - s;
+        if (cnt == 0) {
+            *out = reinterpret_cast<const float4*>(cb_old)[(int64_t)m * ksub + b];
+        } else {
+            float4 r;
+            r.x = (float)(acc[0] / (double)cnt);
+            r.y = (float)(acc[1] / (double)cnt);
+            r.z = (float)(acc[2] / (double)cnt);
+            r.w = (float)(acc[3] / (double)cnt);
+            *out = r;
+        }
+    }
+}
+
+unsigned grid_for(int64_t work, int per_block) {
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (unsigned)g;
+}
+
+tac_status check_pq(int32_t d, int32_t M, int32_t ksub, const char* who) {
+    if (d != kDim) return set_error(TAC_E_INVAL, std::string(who) + ": d must be 128");
+    if (M <= 0 || d % M != 0 || d / M != kDsub)
+        return set_error(TAC_E_INVAL, std::string(who) + ": subspaces of 4 coordinates are required (M = 32)");
+    if (ksub < 1 || ksub > 256) return set_error(TAC_E_INVAL, std::string(who) + ": ksub must be in [1, 256]");
+    return TAC_OK;
+}
+
+bool g_attr_encode = false, g_attr_train = false;
+
+}  // namespace
+
+}  // namespace tac
+
+using namespace tac;
+
+extern "C" tac_status tac_residuals(tac_ctx ctx, const float* x_d, const int32_t* assign_d, const float* C_d, int64_t K,
+                                    const int64_t* rows_d, int64_t n, int32_t d, int normalize, float* R_d,
+                                    float* rnorm_d) {
+    if (!ctx) return set_error(TAC_E_INVAL, "tac_residuals: ctx is NULL");
+    if (d != kDim) return set_error(TAC_E_INVAL, "tac_residuals: d must be 128");
+    if (n < 0 || K < 0) return set_error(TAC_E_INVAL, "tac_residuals: bad sizes");
+    if (n == 0) return TAC_OK;
+    if (!x_d || !assign_d || !R_d || (K > 0 && !C_d)) return set_error(TAC_E_INVAL, "tac_residuals: NULL pointer");
+    TAC_HIP(hipSetDevice(ctx->device));
+    residuals_kernel<<<grid_for(n, 256), 256, 0, ctx->stream>>>(x_d, assign_d, C_d, K, rows_d, n, normalize, R_d,
+                                                                 rnorm_d);
+    TAC_LAUNCH_CHECK("residuals_kernel");
+    return TAC_OK;
+}
+
+extern "C" tac_status pq_encode(tac_ctx ctx, const float* x_d, const int32_t* assign_d, const float* C_d, int64_t K,
+                                int64_t n, int32_t d, const float* codebooks_d, int32_t M, int32_t ksub,
+                                int normalize, uint8_t* codes_d, float* rnorm_d) {
+    if (!ctx) return set_error(TAC_E_INVAL, "pq_encode: ctx is NULL");
+    tac_status st = check_pq(d, M, ksub, "pq_encode");
+    if (st != TAC_OK) return st;
+    if (n < 0 || K < 0) return set_error(TAC_E_INVAL, "pq_encode: bad sizes");
+    if (n == 0) return TAC_OK;
+    if (!x_d || !assign_d || !codebooks_d || !codes_d || (K > 0 && !C_d))
+        return set_error(TAC_E_INVAL, "pq_encode: NULL pointer");
+    TAC_HIP(hipSetDevice(ctx->device));
+    const size_t lds = (size_t)M * ksub * kDsub * sizeof(float);
+    if (!g_attr_encode) {
+        TAC_HIP(hipFuncSetAttribute((const void*)encode_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(kMaxCodebookFloats * sizeof(float))));
+        g_attr_encode = true;
+    }
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, (int64_t)ctx->props_cu * 4);
+    time_start(ctx, TAC_SLOT_ENCODE);
+    encode_kernel<<<grid, 256, lds, ctx->stream>>>(x_d, assign_d, C_d, K, n, normalize, codebooks_d, M, ksub, codes_d,
+                                                   rnorm_d);
+    TAC_LAUNCH_CHECK("encode_kernel");
+    time_stop(ctx, TAC_SLOT_ENCODE);
+    return TAC_OK;
+}
+
+extern "C" tac_status pq_train(tac_ctx ctx, const float* R_d, int64_t n, int32_t d, int32_t M, int32_t ksub,
+                               int32_t iters, const float* init_d, float* codebooks_d) {
+    if (!ctx) return set_error(TAC_E_INVAL, "pq_train: ctx is NULL");
+    tac_status st = check_pq(d, M, ksub, "pq_train");
+    if (st != TAC_OK) return st;
+    if (n < 0 || n > INT32_MAX || iters < 0) return set_error(TAC_E_INVAL, "pq_train: bad sizes");
+    if (!init_d || !codebooks_d || (n > 0 && !R_d)) return set_error(TAC_E_INVAL, "pq_train: NULL pointer");
+    TAC_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const size_t cb_bytes = (size_t)M * ksub * kDsub * sizeof(float);
+    Carve cv;
+    const size_t o_codes = cv.take<uint32_t>((int64_t)M * n + 1);
+    const size_t o_k1 = cv.take<uint32_t>(n + 1);
+    const size_t o_v0 = cv.take<int32_t>(n + 1), o_v1 = cv.take<int32_t>(n + 1);
+    const size_t o_sort = cv.take<char>(radix_sort_scratch_bytes(n));
+    const size_t o_off = cv.take<int64_t>(ksub + 1);
+    const size_t o_cb = cv.take<char>(cb_bytes);
+    st = ws_reserve(ctx, cv.off);
+    if (st != TAC_OK) return st;
+    uint32_t* codes = ws_at<uint32_t>(ctx, o_codes);
+    uint32_t* k1 = ws_at<uint32_t>(ctx, o_k1);
+    int32_t* v0 = ws_at<int32_t>(ctx, o_v0);
+    int32_t* v1 = ws_at<int32_t>(ctx, o_v1);
+    int64_t* off = ws_at<int64_t>(ctx, o_off);
+    float* cur = ws_at<float>(ctx, o_cb);
+    if (init_d != codebooks_d)
+        TAC_HIP(hipMemcpyAsync(codebooks_d, init_d, cb_bytes, hipMemcpyDeviceToDevice, s));
+    if (!g_attr_train) {
+        TAC_HIP(hipFuncSetAttribute((const void*)train_encode, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(kMaxCodebookFloats * sizeof(float))));
+        g_attr_train = true;
+    }
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, (int64_t)ctx->props_cu * 4));
+    for (int it = 0; it < iters && n > 0; ++it) {
+        TAC_HIP(hipMemcpyAsync(cur, codebooks_d, cb_bytes, hipMemcpyDeviceToDevice, s));
+        train_encode<<<grid, 256, cb_bytes, s>>>(R_d, n, cur, M, ksub, codes);
+        TAC_LAUNCH_CHECK("train_encode");
+        for (int m = 0; m < M; ++m) {
+            uint32_t* keys = codes + (int64_t)m * n;  // sorted in place (ping-pong with k1)
+            int in1 = 0;
+            st = radix_sort(s, n, 8, keys, v0, k1, v1, nullptr, ws_at<void>(ctx, o_sort), &in1);
+            if (st != TAC_OK) return st;
+            code_offsets<<<grid_for(n + 1, 256), 256, 0, s>>>(in1 ? k1 : keys, n, ksub, off);
+            TAC_LAUNCH_CHECK("code_offsets");
+            code_means<<<(unsigned)((ksub * 64 + 255) / 256), 256, 0, s>>>(R_d, in1 ? v1 : v0, off, m, ksub, cur,
+                                                                          codebooks_d);
+            TAC_LAUNCH_CHECK("code_means");
+        }
+    }
+    return TAC_OK;
+}

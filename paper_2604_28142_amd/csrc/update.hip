@@ -1,0 +1,143 @@
+// Update step of per-token Lloyd (Sect. 2.1): each centroid becomes the mean of
+// its rows; a centroid with no rows keeps its previous value.
+//
+// Determinism without float atomics: rows are stably sorted by assigned
+// centroid (radix sort on the assignment), so every centroid's members form a
+// contiguous run in ascending row order, and one wavefront sums each run in
+// that fixed order (two dimensions per lane).  Tokens with more than 65,536
+// rows sum in float64; smaller ones use compensated (Kahan) float32 sums.
+#include "tac_internal.h"
+
+namespace tac {
+
+namespace {
+
+__global__ void update_keys(const int32_t* __restrict__ assign, int64_t n, int64_t K, uint32_t* __restrict__ keys) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = assign[i];
+        keys[i] = (a < 0 || a >= K) ? (uint32_t)K : (uint32_t)a;
+    }
+}
+
+// off[k] = first sorted position with key >= k, for k in [0, K].
+__global__ void member_offsets(const uint32_t* __restrict__ keys, int64_t n, int64_t K, int64_t* __restrict__ off) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t prev = i == 0 ? -1 : (int64_t)keys[i - 1];
+        int64_t cur = i == n ? K : (int64_t)keys[i];
+        if (cur > K) cur = K;
+        for (int64_t t = prev + 1; t <= cur; ++t) off[t] = i;
+    }
+}
+
+__global__ void __launch_bounds__(256) centroid_means(const float* __restrict__ xs, const int64_t* __restrict__ seg_off,
+                                                      int32_t T, const int32_t* __restrict__ rows,
+                                                      const int64_t* __restrict__ off, int64_t K,
+                                                      const float* __restrict__ C_old, float* __restrict__ C_new,
+                                                      int64_t* __restrict__ count) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t k = wave0; k < K; k += nwaves) {
+        const int64_t b = off[k], e = off[k + 1];
+        const int64_t cnt = e - b;
+        if (count && lane == 0) count[k] = cnt;
+        float2* out = reinterpret_cast<float2*>(C_new + k * kDim);
+        if (cnt == 0) {
+            out[lane] = reinterpret_cast<const float2*>(C_old + k * kDim)[lane];
+            continue;
+        }
+        // the token of this centroid: the segment holding its first member row
+        const int64_t r0 = rows[b];
+        int32_t lo = 0, hi = T;
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (seg_off[mid] <= r0) lo = mid; else hi = mid;
+        }
+        const bool wide = seg_off[lo + 1] - seg_off[lo] > kFp64Rows;
+        float2 mean;
+        if (wide) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int64_t p = b; p < e; ++p) {
+                const float2 v = reinterpret_cast<const float2*>(xs + (int64_t)rows[p] * kDim)[lane];
+                s0 += (double)v.x;
+                s1 += (double)v.y;
+            }
+            mean.x = (float)(s0 / (double)cnt);
+            mean.y = (float)(s1 / (double)cnt);
+        } else {
+            float s0 = 0.f, s1 = 0.f, c0 = 0.f, c1 = 0.f;
+            for (int64_t p = b; p < e; ++p) {
+                const float2 v = reinterpret_cast<const float2*>(xs + (int64_t)rows[p] * kDim)[lane];
+                float y = __fsub_rn(v.x, c0);
+                float t = __fadd_rn(s0, y);
+                c0 = __fsub_rn(__fsub_rn(t, s0), y);
+                s0 = t;
+                y = __fsub_rn(v.y, c1);
+                t = __fadd_rn(s1, y);
+                c1 = __fsub_rn(__fsub_rn(t, s1), y);
+                s1 = t;
+            }
+            const float fc = (float)cnt;
+            mean.x = __fdiv_rn(__fsub_rn(s0, c0), fc);
+            mean.y = __fdiv_rn(__fsub_rn(s1, c1), fc);
+        }
+        out[lane] = mean;
+    }
+}
+
+unsigned grid_for(int64_t work, int per_block) {
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+}  // namespace tac
+
+using namespace tac;
+
+extern "C" tac_status tac_update(tac_ctx ctx, const float* xs_d, const int64_t* seg_off_d, int32_t T, int64_t N,
+                                 int32_t d, const int32_t* assign_d, const float* C_old_d, int64_t K, float* C_new_d,
+                                 int64_t* count_d) {
+    if (!ctx) return set_error(TAC_E_INVAL, "tac_update: ctx is NULL");
+    if (d != kDim) return set_error(TAC_E_INVAL, "tac_update: d must be 128");
+    if (N < 0 || N > INT32_MAX || K < 0 || K >= INT32_MAX || T < 1)
+        return set_error(TAC_E_INVAL, "tac_update: bad sizes");
+    if (K == 0) return TAC_OK;
+    if (!seg_off_d || !C_old_d || !C_new_d || (N > 0 && (!xs_d || !assign_d)))
+        return set_error(TAC_E_INVAL, "tac_update: NULL pointer");
+    if (C_old_d == C_new_d) return set_error(TAC_E_INVAL, "tac_update: C_old_d and C_new_d must not alias");
+    TAC_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    Carve cv;
+    const size_t o_k0 = cv.take<uint32_t>(N + 1), o_v0 = cv.take<int32_t>(N + 1);
+    const size_t o_k1 = cv.take<uint32_t>(N + 1), o_v1 = cv.take<int32_t>(N + 1);
+    const size_t o_sort = cv.take<char>(radix_sort_scratch_bytes(N));
+    const size_t o_off = cv.take<int64_t>(K + 1);
+    tac_status st = ws_reserve(ctx, cv.off);
+    if (st != TAC_OK) return st;
+    uint32_t* k0 = ws_at<uint32_t>(ctx, o_k0);
+    int32_t* v0 = ws_at<int32_t>(ctx, o_v0);
+    uint32_t* k1 = ws_at<uint32_t>(ctx, o_k1);
+    int32_t* v1 = ws_at<int32_t>(ctx, o_v1);
+    int64_t* off = ws_at<int64_t>(ctx, o_off);
+    if (N > 0) {
+        update_keys<<<grid_for(N, 256), 256, 0, s>>>(assign_d, N, K, k0);
+        TAC_LAUNCH_CHECK("update_keys");
+    }
+    int bits = 1;
+    while (bits < 31 && (int64_t(1) << bits) <= K) ++bits;
+    int in1 = 0;
+    st = radix_sort(s, N, bits, k0, v0, k1, v1, nullptr, ws_at<void>(ctx, o_sort), &in1);
+    if (st != TAC_OK) return st;
+    member_offsets<<<grid_for(N + 1, 256), 256, 0, s>>>(in1 ? k1 : k0, N, K, off);
+    TAC_LAUNCH_CHECK("member_offsets");
+    time_start(ctx, TAC_SLOT_UPDATE);
+    centroid_means<<<grid_for(K * 64, 256), 256, 0, s>>>(xs_d, seg_off_d, T, in1 ? v1 : v0, off, K, C_old_d, C_new_d,
+                                                         count_d);
+    TAC_LAUNCH_CHECK("centroid_means");
+    time_stop(ctx, TAC_SLOT_UPDATE);
+    return TAC_OK;
+}

@@ -31,10 +31,11 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 constexpr int kNB = 4;                          // 16-row column blocks per wave
-constexpr int kTileRows = kWaves * kNB * 16;    // rows per work item
+constexpr int kTileRows = kWaves * kNB * 16;    // rows per screened work item
+constexpr int kDirectRows = kThreads;           // rows per direct work item (one per thread)
 constexpr int kStage = 64;                      // centroids per LDS stage
 constexpr int kRowWords = 132;                  // LDS row stride (512 B + 16 B pad)
 constexpr int kEpochBlocks = 64;                // 16-centroid blocks per packed-index epoch
@@ -42,6 +43,10 @@ constexpr int kDirectMax = 4;                   // tokens with at most this many
 constexpr int kHeavy = 1024;                    // tokens with this many centroids are scheduled first
 constexpr float kInvalid = 3.0e38f;             // screen value of padding centroids
 constexpr unsigned kCntRows = 0, kCntScreened = 1, kCntFallback = 2, kCntUnassigned = 3;
+constexpr int kFbChunks = 16;                   // centroid chunks per fallback row
+// dynamic LDS of the assignment kernel: two centroid stages, their norms, then the
+// per-lane merged top-4 lists (value and index words) of every wave
+constexpr size_t kGlistOffsetWords = (size_t)2 * kStage * kRowWords + (size_t)2 * kStage;
 
 __device__ __forceinline__ float dist32_rows(const float* __restrict__ x, const float* __restrict__ c, float* xx) {
     const float4* xv = reinterpret_cast<const float4*>(x);
@@ -82,15 +87,18 @@ __global__ void plan_count(const int64_t* __restrict__ seg_off, const int64_t* _
     if (j >= T) return;
     const int64_t n = seg_off[j + 1] - seg_off[j];
     const int64_t k = cent_off[j + 1] - cent_off[j];
-    const int64_t tiles = (n + kTileRows - 1) / kTileRows;
     const int cls = k <= kDirectMax ? 2 : (k >= kHeavy ? 0 : 1);
+    const int64_t rows = cls == 2 ? kDirectRows : kTileRows;
+    const int64_t tiles = (n + rows - 1) / rows;
     for (int c = 0; c < 3; ++c) cnt[(int64_t)c * T + j] = c == cls ? tiles : 0;
 }
 
 // ---- centroid preparation: squared norms, max norm, BF16 hi/lo splits ----
-__global__ void prep_centroids(const float* __restrict__ C, int64_t K, float* __restrict__ cn,
-                               unsigned* __restrict__ cstat, unsigned short* __restrict__ chl) {
+__global__ void __launch_bounds__(256) prep_centroids(const float* __restrict__ C, int64_t K, float* __restrict__ cn,
+                                                      unsigned* __restrict__ cstat, unsigned short* __restrict__ chl) {
+    __shared__ unsigned red[256];
     const int sub = threadIdx.x & 31;
+    unsigned mx = 0;
     for (int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5; k < K;
          k += ((int64_t)gridDim.x * blockDim.x) >> 5) {
         const float4 v = reinterpret_cast<const float4*>(C + k * kDim)[sub];
@@ -99,10 +107,8 @@ __global__ void prep_centroids(const float* __restrict__ C, int64_t K, float* __
         s = s + v.z * v.z;
         s = s + v.w * v.w;
         for (int m = 16; m > 0; m >>= 1) s += __shfl_xor(s, m, 32);
-        if (sub == 0) {
-            cn[k] = s;
-            atomicMax(cstat, __float_as_uint(s));
-        }
+        if (sub == 0) cn[k] = s;
+        mx = max(mx, __float_as_uint(s));  // non-negative floats order like their bit patterns
         if (chl) {
             const float e[4] = {v.x, v.y, v.z, v.w};
             unsigned short hi[4], lo[4];
@@ -120,6 +126,13 @@ __global__ void prep_centroids(const float* __restrict__ C, int64_t K, float* __
             reinterpret_cast<uint2*>(row + kDim)[sub] = l;
         }
     }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0]) atomicMax(cstat, red[0]);
 }
 
 struct Params {
@@ -140,11 +153,19 @@ struct Params {
     unsigned long long* counters;
 };
 
-__device__ __forceinline__ void list_insert(float (&l)[4], float p) {
-    l[3] = __builtin_amdgcn_fmed3f(l[2], l[3], p);
-    l[2] = __builtin_amdgcn_fmed3f(l[1], l[2], p);
-    l[1] = __builtin_amdgcn_fmed3f(l[0], l[1], p);
-    l[0] = fminf(l[0], p);
+__device__ __forceinline__ unsigned med3u(unsigned a, unsigned b, unsigned c) {
+    unsigned r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// Running top-4 of packed keys (bit pattern of a non-negative float with its low
+// 8 bits replaced by a lane-local candidate index): one min and three med3.
+__device__ __forceinline__ void list_insert(unsigned (&l)[4], unsigned p) {
+    l[3] = med3u(l[2], l[3], p);
+    l[2] = med3u(l[1], l[2], p);
+    l[1] = med3u(l[0], l[1], p);
+    l[0] = min(l[0], p);
 }
 
 // Insert (t, i) into the ascending list (G, I); `lex` breaks value ties by index.
@@ -168,23 +189,27 @@ struct Frag;
 template <>
 struct Frag<TAC_FP32> {
     float x[kNB][32];
-    float c[32];
 };
 
 template <>
 struct Frag<TAC_BF16> {
     bf8 xh[kNB][4];
     bf8 xl[kNB][4];
-    bf8 ch[4];
-    bf8 cl[4];
 };
 
-__device__ __forceinline__ bf8 pack_bf8(const unsigned short* h) {
-    bf8 r;
-    unsigned short* p = reinterpret_cast<unsigned short*>(&r);
+typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+
+// hi = bf16(v), lo = bf16(v - hi) for 8 consecutive values (round to nearest even)
+__device__ __forceinline__ void split_bf8(const float* v, bf8& hi, bf8& lo) {
+    us8 h, l;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) p[e] = h[e];
-    return r;
+    for (int e = 0; e < 8; ++e) {
+        const unsigned short a = bf16_rne(v[e]);
+        h[e] = a;
+        l[e] = bf16_rne(v[e] - bf16_to_f(a));
+    }
+    hi = __builtin_bit_cast(bf8, h);
+    lo = __builtin_bit_cast(bf8, l);
 }
 
 template <int PREC>
@@ -192,7 +217,7 @@ __device__ __forceinline__ void direct_item(const Params& P, int32_t j, int64_t 
     const int64_t s0 = P.seg_off[j], s1 = P.seg_off[j + 1];
     const int64_t k0 = P.cent_off[j];
     const int kc = (int)(P.cent_off[j + 1] - k0);
-    const int64_t row0 = s0 + tile * kTileRows;
+    const int64_t row0 = s0 + tile * kDirectRows;
     const int64_t v = row0 + threadIdx.x;
     const bool valid = v < s1;
     if (valid) {
@@ -250,8 +275,8 @@ __device__ __forceinline__ void screen_item(const Params& P, int32_t j, int64_t 
     float* stage_cn = reinterpret_cast<float*>(lds + 2 * kStage * kRowWords);  // [2][kStage]
 
     Frag<PREC> F;
-    float beta[kNB];
     int64_t rowv[kNB];
+    float xxmax = 0.f;
 #pragma unroll
     for (int nb = 0; nb < kNB; ++nb) {
         const int64_t v = row0 + nb * 16 + col;
@@ -273,44 +298,45 @@ __device__ __forceinline__ void screen_item(const Params& P, int32_t j, int64_t 
         for (int i = 0; i < 32; ++i) xx += xs[i] * xs[i];
         xx += __shfl_xor(xx, 16);
         xx += __shfl_xor(xx, 32);
-        beta[nb] = xx * (1.0f + 0.00390625f) + 0.00390625f * cnmax + 1e-30f;
+        xxmax = fmaxf(xxmax, xx);
         if constexpr (PREC == TAC_FP32) {
 #pragma unroll
             for (int i = 0; i < 32; ++i) F.x[nb][i] = -2.0f * xs[i];
         } else {
-            unsigned short h[32], l[32];
 #pragma unroll
-            for (int i = 0; i < 32; ++i) {
-                const float m2 = -2.0f * xs[i];
-                h[i] = bf16_rne(m2);
-                l[i] = bf16_rne(m2 - bf16_to_f(h[i]));
-            }
+            for (int i = 0; i < 32; ++i) xs[i] = -2.0f * xs[i];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                F.xh[nb][s] = pack_bf8(h + 8 * s);
-                F.xl[nb][s] = pack_bf8(l + 8 * s);
-            }
+            for (int s = 0; s < 4; ++s) split_bf8(xs + 8 * s, F.xh[nb][s], F.xl[nb][s]);
         }
     }
+    // One shift for the whole wave makes every screen value positive:
+    // beta >= ||x||^2 + (screen error) for each of its rows, so that
+    // beta + ||c||^2 - 2 x.c >= ||x - c||^2 + margin > 0 and packed keys order as floats.
+#pragma unroll
+    for (int m = 1; m < 16; m <<= 1) xxmax = fmaxf(xxmax, __shfl_xor(xxmax, m));
+    const float beta = xxmax * (1.0f + 0.00390625f) + 0.00390625f * cnmax + 1e-30f;
 
-    float el[kNB][4];
-    float G[kNB][4];
-    int I[kNB][4];
+    // epoch lists in registers; the merged (value, index) lists of each row live in
+    // wave-private LDS, touched only at epoch ends and once per item
+    unsigned el[kNB][4];
+    unsigned* glist = lds + kGlistOffsetWords + (unsigned)wave * (kNB * 8 * 64) + lane;
+    auto gslot = [&](int nb, int e) -> unsigned& { return glist[(nb * 8 + e) * 64]; };
 #pragma unroll
     for (int nb = 0; nb < kNB; ++nb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            el[nb][e] = FLT_MAX;
-            G[nb][e] = kInvalid;
-            I[nb][e] = -1;
+            el[nb][e] = 0xFFFFFFFFu;
+            gslot(nb, e) = __float_as_uint(kInvalid);
+            gslot(nb, 4 + e) = 0xFFFFFFFFu;
         }
 
     const char* csrc = static_cast<const char*>(P.cstage);
     const int nst = (kc + kStage - 1) / kStage;
-    // stage loader: 64 rows x 512 B = 2048 float4; thread t moves 8 of them
-    auto load_stage = [&](int st, u4 (&reg)[8], float& rcn) {
+    // stage loader: 64 rows x 512 B = 2048 float4; each thread moves kStageVec of them
+    constexpr int kStageVec = kStage * 32 / kThreads;
+    auto load_stage = [&](int st, u4 (&reg)[kStageVec], float& rcn) {
 #pragma unroll
-        for (int it = 0; it < 8; ++it) {
+        for (int it = 0; it < kStageVec; ++it) {
             const int chunk = it * kThreads + threadIdx.x;
             const int row = chunk >> 5;
             const int c16 = chunk & 31;
@@ -320,9 +346,9 @@ __device__ __forceinline__ void screen_item(const Params& P, int32_t j, int64_t 
         const int kk = st * kStage + (threadIdx.x & 63);
         rcn = kk < kc ? P.cn[k0 + kk] : kInvalid;
     };
-    auto store_stage = [&](int buf, const u4 (&reg)[8], float rcn) {
+    auto store_stage = [&](int buf, const u4 (&reg)[kStageVec], float rcn) {
 #pragma unroll
-        for (int it = 0; it < 8; ++it) {
+        for (int it = 0; it < kStageVec; ++it) {
             const int chunk = it * kThreads + threadIdx.x;
             const int row = chunk >> 5;
             const int c16 = chunk & 31;
@@ -331,7 +357,7 @@ __device__ __forceinline__ void screen_item(const Params& P, int32_t j, int64_t 
         if (threadIdx.x < kStage) stage_cn[buf * kStage + threadIdx.x] = rcn;
     };
 
-    u4 pf[8];
+    u4 pf[kStageVec];
     float pcn;
     load_stage(0, pf, pcn);
     store_stage(0, pf, pcn);
@@ -347,69 +373,67 @@ __device__ __forceinline__ void screen_item(const Params& P, int32_t j, int64_t 
             if (blk16 * 16 >= kc) break;
             const unsigned* crow = stage_rows + (buf * kStage + b * 16 + col) * kRowWords;
             const f4 cinit = *reinterpret_cast<const f4*>(stage_cn + buf * kStage + b * 16 + 4 * g);
+            f4 acc[kNB];
+            const f4 cb4 = cinit + beta;
+#pragma unroll
+            for (int nb = 0; nb < kNB; ++nb) acc[nb] = cb4;
+            // centroid fragments stream from LDS one k-step group at a time
             if constexpr (PREC == TAC_FP32) {
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    const f4 v = *reinterpret_cast<const f4*>(crow + 32 * g + 4 * q);
-                    F.c[4 * q + 0] = v.x;
-                    F.c[4 * q + 1] = v.y;
-                    F.c[4 * q + 2] = v.z;
-                    F.c[4 * q + 3] = v.w;
+                    const f4 c4 = *reinterpret_cast<const f4*>(crow + 32 * g + 4 * q);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+#pragma unroll
+                        for (int nb = 0; nb < kNB; ++nb)
+                            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(c4[e], F.x[nb][4 * q + e], acc[nb], 0, 0, 0);
                 }
             } else {
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    F.ch[s] = *reinterpret_cast<const bf8*>(crow + 16 * g + 4 * s);
-                    F.cl[s] = *reinterpret_cast<const bf8*>(crow + 64 + 16 * g + 4 * s);
+                for (int st4 = 0; st4 < 4; ++st4) {
+                    const bf8 ch = *reinterpret_cast<const bf8*>(crow + 16 * g + 4 * st4);
+                    const bf8 cl = *reinterpret_cast<const bf8*>(crow + 64 + 16 * g + 4 * st4);
+#pragma unroll
+                    for (int nb = 0; nb < kNB; ++nb)
+                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, F.xh[nb][st4], acc[nb], 0, 0, 0);
+#pragma unroll
+                    for (int nb = 0; nb < kNB; ++nb)
+                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, F.xl[nb][st4], acc[nb], 0, 0, 0);
+#pragma unroll
+                    for (int nb = 0; nb < kNB; ++nb)
+                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl, F.xh[nb][st4], acc[nb], 0, 0, 0);
                 }
-            }
-            f4 acc[kNB];
-#pragma unroll
-            for (int nb = 0; nb < kNB; ++nb) acc[nb] = cinit + beta[nb];
-            if constexpr (PREC == TAC_FP32) {
-#pragma unroll
-                for (int s = 0; s < 32; ++s)
-#pragma unroll
-                    for (int nb = 0; nb < kNB; ++nb)
-                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(F.c[s], F.x[nb][s], acc[nb], 0, 0, 0);
-            } else {
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-#pragma unroll
-                    for (int nb = 0; nb < kNB; ++nb)
-                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.ch[s], F.xh[nb][s], acc[nb], 0, 0, 0);
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-#pragma unroll
-                    for (int nb = 0; nb < kNB; ++nb)
-                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.cl[s], F.xh[nb][s], acc[nb], 0, 0, 0);
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-#pragma unroll
-                    for (int nb = 0; nb < kNB; ++nb)
-                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.ch[s], F.xl[nb][s], acc[nb], 0, 0, 0);
             }
             const unsigned lb = (unsigned)(blk16 - epoch_first) * 4u;
 #pragma unroll
             for (int nb = 0; nb < kNB; ++nb)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float p = __uint_as_float((__float_as_uint(acc[nb][r]) & ~0xFFu) | (lb + r));
-                    list_insert(el[nb], p);
-                }
+                for (int r = 0; r < 4; ++r) list_insert(el[nb], (__float_as_uint(acc[nb][r]) & ~0xFFu) | (lb + r));
             const bool last = (blk16 + 1) * 16 >= kc;
             if (blk16 - epoch_first == kEpochBlocks - 1 || last) {
                 const int64_t ebase = k0 + (int64_t)epoch_first * 16 + 4 * g;
 #pragma unroll
                 for (int nb = 0; nb < kNB; ++nb) {
+                    float G[4];
+                    int I[4];
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        const unsigned bits = __float_as_uint(el[nb][e]);
+                        G[e] = __uint_as_float(gslot(nb, e));
+                        I[e] = (int)gslot(nb, 4 + e);
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const unsigned bits = el[nb][e];
                         const float t = __uint_as_float(bits & ~0xFFu);
                         const unsigned loc = bits & 0xFFu;
                         const int gi = (int)(ebase + (int64_t)(loc >> 2) * 16 + (loc & 3u));
-                        if (t < 1.0e38f) glist_insert(G[nb], I[nb], t, gi, false);
-                        el[nb][e] = FLT_MAX;
+                        if (t < 1.0e38f) glist_insert(G, I, t, gi, false);
+                        el[nb][e] = 0xFFFFFFFFu;
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        gslot(nb, e) = __float_as_uint(G[e]);
+                        gslot(nb, 4 + e) = (unsigned)I[e];
                     }
                 }
                 epoch_first = blk16 + 1;
@@ -419,34 +443,37 @@ __device__ __forceinline__ void screen_item(const Params& P, int32_t j, int64_t 
         __syncthreads();
     }
 
-    // merge the four lanes that share a row (lane groups g = 0..3)
-#pragma unroll
-    for (int m = 16; m <= 32; m <<= 1) {
-#pragma unroll
-        for (int nb = 0; nb < kNB; ++nb) {
-            float pt[4];
-            int pi[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                pt[e] = __shfl_xor(G[nb][e], m);
-                pi[e] = __shfl_xor(I[nb][e], m);
-            }
-#pragma unroll
-            for (int e = 0; e < 4; ++e) glist_insert(G[nb], I[nb], pt[e], pi[e], true);
-        }
-    }
-
     // rescore nominee g of each row with the canonical distance, then certify
     const double u = 5.9604644775390625e-8;  // 2^-24
     const double g130 = 130.0 * u / (1.0 - 130.0 * u);
     const double g386 = 386.0 * u / (1.0 - 386.0 * u);
     int nscreen = 0;
-#pragma unroll 1
+#pragma unroll
     for (int nb = 0; nb < kNB; ++nb) {
+        float G[4];
+        int I[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            G[e] = __uint_as_float(gslot(nb, e));
+            I[e] = (int)gslot(nb, 4 + e);
+        }
+        // merge the four lanes that share a row (lane groups g = 0..3)
+#pragma unroll
+        for (int m = 16; m <= 32; m <<= 1) {
+            float pt[4];
+            int pi[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                pt[e] = __shfl_xor(G[e], m);
+                pi[e] = __shfl_xor(I[e], m);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) glist_insert(G, I, pt[e], pi[e], true);
+        }
         const int64_t v = rowv[nb];
         const bool valid = v < s1;
         const int64_t r = valid ? (P.rowmap ? (int64_t)P.rowmap[v] : v) : 0;
-        const int nom = g == 0 ? I[nb][0] : g == 1 ? I[nb][1] : g == 2 ? I[nb][2] : I[nb][3];
+        const int nom = g == 0 ? I[0] : g == 1 ? I[1] : g == 2 ? I[2] : I[3];
         float d32 = INFINITY, xxc = 0.f;
         if (valid && nom >= 0) d32 = dist32_rows(P.x + r * kDim, P.C + (int64_t)nom * kDim, &xxc);
         if (valid && nom < 0) dist32_rows(P.x + r * kDim, P.x + r * kDim, &xxc);
@@ -464,13 +491,13 @@ __device__ __forceinline__ void screen_item(const Params& P, int32_t j, int64_t 
         const float xxs = __shfl(xxc, col);  // lane group 0 holds the canonical ||x||^2
         if (valid && g == 0) {
             ++nscreen;
-            const double tau = (double)G[nb][3];
+            const double tau = (double)G[3];
             bool ok = tau >= 1.0e38;
             if (!ok) {
                 const double xx_hi = (double)xxs * (1.0 + g130);
                 const double xx_lo = (double)xxs * (1.0 - g130);
                 const double xn = sqrt(xx_hi);
-                const double bt = (double)beta[nb];
+                const double bt = (double)beta;
                 const double cm = (double)cmax, cn2 = (double)cnmax;
                 double E;
                 if constexpr (PREC == TAC_FP32)
@@ -525,49 +552,64 @@ __global__ void __launch_bounds__(kThreads) assign_main(Params P) {
     }
 }
 
-// Exhaustive canonical rescoring of the rows whose certificate failed: one
-// wavefront per row, lanes stride over the token's centroids.
-__global__ void __launch_bounds__(256) assign_fallback(const float* __restrict__ x, const int32_t* __restrict__ rowmap,
-                                                       const int64_t* __restrict__ cent_off, const float* __restrict__ C,
-                                                       const int32_t* __restrict__ fb,
-                                                       const unsigned long long* __restrict__ counters,
-                                                       int32_t* __restrict__ assign, float* __restrict__ dist) {
-    __shared__ float xrow[4][kDim];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+// Exhaustive canonical rescoring of the rows whose certificate failed.  Work
+// item (row q, chunk c): a block scans chunk c of the row's token centroids and
+// folds its best (distance, index) into the row's 64-bit slot with atomicMin;
+// non-negative float bits in the high word order like the distances, so the
+// slot ends at the lexicographic minimum whatever the order of the blocks.
+__global__ void fb_init(const unsigned long long* __restrict__ counters, unsigned long long* __restrict__ slot) {
     const int64_t nfb = (int64_t)counters[kCntFallback];
-    for (int64_t q = (int64_t)blockIdx.x * 4 + wave; q < nfb; q += (int64_t)gridDim.x * 4) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nfb; q += (int64_t)gridDim.x * blockDim.x)
+        slot[q] = ~0ull;
+}
+
+__global__ void __launch_bounds__(256) fb_scan(const float* __restrict__ x, const int32_t* __restrict__ rowmap,
+                                               const int64_t* __restrict__ cent_off, const float* __restrict__ C,
+                                               const int32_t* __restrict__ fb,
+                                               const unsigned long long* __restrict__ counters,
+                                               unsigned long long* __restrict__ slot) {
+    __shared__ float xrow[kDim];
+    __shared__ unsigned long long red[256];
+    const int64_t total = (int64_t)counters[kCntFallback] * kFbChunks;
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        const int64_t q = w / kFbChunks;
+        const int c = (int)(w % kFbChunks);
         const int64_t v = fb[2 * q];
         const int32_t j = fb[2 * q + 1];
         const int64_t r = rowmap ? (int64_t)rowmap[v] : v;
-        xrow[wave][lane] = x[r * kDim + lane];
-        xrow[wave][lane + 64] = x[r * kDim + lane + 64];
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __syncthreads();
+        if (threadIdx.x < kDim) xrow[threadIdx.x] = x[r * kDim + threadIdx.x];
+        __syncthreads();
         const int64_t k0 = cent_off[j];
-        const int kc = (int)(cent_off[j + 1] - k0);
-        float bd = INFINITY;
-        int bi = INT32_MAX;
-        for (int k = lane; k < kc; k += 64) {
-            const float d = dist32_rows(xrow[wave], C + (k0 + k) * kDim, nullptr);
-            if (d < bd) {
-                bd = d;
-                bi = (int)(k0 + k);
-            }
+        const int64_t kc = cent_off[j + 1] - k0;
+        const int64_t lo = k0 + kc * c / kFbChunks, hi = k0 + kc * (c + 1) / kFbChunks;
+        unsigned long long best = ~0ull;
+        for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+            const float d = dist32_rows(xrow, C + k * kDim, nullptr);
+            const unsigned long long key = ((unsigned long long)__float_as_uint(d) << 32) | (unsigned)k;
+            best = key < best ? key : best;
         }
-        for (int m = 32; m > 0; m >>= 1) {
-            const float od = __shfl_xor(bd, m);
-            const int oi = __shfl_xor(bi, m);
-            if (od < bd || (od == bd && oi < bi)) {
-                bd = od;
-                bi = oi;
-            }
+        red[threadIdx.x] = best;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if (threadIdx.x < off) red[threadIdx.x] = red[threadIdx.x + off] < red[threadIdx.x] ? red[threadIdx.x + off]
+                                                                                             : red[threadIdx.x];
+            __syncthreads();
         }
-        if (lane == 0) {
-            assign[r] = bi;
-            dist[r] = bd;
-        }
-        __builtin_amdgcn_wave_barrier();
+        if (threadIdx.x == 0 && red[0] != ~0ull) atomicMin(&slot[q], red[0]);
+    }
+}
+
+__global__ void fb_final(const int32_t* __restrict__ rowmap, const int32_t* __restrict__ fb,
+                         const unsigned long long* __restrict__ counters, const unsigned long long* __restrict__ slot,
+                         int32_t* __restrict__ assign, float* __restrict__ dist) {
+    const int64_t nfb = (int64_t)counters[kCntFallback];
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nfb; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = fb[2 * q];
+        const int64_t r = rowmap ? (int64_t)rowmap[v] : v;
+        const unsigned long long key = slot[q];
+        assign[r] = (int32_t)(unsigned)(key & 0xFFFFFFFFull);
+        dist[r] = __uint_as_float((unsigned)(key >> 32));
     }
 }
 
@@ -638,7 +680,7 @@ unsigned grid_for(int64_t work, int per_block) {
     return (unsigned)g;
 }
 
-constexpr size_t kLdsBytes = (size_t)2 * kStage * kRowWords * 4 + (size_t)2 * kStage * 4;
+constexpr size_t kLdsBytes = (kGlistOffsetWords + (size_t)kWaves * kNB * 8 * 64) * 4;
 
 }  // namespace
 
@@ -672,6 +714,7 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     const size_t o_cn = cv.take<float>(K + 1);
     const size_t o_chl = precision == TAC_BF16 ? cv.take<unsigned short>((K + 1) * 2 * kDim) : 0;
     const size_t o_fb = cv.take<int32_t>(2 * (N + 1));
+    const size_t o_slot = cv.take<unsigned long long>(N + 1);
     const size_t o_dist = dist_d ? 0 : cv.take<float>(N + 1);
     const int64_t nred = (N + kRedThreads * kRedItems - 1) / (kRedThreads * kRedItems);
     const size_t o_red = cv.take<double>(nred + 1);
@@ -741,15 +784,18 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     P.dist = dist;
     P.fb = ws_at<int32_t>(ctx, o_fb);
     P.counters = ctx->counters;
-    const unsigned grid = (unsigned)ctx->props_cu * 2;
-    static bool lds_attr_set = false;
-    if (!lds_attr_set) {
+    // persistent grid: as many work-group slots as the device holds at once
+    static int occ[2] = {0, 0};
+    if (!occ[0]) {
         TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_FP32>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)kLdsBytes));
         TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_BF16>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)kLdsBytes));
-        lds_attr_set = true;
+        TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], assign_main<TAC_FP32>, kThreads, kLdsBytes));
+        TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], assign_main<TAC_BF16>, kThreads, kLdsBytes));
+        for (int i = 0; i < 2; ++i) occ[i] = occ[i] < 1 ? 1 : occ[i];
     }
+    const unsigned grid = (unsigned)ctx->props_cu * (unsigned)occ[precision == TAC_BF16 ? 1 : 0];
     time_start(ctx, TAC_SLOT_ASSIGN);
     if (precision == TAC_FP32) {
         assign_main<TAC_FP32><<<grid, kThreads, kLdsBytes, s>>>(P);
@@ -759,9 +805,13 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
         TAC_LAUNCH_CHECK("assign_main<bf16>");
     }
     time_stop(ctx, TAC_SLOT_ASSIGN);
-    assign_fallback<<<(unsigned)ctx->props_cu * 4, 256, 0, s>>>(x_d, rowmap, cent_off_d, C_d, P.fb, ctx->counters,
-                                                                 assign_d, dist);
-    TAC_LAUNCH_CHECK("assign_fallback");
+    unsigned long long* slot = ws_at<unsigned long long>(ctx, o_slot);
+    fb_init<<<(unsigned)ctx->props_cu, 256, 0, s>>>(ctx->counters, slot);
+    TAC_LAUNCH_CHECK("fb_init");
+    fb_scan<<<(unsigned)ctx->props_cu * 4, 256, 0, s>>>(x_d, rowmap, cent_off_d, C_d, P.fb, ctx->counters, slot);
+    TAC_LAUNCH_CHECK("fb_scan");
+    fb_final<<<(unsigned)ctx->props_cu, 256, 0, s>>>(rowmap, P.fb, ctx->counters, slot, assign_d, dist);
+    TAC_LAUNCH_CHECK("fb_final");
     if (inertia_d) {
         double* part = ws_at<double>(ctx, o_red);
         if (nred > 0) {

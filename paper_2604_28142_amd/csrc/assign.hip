@@ -275,39 +275,40 @@ __device__ __forceinline__ void screen_item(const Params& P, int32_t j, int64_t 
     float* stage_cn = reinterpret_cast<float*>(lds + 2 * kStage * kRowWords);  // [2][kStage]
 
     Frag<PREC> F;
-    int64_t rowv[kNB];
     float xxmax = 0.f;
 #pragma unroll
     for (int nb = 0; nb < kNB; ++nb) {
+        __builtin_amdgcn_sched_barrier(0);  // convert one column block at a time (bounded live registers)
         const int64_t v = row0 + nb * 16 + col;
-        rowv[nb] = v;
         const bool valid = v < s1;
         const int64_t r = valid ? (P.rowmap ? (int64_t)P.rowmap[v] : v) : 0;
         const float4* xv = reinterpret_cast<const float4*>(P.x + r * kDim + 32 * g);
-        float xs[32];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const float4 a = valid ? xv[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-            xs[4 * q + 0] = a.x;
-            xs[4 * q + 1] = a.y;
-            xs[4 * q + 2] = a.z;
-            xs[4 * q + 3] = a.w;
-        }
         float xx = 0.f;
+        if constexpr (PREC == TAC_FP32) {
 #pragma unroll
-        for (int i = 0; i < 32; ++i) xx += xs[i] * xs[i];
+            for (int q = 0; q < 8; ++q) {
+                const float4 a = valid ? xv[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+                xx += a.x * a.x + a.y * a.y + a.z * a.z + a.w * a.w;
+                F.x[nb][4 * q + 0] = -2.0f * a.x;
+                F.x[nb][4 * q + 1] = -2.0f * a.y;
+                F.x[nb][4 * q + 2] = -2.0f * a.z;
+                F.x[nb][4 * q + 3] = -2.0f * a.w;
+            }
+        } else {
+            // eight coordinates at a time straight into the hi/lo fragments
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const float4 a = valid ? xv[2 * s] : make_float4(0.f, 0.f, 0.f, 0.f);
+                const float4 b = valid ? xv[2 * s + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+                xx += a.x * a.x + a.y * a.y + a.z * a.z + a.w * a.w + b.x * b.x + b.y * b.y + b.z * b.z + b.w * b.w;
+                const float v8[8] = {-2.0f * a.x, -2.0f * a.y, -2.0f * a.z, -2.0f * a.w,
+                                     -2.0f * b.x, -2.0f * b.y, -2.0f * b.z, -2.0f * b.w};
+                split_bf8(v8, F.xh[nb][s], F.xl[nb][s]);
+            }
+        }
         xx += __shfl_xor(xx, 16);
         xx += __shfl_xor(xx, 32);
         xxmax = fmaxf(xxmax, xx);
-        if constexpr (PREC == TAC_FP32) {
-#pragma unroll
-            for (int i = 0; i < 32; ++i) F.x[nb][i] = -2.0f * xs[i];
-        } else {
-#pragma unroll
-            for (int i = 0; i < 32; ++i) xs[i] = -2.0f * xs[i];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) split_bf8(xs + 8 * s, F.xh[nb][s], F.xl[nb][s]);
-        }
     }
     // One shift for the whole wave makes every screen value positive:
     // beta >= ||x||^2 + (screen error) for each of its rows, so that
@@ -470,7 +471,7 @@ __device__ __forceinline__ void screen_item(const Params& P, int32_t j, int64_t 
 #pragma unroll
             for (int e = 0; e < 4; ++e) glist_insert(G, I, pt[e], pi[e], true);
         }
-        const int64_t v = rowv[nb];
+        const int64_t v = row0 + nb * 16 + col;
         const bool valid = v < s1;
         const int64_t r = valid ? (P.rowmap ? (int64_t)P.rowmap[v] : v) : 0;
         const int nom = g == 0 ? I[0] : g == 1 ? I[1] : g == 2 ? I[2] : I[3];

@@ -18,6 +18,7 @@ namespace {
 
 constexpr int kDsub = 4;
 constexpr int kMaxCodebookFloats = 32 * 256 * kDsub;
+constexpr size_t kMaxCodebookLds = (size_t)32 * 256 * (kDsub + 1) * sizeof(float);  // codes + norms
 
 // Canonical residual of one row: r_i = x_i - c_i, rho = sqrt(sum r_i * r_i), each op rounded.
 __device__ __forceinline__ float residual_norm(const float* __restrict__ x, const float* __restrict__ c) {
@@ -35,22 +36,95 @@ __device__ __forceinline__ float residual_norm(const float* __restrict__ x, cons
     return sqrtf(acc);  // correctly rounded (HIP default for sqrtf); __fsqrt_rn may map to the native approximation
 }
 
-__device__ __forceinline__ int nearest_code(const float4 u, const float4* __restrict__ cb, int ksub) {
+// Canonical 4-d distance: t = u_i - b_i, acc = acc + t * t, each op rounded, no fusion.
+__device__ __forceinline__ float dist4(const float4 u, const float4 b) {
+    float t = __fsub_rn(u.x, b.x);
+    float acc = __fmul_rn(t, t);
+    t = __fsub_rn(u.y, b.y);
+    acc = __fadd_rn(acc, __fmul_rn(t, t));
+    t = __fsub_rn(u.z, b.z);
+    acc = __fadd_rn(acc, __fmul_rn(t, t));
+    t = __fsub_rn(u.w, b.w);
+    return __fadd_rn(acc, __fmul_rn(t, t));
+}
+
+__device__ __forceinline__ unsigned med3u(unsigned a, unsigned b, unsigned c) {
+    unsigned r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// Canonical argmin over the ksub codes (LDS cb / cn = squared norms) of one 4-d
+// subvector u, lowest code on ties.  A fused-FMA screen ||b||^2 + beta - 2 u.b,
+// shifted by beta >= ||u||^2 + margin so that it is positive, keeps a top-2 of
+// keys (screen bits with the code in the low 8 bits: one min and one med3 per
+// code); both nominees are rescored with the canonical distance, and a rigorous
+// bound on the screen error shows that no other code can win.  If it cannot,
+// the lane scans every code with the canonical distance.
+__device__ __forceinline__ int code_argmin(const float4 u, const float4* cb, const float* cn, int ksub, float cnmax) {
+    const float uu = u.x * u.x + u.y * u.y + u.z * u.z + u.w * u.w;
+    const float beta = uu * (1.0f + 0.00390625f) + 0.00390625f * cnmax + 1e-30f;
+    const float m0 = -2.0f * u.x, m1 = -2.0f * u.y, m2 = -2.0f * u.z, m3 = -2.0f * u.w;
+    unsigned k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu;
+#pragma unroll 8
+    for (int b = 0; b < ksub; ++b) {
+        const float4 v = cb[b];
+        float t = cn[b] + beta;
+        t = fmaf(m0, v.x, t);
+        t = fmaf(m1, v.y, t);
+        t = fmaf(m2, v.z, t);
+        t = fmaf(m3, v.w, t);
+        const unsigned key = (__float_as_uint(t) & ~0xFFu) | (unsigned)b;
+        k2 = med3u(k1, k2, key);
+        k1 = min(k1, key);
+    }
+    const int n1 = (int)(k1 & 0xFFu);
+    const float d1 = dist4(u, cb[n1]);
+    if (ksub == 1) return n1;
+    const int n2 = (int)(k2 & 0xFFu);
+    const float d2 = dist4(u, cb[n2]);
+    const bool second = d2 < d1 || (d2 == d1 && n2 < n1);
+    const int win = second ? n2 : n1;
+    const float dw = second ? d2 : d1;
+    if (ksub == 2) return win;
+    // every other code has screen >= tau (its key is >= k2, and truncation only lowers tau)
+    const double uc = 5.9604644775390625e-8;  // 2^-24
+    const double g6 = 6.0 * uc / (1.0 - 6.0 * uc);
+    float ucan = __fmul_rn(u.x, u.x);
+    ucan = __fadd_rn(ucan, __fmul_rn(u.y, u.y));
+    ucan = __fadd_rn(ucan, __fmul_rn(u.z, u.z));
+    ucan = __fadd_rn(ucan, __fmul_rn(u.w, u.w));
+    const double tau = (double)__uint_as_float(k2 & ~0xFFu);
+    const double un = sqrt((double)ucan * (1.0 + g6));
+    const double bt = (double)beta, cm2 = (double)cnmax * (1.0 + 1e-5);
+    const double E = 1.1 * g6 * (2.0 * (cm2 + bt) + 2.0 * un * sqrt(cm2)) + 1e-30;
+    const double L = (tau - E - bt + (double)ucan * (1.0 - g6)) * (1.0 - g6);
+    if (L > (double)dw) return win;
     float best = INFINITY;
     int bi = 0;
     for (int b = 0; b < ksub; ++b) {
-        const float4 v = cb[b];
-        float t, acc;
-        t = __fsub_rn(u.x, v.x); acc = __fmul_rn(t, t);
-        t = __fsub_rn(u.y, v.y); acc = __fadd_rn(acc, __fmul_rn(t, t));
-        t = __fsub_rn(u.z, v.z); acc = __fadd_rn(acc, __fmul_rn(t, t));
-        t = __fsub_rn(u.w, v.w); acc = __fadd_rn(acc, __fmul_rn(t, t));
-        if (acc < best) {
-            best = acc;
+        const float d = dist4(u, cb[b]);
+        if (d < best) {
+            best = d;
             bi = b;
         }
     }
     return bi;
+}
+
+// Codebooks (float4 per code) and their squared norms into LDS; returns the max norm^2.
+__device__ float load_codebooks_norms(const float* __restrict__ cbg, int M, int ksub, float4* lcb, float* lcn) {
+    const int n = M * ksub;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const float4 v = reinterpret_cast<const float4*>(cbg)[i];
+        lcb[i] = v;
+        lcn[i] = v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w;
+    }
+    __syncthreads();
+    float mx = 0.f;
+    for (int i = threadIdx.x & 63; i < n; i += 64) mx = fmaxf(mx, lcn[i]);
+    for (int m = 32; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
+    return mx;
 }
 
 __global__ void __launch_bounds__(256) residuals_kernel(const float* __restrict__ x, const int32_t* __restrict__ assign,
@@ -92,25 +166,21 @@ __global__ void __launch_bounds__(256) residuals_kernel(const float* __restrict_
     }
 }
 
-__device__ void load_codebooks(const float* __restrict__ cb, int M, int ksub, float* lds) {
-    const int nf4 = M * ksub;  // float4 entries
-    for (int i = threadIdx.x; i < nf4; i += blockDim.x)
-        reinterpret_cast<float4*>(lds)[i] = reinterpret_cast<const float4*>(cb)[i];
-    __syncthreads();
-}
-
-// Fused residual + normalisation + encoding, one row per thread.
-__global__ void __launch_bounds__(256) encode_kernel(const float* __restrict__ x, const int32_t* __restrict__ assign,
+// Fused residual + normalisation + encoding, one row per thread; codebooks and
+// their norms resident in LDS (32 x 256 x 16 B + 32 x 256 x 4 B = 160 KiB).
+__global__ void __launch_bounds__(512) encode_kernel(const float* __restrict__ x, const int32_t* __restrict__ assign,
                                                      const float* __restrict__ C, int64_t K, int64_t n, int normalize,
                                                      const float* __restrict__ cb, int M, int ksub,
                                                      uint8_t* __restrict__ codes, float* __restrict__ rnorm) {
-    extern __shared__ float lcb[];
-    load_codebooks(cb, M, ksub, lcb);
+    extern __shared__ float4 lds4[];
+    float4* lcb = lds4;
+    float* lcn = reinterpret_cast<float*>(lds4 + M * ksub);
+    const float cnmax = load_codebooks_norms(cb, M, ksub, lcb, lcn);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t a = assign[i];
-        uint8_t* out = codes + i * M;
+        uint32_t* out = reinterpret_cast<uint32_t*>(codes + i * M);
         if (a < 0 || a >= K) {
-            for (int m = 0; m < M; ++m) out[m] = 0;
+            for (int m = 0; m < M / 4; ++m) out[m] = 0u;
             if (rnorm) rnorm[i] = 0.f;
             continue;
         }
@@ -118,6 +188,7 @@ __global__ void __launch_bounds__(256) encode_kernel(const float* __restrict__ x
         const float* cr = C + (int64_t)a * kDim;
         const float rho = residual_norm(xr, cr);
         const bool scale = normalize && rho > 0.f;
+        uint32_t word = 0;
         for (int m = 0; m < M; ++m) {
             const float4 xa = reinterpret_cast<const float4*>(xr)[m];
             const float4 cv = reinterpret_cast<const float4*>(cr)[m];
@@ -134,22 +205,29 @@ __global__ void __launch_bounds__(256) encode_kernel(const float* __restrict__ x
             } else if (normalize) {
                 u = make_float4(0.f, 0.f, 0.f, 0.f);
             }
-            out[m] = (uint8_t)nearest_code(u, reinterpret_cast<const float4*>(lcb) + m * ksub, ksub);
+            const unsigned c = (unsigned)code_argmin(u, lcb + m * ksub, lcn + m * ksub, ksub, cnmax);
+            word |= c << (8 * (m & 3));
+            if ((m & 3) == 3) {
+                out[m >> 2] = word;
+                word = 0;
+            }
         }
         if (rnorm) rnorm[i] = rho;
     }
 }
 
 // Codes of training rows R (already normalised residuals), one row per thread.
-__global__ void __launch_bounds__(256) train_encode(const float* __restrict__ R, int64_t n,
+__global__ void __launch_bounds__(512) train_encode(const float* __restrict__ R, int64_t n,
                                                     const float* __restrict__ cb, int M, int ksub,
                                                     uint32_t* __restrict__ codes /* [M][n] */) {
-    extern __shared__ float lcb[];
-    load_codebooks(cb, M, ksub, lcb);
+    extern __shared__ float4 lds4[];
+    float4* lcb = lds4;
+    float* lcn = reinterpret_cast<float*>(lds4 + M * ksub);
+    const float cnmax = load_codebooks_norms(cb, M, ksub, lcb, lcn);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         for (int m = 0; m < M; ++m) {
             const float4 u = reinterpret_cast<const float4*>(R + i * kDim)[m];
-            codes[(int64_t)m * n + i] = (uint32_t)nearest_code(u, reinterpret_cast<const float4*>(lcb) + m * ksub, ksub);
+            codes[(int64_t)m * n + i] = (uint32_t)code_argmin(u, lcb + m * ksub, lcn + m * ksub, ksub, cnmax);
         }
     }
 }
@@ -247,15 +325,15 @@ extern "C" tac_status pq_encode(tac_ctx ctx, const float* x_d, const int32_t* as
     if (!x_d || !assign_d || !codebooks_d || !codes_d || (K > 0 && !C_d))
         return set_error(TAC_E_INVAL, "pq_encode: NULL pointer");
     TAC_HIP(hipSetDevice(ctx->device));
-    const size_t lds = (size_t)M * ksub * kDsub * sizeof(float);
+    const size_t lds = (size_t)M * ksub * (kDsub + 1) * sizeof(float);
     if (!g_attr_encode) {
         TAC_HIP(hipFuncSetAttribute((const void*)encode_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(kMaxCodebookFloats * sizeof(float))));
+                                    (int)kMaxCodebookLds));
         g_attr_encode = true;
     }
-    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, (int64_t)ctx->props_cu * 4);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 511) / 512, (int64_t)ctx->props_cu));
     time_start(ctx, TAC_SLOT_ENCODE);
-    encode_kernel<<<grid, 256, lds, ctx->stream>>>(x_d, assign_d, C_d, K, n, normalize, codebooks_d, M, ksub, codes_d,
+    encode_kernel<<<grid, 512, lds, ctx->stream>>>(x_d, assign_d, C_d, K, n, normalize, codebooks_d, M, ksub, codes_d,
                                                    rnorm_d);
     TAC_LAUNCH_CHECK("encode_kernel");
     time_stop(ctx, TAC_SLOT_ENCODE);
@@ -291,13 +369,14 @@ extern "C" tac_status pq_train(tac_ctx ctx, const float* R_d, int64_t n, int32_t
         TAC_HIP(hipMemcpyAsync(codebooks_d, init_d, cb_bytes, hipMemcpyDeviceToDevice, s));
     if (!g_attr_train) {
         TAC_HIP(hipFuncSetAttribute((const void*)train_encode, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(kMaxCodebookFloats * sizeof(float))));
+                                    (int)kMaxCodebookLds));
         g_attr_train = true;
     }
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, (int64_t)ctx->props_cu * 4));
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 511) / 512, (int64_t)ctx->props_cu));
+    const size_t lds = (size_t)M * ksub * (kDsub + 1) * sizeof(float);
     for (int it = 0; it < iters && n > 0; ++it) {
         TAC_HIP(hipMemcpyAsync(cur, codebooks_d, cb_bytes, hipMemcpyDeviceToDevice, s));
-        train_encode<<<grid, 256, cb_bytes, s>>>(R_d, n, cur, M, ksub, codes);
+        train_encode<<<grid, 512, lds, s>>>(R_d, n, cur, M, ksub, codes);
         TAC_LAUNCH_CHECK("train_encode");
         for (int m = 0; m < M; ++m) {
             uint32_t* keys = codes + (int64_t)m * n;  // sorted in place (ping-pong with k1)

@@ -67,6 +67,41 @@ def cpu_baseline(x, tok, w, sample_rows: int, seed: int = 0):
                       f"against their tokens' initial centroids ({dt:.1f}s on {threads} threads)"}
 
 
+def serve_bench(idx, w, requests: int, seed: int = 0):
+    """Encode service against the resident index: saturated throughput, then
+    Poisson arrivals at 0.3 / 0.6 / 0.9 of it (first 5% of requests discarded)."""
+    import datagen
+    from paper_2604_28142_amd.serve import EncodeService, GpuExecutor, ResidentIndex, run_load
+
+    index = ResidentIndex(T=idx.T, K=idx.K, C=idx.C, cent_off=idx.cent_off, codebooks=idx.codebooks)
+    ex = GpuExecutor(index, n_slots=3, max_rows=512 * 180)
+    svc = EncodeService(ex, max_docs=512)
+    lens, x, tok = datagen.serving_docs(w, requests, seed=seed + 20)
+    edges = np.concatenate([[0], np.cumsum(lens)])
+    docs = [(x[edges[i]:edges[i + 1]], tok[edges[i]:edges[i + 1]]) for i in range(len(lens))]
+    run_load(svc, docs[:2000], None)                      # warm-up (workspaces, kernels)
+    nsat = min(len(docs), 10_000)
+    _, wall = run_load(svc, docs[:nsat], None)
+    r_sat = nsat / wall
+    log(f"serve: saturated {r_sat:.0f} docs/s")
+    out = {"index": f"{w.name}: K={w.k} centroids, PQ 32x256", "requests_per_rate": requests,
+           "docs_mean_vectors": float(lens.mean()), "saturated_docs_per_s": r_sat, "rates": []}
+    for f in (0.3, 0.6, 0.9):
+        rate = f * r_sat
+        arr = datagen.poisson_arrivals(rate, len(docs), seed=seed + int(f * 10))
+        res, wall = run_load(svc, docs, arr)
+        skip = len(docs) // 20
+        lat = np.array([r.latency for r in res[skip:]])
+        vec = float(lens[skip:].sum())
+        out["rates"].append({"docs_per_s": rate, "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                             "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                             "vectors_per_s": vec / (wall * (len(docs) - skip) / len(docs))})
+        log(f"serve: rate {rate:.0f}/s p50 {out['rates'][-1]['p50_ms']:.2f} ms p99 {out['rates'][-1]['p99_ms']:.2f} ms")
+    svc.close()
+    ex.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +112,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=50_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=20_000)
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
@@ -202,6 +239,9 @@ def main():
     extra["mfma_executed_tflops_bf16x3"] = 3 * achieved
     if "fp32" in kms:
         extra["fp32_roofline_frac"] = F / (kms["fp32"] / 1e3) / 1e12 / PEAK["fp32"]
+
+    if not args.no_serve:
+        extra["encode_service"] = serve_bench(idx, w, args.serve_requests)
 
     cpu = None
     if not args.no_cpu_baseline:

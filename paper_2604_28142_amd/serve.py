@@ -1,0 +1,304 @@
+"""Encode service: assigns and PQ-encodes newly arriving documents against a
+resident token-aware index (centroids, centroid offsets and PQ codebooks stay
+in HBM).
+
+Continuous batching.  A scheduler thread admits waiting requests into the next
+batch while the earlier batches are still on the GPU: a batch is formed as soon
+as a stream slot is free, from every admitted request that fits (at most
+`max_docs` documents and `max_rows` vectors), and a byte ledger bounds the
+staging memory held by batches in flight -- a request that does not fit waits,
+it is never dropped.  Each slot owns a libtac context on its own HIP stream and
+pinned staging buffers, so the copies and kernels of consecutive batches
+overlap.  A completion thread waits for batches in launch order, splits their
+outputs per document and resolves the futures.
+
+Every output row is the canonical argmin for that row alone (assignment and
+PQ codes), so a document's result is bitwise the same alone or in any batch.
+A document with a token that has no centroid (or an id outside [0, T)) fails
+on its own with TacError(TAC_E_UNSEEN_TOKEN); the rest of its batch succeeds.
+"""
+from __future__ import annotations
+
+import queue
+import threading
+import time
+from concurrent.futures import Future
+from dataclasses import dataclass, field
+
+import numpy as np
+
+ROW_BYTES = 128 * 4 + 4 + 4 + 32 + 4   # staged per vector: x, token, assignment, codes, norm
+
+
+@dataclass
+class ResidentIndex:
+    """What the service keeps in HBM: centroids [K, 128], centroid offsets
+    [T + 1] and PQ codebooks [M, 256, 4] (torch tensors on the GPU)."""
+    T: int
+    K: int
+    C: object
+    cent_off: object
+    codebooks: object
+
+
+@dataclass
+class Request:
+    x: np.ndarray            # float32[n_d, 128]
+    tok: np.ndarray          # int32[n_d]
+    future: Future
+    t_arrival: float
+    t_done: float = 0.0
+    rid: int = 0
+
+
+@dataclass
+class Result:
+    assign: np.ndarray       # int32[n_d]: global centroid id
+    codes: np.ndarray        # uint8[n_d, M]
+    rnorm: np.ndarray        # float32[n_d]: residual norm
+    latency: float = 0.0     # seconds from submit to completion
+
+
+@dataclass
+class ServiceStats:
+    latencies: list = field(default_factory=list)     # seconds, per completed request
+    batches: int = 0
+    docs: int = 0
+    vectors: int = 0
+    failed: int = 0
+    batch_sizes: list = field(default_factory=list)
+
+    def percentile(self, q: float) -> float:
+        return float(np.percentile(np.asarray(self.latencies), q)) if self.latencies else float("nan")
+
+
+class GpuExecutor:
+    """Runs batches on the GPU through libtac; one context, stream and set of
+    staging buffers per slot."""
+
+    def __init__(self, index, n_slots: int = 3, max_rows: int = 512 * 180, device: int = 0,
+                 precision: int | None = None):
+        import torch
+
+        from . import _lib as L
+        self.L, self.torch = L, torch
+        self.index = index
+        self.n_slots = n_slots
+        self.max_rows = max_rows
+        self.precision = L.TAC_BF16 if precision is None else precision
+        dev = torch.device("cuda", device)
+        M = index.codebooks.shape[0]
+        self.M = M
+        self.slots = []
+        for _ in range(n_slots):
+            s = torch.cuda.Stream(device=dev)
+            ctx = L.Context(device, stream=s)
+            self.slots.append(dict(
+                stream=s, ctx=ctx, event=torch.cuda.Event(),
+                x_h=torch.empty((max_rows, 128), dtype=torch.float32, pin_memory=True),
+                tok_h=torch.empty(max_rows, dtype=torch.int32, pin_memory=True),
+                a_h=torch.empty(max_rows, dtype=torch.int32, pin_memory=True),
+                c_h=torch.empty((max_rows, M), dtype=torch.uint8, pin_memory=True),
+                r_h=torch.empty(max_rows, dtype=torch.float32, pin_memory=True),
+                x_d=torch.empty((max_rows, 128), dtype=torch.float32, device=dev),
+                tok_d=torch.empty(max_rows, dtype=torch.int32, device=dev),
+                a_d=torch.empty(max_rows, dtype=torch.int32, device=dev),
+                dist_d=torch.empty(max_rows, dtype=torch.float32, device=dev),
+                c_d=torch.empty((max_rows, M), dtype=torch.uint8, device=dev),
+                r_d=torch.empty(max_rows, dtype=torch.float32, device=dev)))
+
+    def launch(self, slot: int, xs: list, toks: list) -> int:
+        """Stage the rows of a batch into the slot's pinned buffers and enqueue
+        copy-in, assignment, PQ encoding and copy-out on the slot's stream."""
+        S = self.slots[slot]
+        n = 0
+        xh, th = S["x_h"].numpy(), S["tok_h"].numpy()
+        for x, t in zip(xs, toks):
+            k = x.shape[0]
+            xh[n:n + k] = x
+            th[n:n + k] = t
+            n += k
+        torch, L, ix = self.torch, self.L, self.index
+        with torch.cuda.stream(S["stream"]):
+            S["x_d"][:n].copy_(S["x_h"][:n], non_blocking=True)
+            S["tok_d"][:n].copy_(S["tok_h"][:n], non_blocking=True)
+            L.tac_assign(S["ctx"], S["x_d"][:n], ix.C, ix.cent_off, S["a_d"][:n], tok=S["tok_d"][:n],
+                         precision=self.precision, dist=S["dist_d"][:n])
+            L.pq_encode(S["ctx"], S["x_d"][:n], S["a_d"][:n], ix.C, ix.codebooks, S["c_d"][:n],
+                        rnorm=S["r_d"][:n])
+            S["a_h"][:n].copy_(S["a_d"][:n], non_blocking=True)
+            S["c_h"][:n].copy_(S["c_d"][:n], non_blocking=True)
+            S["r_h"][:n].copy_(S["r_d"][:n], non_blocking=True)
+            S["event"].record(S["stream"])
+        return n
+
+    def wait(self, slot: int, n: int):
+        S = self.slots[slot]
+        S["event"].synchronize()
+        return S["a_h"].numpy()[:n], S["c_h"].numpy()[:n], S["r_h"].numpy()[:n]
+
+    def close(self):
+        for S in self.slots:
+            S["ctx"].close()
+
+
+class EncodeService:
+    """Continuous-batching encode service over an executor (GpuExecutor, or a
+    stand-in with the same launch / wait interface)."""
+
+    def __init__(self, executor, max_docs: int = 512, ledger_bytes: int | None = None, idle_wait: float = 0.0005):
+        self.ex = executor
+        self.n_slots = executor.n_slots
+        self.max_docs = max_docs
+        self.max_rows = executor.max_rows
+        self.ledger_cap = ledger_bytes if ledger_bytes is not None else self.n_slots * self.max_rows * ROW_BYTES
+        self.ledger_used = 0
+        self.idle_wait = idle_wait
+        self.stats = ServiceStats()
+        self._in = queue.Queue()
+        self._pending: list[Request] = []
+        self._free = list(range(self.n_slots))
+        self._inflight = queue.Queue()
+        self._lock = threading.Condition()
+        self._stop = False
+        self._next_id = 0
+        self._sched = threading.Thread(target=self._schedule, name="tac-scheduler", daemon=True)
+        self._done = threading.Thread(target=self._complete, name="tac-completion", daemon=True)
+        self._sched.start()
+        self._done.start()
+
+    # ---- public -------------------------------------------------------------
+    def submit(self, x: np.ndarray, tok: np.ndarray) -> Future:
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        tok = np.ascontiguousarray(tok, dtype=np.int32)
+        if x.ndim != 2 or x.shape[1] != 128 or tok.shape != (x.shape[0],):
+            raise ValueError("a document is x float32[n, 128] with tok int32[n]")
+        if x.shape[0] > self.max_rows or x.shape[0] == 0 or x.shape[0] * ROW_BYTES > self.ledger_cap:
+            raise ValueError(f"a document holds 1..{self.max_rows} vectors (and fits the memory ledger)")
+        f = Future()
+        r = Request(x, tok, f, time.perf_counter())
+        with self._lock:
+            r.rid = self._next_id
+            self._next_id += 1
+        self._in.put(r)
+        return f
+
+    def close(self):
+        with self._lock:
+            self._stop = True
+            self._lock.notify_all()
+        self._in.put(None)
+        self._sched.join()
+        self._inflight.put(None)
+        self._done.join()
+
+    # ---- scheduler ----------------------------------------------------------
+    def _take_arrivals(self, block: bool):
+        try:
+            r = self._in.get(timeout=self.idle_wait) if block else self._in.get_nowait()
+        except queue.Empty:
+            return
+        while r is not None:
+            self._pending.append(r)
+            try:
+                r = self._in.get_nowait()
+            except queue.Empty:
+                return
+
+    def _schedule(self):
+        while True:
+            with self._lock:
+                stop = self._stop
+            self._take_arrivals(block=not self._pending)
+            if stop and not self._pending and self._in.empty():
+                return
+            if not self._pending:
+                continue
+            with self._lock:
+                while not self._free and not self._stop:
+                    self._lock.wait()
+                if not self._free:
+                    continue
+                slot = self._free.pop(0)
+                # admit in arrival order while the batch and the ledger have room
+                batch, rows, nbytes = [], 0, 0
+                while self._pending and len(batch) < self.max_docs:
+                    r = self._pending[0]
+                    k = r.x.shape[0]
+                    b = k * ROW_BYTES
+                    if rows + k > self.max_rows or self.ledger_used + nbytes + b > self.ledger_cap:
+                        break
+                    batch.append(self._pending.pop(0))
+                    rows += k
+                    nbytes += b
+                if not batch:            # nothing fits until memory is released
+                    self._free.insert(0, slot)
+                    self._lock.wait()
+                    continue
+                self.ledger_used += nbytes
+            try:
+                n = self.ex.launch(slot, [r.x for r in batch], [r.tok for r in batch])
+                self._inflight.put((slot, batch, n, nbytes, None))
+            except Exception as e:  # the batch fails as a whole; the loop continues
+                self._inflight.put((slot, batch, 0, nbytes, e))
+
+    # ---- completion ---------------------------------------------------------
+    def _complete(self):
+        from ._lib import TAC_E_UNSEEN_TOKEN, TacError
+        while True:
+            item = self._inflight.get()
+            if item is None:
+                return
+            slot, batch, n, nbytes, err = item
+            if err is None:
+                try:
+                    a, c, rho = self.ex.wait(slot, n)
+                except Exception as e:
+                    err = e
+            now = time.perf_counter()
+            off = 0
+            for r in batch:
+                k = r.x.shape[0]
+                r.t_done = now
+                if err is not None:
+                    r.future.set_exception(err)
+                    self.stats.failed += 1
+                else:
+                    ra = a[off:off + k].copy()
+                    if np.any(ra < 0):
+                        r.future.set_exception(TacError(TAC_E_UNSEEN_TOKEN,
+                                                        "a token of this document has no centroid"))
+                        self.stats.failed += 1
+                    else:
+                        r.future.set_result(Result(ra, c[off:off + k].copy(), rho[off:off + k].copy(),
+                                                   now - r.t_arrival))
+                        self.stats.latencies.append(now - r.t_arrival)
+                off += k
+            self.stats.batches += 1
+            self.stats.docs += len(batch)
+            self.stats.vectors += off
+            self.stats.batch_sizes.append(len(batch))
+            with self._lock:
+                self.ledger_used -= nbytes
+                self._free.append(slot)
+                self._lock.notify_all()
+
+
+def run_load(service: EncodeService, docs: list, arrivals: np.ndarray | None):
+    """Submit documents at the given arrival times (seconds from now; None = all
+    at once) and wait for every result.  Returns (results, wall seconds)."""
+    t0 = time.perf_counter()
+    futs = []
+    for i, (x, t) in enumerate(docs):
+        if arrivals is not None:
+            delay = t0 + arrivals[i] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+        futs.append(service.submit(x, t))
+    out = []
+    for f in futs:
+        try:
+            out.append(f.result())
+        except Exception as e:  # failed documents are reported as their exception
+            out.append(e)
+    return out, time.perf_counter() - t0

@@ -1,0 +1,174 @@
+"""GPU edge cases through the C ABI: empty inputs, class boundaries of the
+assignment kernel, epoch flushes, forced certificate fallbacks, exact ties on
+dyadic inputs, the serving path's token grouping, and graph replay."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+
+from gpu_common import Case, check_assign, check_centroids, dev, host
+
+pytestmark = pytest.mark.gpu
+
+tac = pytest.importorskip("paper_2604_28142_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tac.Context(0)
+    yield c
+    c.close()
+
+
+def run_assign(ctx, xs, seg_off, C, cent_off, prec):
+    N = xs.shape[0]
+    a = torch.empty(max(N, 1), dtype=torch.int32, device="cuda")[:N]
+    d = torch.empty(max(N, 1), dtype=torch.float32, device="cuda")[:N]
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    tac.tac_assign(ctx, dev(xs), dev(C), dev(cent_off), a, seg_off=dev(seg_off), precision=prec, dist=d, inertia=J)
+    return host(a), host(d), float(host(J)[0])
+
+
+def clustered(rng, n, k, spread=0.05):
+    centres = rng.standard_normal((k, 128))
+    centres /= np.linalg.norm(centres, axis=1, keepdims=True)
+    x = centres[rng.integers(0, k, n)] + spread * rng.standard_normal((n, 128)) / np.sqrt(128)
+    return (x / np.linalg.norm(x, axis=1, keepdims=True)).astype(np.float32)
+
+
+def test_empty_inputs(ctx):
+    x = torch.empty((0, 128), dtype=torch.float32, device="cuda")
+    tok = torch.empty(0, dtype=torch.int32, device="cuda")
+    perm = torch.empty(0, dtype=torch.int32, device="cuda")
+    out = tac.tac_budget(ctx, x, tok, 5, 0, perm=perm)
+    assert out["kappa"].sum() == 0 and np.all(out["seg_off"] == 0)
+    with pytest.raises(tac.TacError):
+        tac.tac_budget(ctx, x, tok, 5, 3, perm=perm)          # infeasible: no vectors
+    a, d, J = run_assign(ctx, np.zeros((0, 128), np.float32), np.zeros(6, np.int64),
+                         np.zeros((2, 128), np.float32), np.array([0, 1, 1, 2, 2, 2]), tac.TAC_BF16)
+    assert a.shape == (0,) and J == 0.0
+
+
+@pytest.mark.parametrize("kappa", [1, 2, 4, 5, 16, 17, 63, 64, 65, 300])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_class_boundaries_and_ragged_tiles(ctx, kappa, prec):
+    rng = np.random.default_rng(kappa)
+    sizes = [kappa, 3 * kappa + 7, 513, 1030]        # ragged against 16-row blocks and 512-row tiles
+    xs = np.concatenate([clustered(rng, n, max(2, kappa // 2)) for n in sizes])
+    seg_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    picks = np.concatenate([rng.choice(n, kappa, replace=False) for n in sizes]).astype(np.int64)
+    cent_off = np.arange(len(sizes) + 1, dtype=np.int64) * kappa
+    C = np.concatenate([xs[seg_off[j] + picks[cent_off[j]:cent_off[j + 1]]] for j in range(len(sizes))])
+    a, d, J = run_assign(ctx, xs, seg_off, C, cent_off, prec)
+    ties, r64 = check_assign(xs, seg_off, C, cent_off, a, d)
+    assert abs(J - r64["J"]) <= 1e-5 * max(r64["J"], 1e-30)
+
+
+def test_heavy_token_epoch_flush(ctx):
+    """A token with 2,500 centroids spans three packed-index epochs."""
+    rng = np.random.default_rng(11)
+    xs = clustered(rng, 6000, 400, spread=0.3)
+    C = xs[rng.choice(6000, 2500, replace=False)].copy()
+    seg_off = np.array([0, 6000], np.int64)
+    cent_off = np.array([0, 2500], np.int64)
+    for prec in (0, 1):
+        a, d, J = run_assign(ctx, xs, seg_off, C, cent_off, prec)
+        check_assign(xs, seg_off, C, cent_off, a, d)
+
+
+def test_forced_certificate_fallback(ctx):
+    """Centroids nearly equidistant from every row defeat the screen's
+    certificate; the exhaustive canonical rescoring still returns the exact argmin."""
+    rng = np.random.default_rng(12)
+    k = 700
+    dirs = rng.standard_normal((k, 128))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    C = (dirs * (1.0 + 1e-7 * rng.standard_normal((k, 1)))).astype(np.float32)
+    xs = (1e-7 * rng.standard_normal((300, 128))).astype(np.float32)
+    seg_off = np.array([0, 300], np.int64)
+    cent_off = np.array([0, k], np.int64)
+    for prec in (0, 1):
+        a, d, J = run_assign(ctx, xs, seg_off, C, cent_off, prec)
+        assert tac.tac_assign_stats(ctx)["fallback"] > 0
+        check_assign(xs, seg_off, C, cent_off, a, d, fp64=False)
+
+
+def test_dyadic_exact_ties_bitwise(ctx):
+    """Dyadic 1-D values in coordinate 0 make every float operation exact, so
+    equal distances are exact ties; both paths break them to the lowest index
+    exactly as the oracle does."""
+    rng = np.random.default_rng(13)
+    toks = []
+    for j in range(12):
+        kc = [1, 2, 3, 5, 6, 8, 12, 20, 5, 7, 33, 2][j]
+        n = int(rng.integers(kc, 4 * kc + 10))
+        vals = rng.integers(-64, 65, n) / 8.0
+        cvals = rng.choice(np.arange(-64, 65, 2) / 8.0, kc, replace=False)   # midpoints on the grid
+        toks.append((vals, cvals))
+    xs = np.zeros((sum(len(v) for v, _ in toks), 128), np.float32)
+    C = np.zeros((sum(len(c) for _, c in toks), 128), np.float32)
+    xs[:, 0] = np.concatenate([v for v, _ in toks])
+    C[:, 0] = np.concatenate([c for _, c in toks])
+    seg_off = np.concatenate([[0], np.cumsum([len(v) for v, _ in toks])]).astype(np.int64)
+    cent_off = np.concatenate([[0], np.cumsum([len(c) for _, c in toks])]).astype(np.int64)
+    ref = oracle.assign(xs, seg_off, C, cent_off, decide="fp64")
+    for prec in (0, 1):
+        a, d, J = run_assign(ctx, xs, seg_off, C, cent_off, prec)
+        assert np.array_equal(a, ref["a"])
+        assert np.array_equal(d.astype(np.float64), ref["D"])
+        assert J == ref["J"]
+    Cn = torch.empty((C.shape[0], 128), dtype=torch.float32, device="cuda")
+    cnt = torch.empty(C.shape[0], dtype=torch.int64, device="cuda")
+    tac.tac_update(ctx, dev(xs), dev(seg_off), dev(ref["a"].astype(np.int32)), dev(C), Cn, cnt)
+    C1, cnt1 = oracle.update(xs, ref["a"], C)
+    assert np.array_equal(host(cnt), cnt1)
+    check_centroids(host(Cn), C1)
+
+
+def test_serving_path_groups_unsorted_rows(ctx):
+    """tac_assign with token ids (rows in any order) equals the sorted path;
+    ids outside [0, T) and tokens without centroids give -1."""
+    c = Case("small")
+    rng = np.random.default_rng(14)
+    idx = rng.permutation(c.x.shape[0])[:5000]
+    x, t = c.x[idx].copy(), c.tok[idx].copy()
+    t[:7] = c.T + 3                                    # invalid ids
+    a = torch.empty(x.shape[0], dtype=torch.int32, device="cuda")
+    d = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
+    for prec in (0, 1):
+        tac.tac_assign(ctx, dev(x), dev(c.C0), dev(c.cent_off), a, tok=dev(t), precision=prec, dist=d)
+        ga = host(a)
+        assert np.all(ga[:7] == -1)
+        assert tac.tac_assign_stats(ctx)["unassigned"] >= 7
+        keep = np.arange(7, x.shape[0])
+        perm, seg_off, _ = oracle.group_by_token(t[keep], c.T)
+        ref = oracle.assign(x[keep][perm], seg_off, c.C0, c.cent_off, decide="fp32")
+        exp = np.empty(keep.shape[0], np.int64)
+        exp[perm] = ref["a"]
+        assert np.array_equal(ga[keep], exp)
+
+
+def test_graph_replay_equals_eager(ctx):
+    from paper_2604_28142_amd import index as IX
+    c = Case("small")
+    d = c.device()
+    ix = IX.Index(T=c.T, K=c.K, xs=d["xs"], perm=dev(c.perm.astype(np.int32)), seg_off=d["seg_off"],
+                  cent_off=d["cent_off"], C=dev(c.C0))
+    C0 = ix.C.clone()
+    loop = IX.LloydLoop(ctx, ix, iters=3, precision=tac.TAC_BF16)
+    loop.run()
+    torch.cuda.synchronize()
+    C_eager, a_eager, J_eager = ix.C.clone(), loop.assign.clone(), loop.inertia.clone()
+    ix.C.copy_(C0)
+    loop.capture()
+    for rep in range(3):
+        ix.C.copy_(C0)
+        loop.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ix.C, C_eager), rep
+        assert torch.equal(loop.assign, a_eager), rep
+        assert torch.equal(loop.inertia, J_eager), rep
+        # eager work between replays
+        run_assign(ctx, c.xs, c.seg_off, c.C0, c.cent_off, tac.TAC_FP32)

@@ -1,0 +1,89 @@
+"""GPU tests of the encode service: results equal the oracle's, are bitwise the
+same alone and in a mixed batch, and unseen tokens fail only their document."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+
+from gpu_common import Case, dev
+
+pytestmark = pytest.mark.gpu
+
+tac = pytest.importorskip("paper_2604_28142_amd")
+from paper_2604_28142_amd.serve import EncodeService, GpuExecutor, ResidentIndex, run_load  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def served():
+    c = Case("small")
+    a = oracle.assign(c.xs, c.seg_off, c.C0, c.cent_off, decide="fp32")["a"]
+    u32, _ = oracle.residuals(c.xs, c.C0[a], mode="fp32")
+    sample = datagen.pq_sample(u32.shape[0], 20_000, 0)
+    cb = oracle.pq_train(u32[sample], 32, 256, 3, datagen.pq_init_rows(sample.shape[0], 256, 0), decide="fp32")
+    index = ResidentIndex(T=c.T, K=c.K, C=dev(c.C0), cent_off=dev(c.cent_off), codebooks=dev(cb))
+    lens, x, tok = datagen.serving_docs("small", 400, seed=3)
+    edges = np.concatenate([[0], np.cumsum(lens)])
+    docs = [(x[edges[i]:edges[i + 1]], tok[edges[i]:edges[i + 1]]) for i in range(len(lens))]
+    ex = GpuExecutor(index, n_slots=3, max_rows=64 * 180)
+    svc = EncodeService(ex, max_docs=64)
+    yield c, cb, docs, svc
+    svc.close()
+    ex.close()
+
+
+def _expected(c, cb, x, t):
+    perm, seg_off, _ = oracle.group_by_token(t, c.T)
+    r = oracle.assign(x[perm], seg_off, c.C0, c.cent_off, decide="fp32")
+    a = np.empty_like(r["a"])
+    a[perm] = r["a"]
+    u, rho = oracle.residuals(x, c.C0[a], mode="fp32")
+    return a, oracle.pq_encode(u, cb, decide="fp32"), rho
+
+
+def test_service_matches_oracle_and_isolates_unseen(served):
+    c, cb, docs, svc = served
+    present = c.kappa > 0
+    res, wall = run_load(svc, docs, None)
+    n_fail = 0
+    for (x, t), r in zip(docs, res):
+        if not np.all(present[t]):
+            assert isinstance(r, tac.TacError)
+            n_fail += 1
+            continue
+        a, codes, rho = _expected(c, cb, x, t)
+        assert np.array_equal(r.assign, a)
+        assert np.array_equal(r.codes, codes)
+        assert np.array_equal(r.rnorm, rho)
+    assert svc.stats.docs >= len(docs)
+    # a document with an id outside [0, T) fails on its own
+    x, t = docs[0]
+    bad = t.copy()
+    bad[0] = c.T
+    with pytest.raises(tac.TacError):
+        svc.submit(x, bad).result()
+    assert not isinstance(svc.submit(x, t).result(), Exception)
+
+
+def test_alone_equals_in_the_mix(served):
+    c, cb, docs, svc = served
+    present = c.kappa > 0
+    ok = [i for i, (x, t) in enumerate(docs) if np.all(present[t])][:200]
+    mixed, _ = run_load(svc, [docs[i] for i in ok], None)
+    for k, i in enumerate(ok):
+        alone = svc.submit(*docs[i]).result()
+        assert np.array_equal(alone.assign, mixed[k].assign)
+        assert np.array_equal(alone.codes, mixed[k].codes)
+        assert np.array_equal(alone.rnorm, mixed[k].rnorm)
+
+
+def test_poisson_load_reports_latency(served):
+    c, cb, docs, svc = served
+    present = c.kappa > 0
+    ok = [d for d in docs if np.all(present[d[1]])][:300]
+    before = len(svc.stats.latencies)
+    res, wall = run_load(svc, ok, datagen.poisson_arrivals(2000.0, len(ok), seed=1))
+    lat = np.asarray(svc.stats.latencies[before:])
+    assert lat.shape[0] == len(ok)
+    assert np.all(lat > 0) and np.percentile(lat, 99) < wall

@@ -37,6 +37,35 @@ WORKLOAD_TEXT = {
 }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assign_main_bf16_c1_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_28142_amd", "csrc", f) for f in ("assign.hip", "tac_internal.h")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(config: str):
+    """HBM bytes per launch of the BF16 assignment kernel from the committed counter
+    summary, or None when it was taken on another workload or an older kernel source."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = dict(ln.split(":", 1) for ln in text.splitlines() if ln.startswith(("traffic_bytes_per_launch:",
+                                                                              "kernel_source_sha1:", "workload:")))
+    if vals.get("kernel_source_sha1", "").strip() != kernel_source_hash():
+        return None
+    if vals.get("workload", "").strip() != config:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -109,11 +138,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c1", choices=["c0", "c1", "c3"])
     ap.add_argument("--iters", type=int, default=10)
-    ap.add_argument("--cpu-sample", type=int, default=50_000)
+    ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=20_000)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="first run one plain 1 GiB device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
@@ -124,6 +156,7 @@ def main():
 
     import datagen
     import paper_2604_28142_amd as tac
+    from paper_2604_28142_amd import autotune
     from paper_2604_28142_amd import index as IX
 
     w = datagen.WORKLOADS[args.config]
@@ -136,6 +169,12 @@ def main():
     tok = torch.from_numpy(tok_h).to(dev)
     ctx = tac.Context(0)
     stream = torch.cuda.current_stream(dev)
+    if args.calibration_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # one eager pass sizes the workspace and gives the budget for the plan
     idx = IX.group_and_budget(ctx, x, tok, w.vocab, w.k)
@@ -149,10 +188,19 @@ def main():
     F = 2.0 * 128 * float((counts[screen] * kappa[screen]).sum())   # algorithmic contraction flops per assign
     log(f"budget: K={int(kappa.sum())}, max kappa={int(kappa.max())}, screen flops/assign={F:.3e}")
 
-    loops = {}
+    loops, tuned, tuning = {}, {}, {}
     for name, prec in (("bf16", tac.TAC_BF16), ("fp32", tac.TAC_FP32)):
         if name == "fp32" and args.no_fp32:
             continue
+        if not args.no_autotune:
+            # launch tuning for this precision, measured on the initial centroids (cached per workload);
+            # it is baked into the captured graph
+            r = autotune.tune_assign(ctx, idx.xs, idx.C, idx.cent_off, idx.seg_off, precision=prec,
+                                     host_seg_off=idx.host["seg_off"], host_cent_off=idx.host["cent_off"])
+            tuned[name] = {"tuning": r["tuning"], "assign_ms": r["ms"], "default_assign_ms": r["default_ms"],
+                           "cached": r["cached"]}
+            log(f"autotune {name}: {r['tuning']} {r['ms']:.2f} ms (default {r['default_ms']:.2f} ms)")
+        tuning[name] = ctx.get_tuning()
         lp = IX.LloydLoop(ctx, idx, iters=args.iters, precision=prec)
         idx.C.copy_(C0)
         lp.run()                       # eager: sizes the workspace, sets kernel attributes
@@ -170,7 +218,7 @@ def main():
         return ev[0].elapsed_time(ev[1])
 
     def step(lp):
-        """One pass of the whole path; returns (step ms, Lloyd ms)."""
+        """One pass of the whole path; returns (step ms, Lloyd ms, final-assign kernel ms, encode kernel ms)."""
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = tac.tac_budget(ctx, x, tok, w.vocab, w.k, perm=idx.perm, xs=idx.xs, seg_off=idx.seg_off,
@@ -184,9 +232,14 @@ def main():
         IX.train_pq(ctx, idx, sample, init_rows, M=w.pq_m, ksub=w.pq_ksub, iters=10)
         IX.encode_all(ctx, idx)
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3, ev[0].elapsed_time(ev[1])
+        return ((time.perf_counter() - t0) * 1e3, ev[0].elapsed_time(ev[1]),
+                ctx.kernel_ms(tac._lib.TAC_SLOT_ASSIGN), ctx.kernel_ms(tac._lib.TAC_SLOT_ENCODE))
 
     head = loops["bf16"]
+    ctx.set_tuning(**tuning["bf16"])
+    # kernel events: each step's final assignment (one launch of the persistent BF16 assignment
+    # kernel) and its encode kernel are timed on the context's stream inside the timed region
+    ctx.enable_timing(True)
     for _ in range(args.warmup):
         step(head)
     torch.cuda.synchronize()
@@ -194,8 +247,11 @@ def main():
     res = [step(head) for _ in range(args.steps)]
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t_start) * 1e3
+    ctx.enable_timing(False)
     step_ms = [r[0] for r in res]
     lloyd = [r[1] for r in res]
+    assign_kernel_ms = float(np.mean([r[2] for r in res]))
+    encode_kernel_ms = float(np.mean([r[3] for r in res]))
     final_bf16 = idx.assign.clone()
     lloyd_med = float(np.median(lloyd))
     value = N * args.iters / (lloyd_med / 1e3)
@@ -219,21 +275,26 @@ def main():
     for name, prec in (("bf16", tac.TAC_BF16), ("fp32", tac.TAC_FP32)):
         if name not in loops:
             continue
+        ctx.set_tuning(**tuning[name])
         vals = []
         for _ in range(3):
             tac.tac_assign(ctx, idx.xs, idx.C, idx.cent_off, idx.assign, seg_off=idx.seg_off, precision=prec)
             vals.append(ctx.kernel_ms(tac._lib.TAC_SLOT_ASSIGN))
         kms[name] = float(np.mean(vals))
-    stats = tac.tac_assign_stats(ctx)
+        if name == "bf16":
+            stats = tac.tac_assign_stats(ctx)
     tac.tac_update(ctx, idx.xs, idx.seg_off, idx.assign, idx.C, loops["bf16"].other)
     upd_ms = ctx.kernel_ms(tac._lib.TAC_SLOT_UPDATE)
     IX.encode_all(ctx, idx)
     enc_ms = ctx.kernel_ms(tac._lib.TAC_SLOT_ENCODE)
     ctx.enable_timing(False)
-    achieved = F / (kms["bf16"] / 1e3) / 1e12
-    extra["kernels_ms"] = {"assign_bf16": kms.get("bf16"), "assign_fp32": kms.get("fp32"), "update_means": upd_ms,
+    achieved = F / (assign_kernel_ms / 1e3) / 1e12
+    extra["kernels_ms"] = {"assign_bf16_timed_region": assign_kernel_ms, "pq_encode_timed_region": encode_kernel_ms,
+                           "assign_bf16": kms.get("bf16"), "assign_fp32": kms.get("fp32"), "update_means": upd_ms,
                            "pq_encode": enc_ms}
     extra["assign_counters"] = stats
+    if tuned:
+        extra["autotune"] = tuned
     extra["lloyd_ms_per_iter"] = lloyd_med / args.iters
     extra["screen_flops_per_assign"] = F
     extra["mfma_executed_tflops_bf16x3"] = 3 * achieved
@@ -250,7 +311,7 @@ def main():
         cpu["value"] = float(cpu["value"])
 
     line = {
-        "metric": "vectors assigned/sec per Lloyd iter (bf16 screen, identical argmins to fp32)",
+        "metric": "vectors assigned/sec per Lloyd iter, bf16 vs fp32 at equal argmin; encode p99",
         "value": value,
         "unit": "vectors/s",
         "n_gpus": 1,
@@ -266,7 +327,7 @@ def main():
                    "centroids": w.k, "lloyd_iters": args.iters, "budget": "mu=128 tau=256 eps=4 theta=39",
                    "timed_region_ms": wall},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["bf16"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["bf16"], "traffic": None,
+                     "frac": achieved / PEAK["bf16"], "traffic": measured_traffic(args.config),
                      "kernel": "assign_main<bf16> (persistent screen + top-4 + certificate)"},
         "cpu_baseline": cpu,
         **extra,

@@ -105,6 +105,23 @@ enum { TAC_SLOT_ASSIGN = 0, TAC_SLOT_UPDATE = 1, TAC_SLOT_ENCODE = 2 };
 tac_status tac_ctx_enable_timing(tac_ctx ctx, int enable);
 tac_status tac_kernel_ms(tac_ctx ctx, int slot, float* ms);
 
+/* Launch tuning of tac_assign, chosen per workload by measurement
+ * (paper_2604_28142_amd/autotune.py).  Results do not depend on it.
+ *  direct_max_kappa  tokens with at most this many centroids (0..16) skip the
+ *                    matrix-core screen and compute every canonical distance;
+ *                    tokens without centroids always take that route (default 4)
+ *  heavy_kappa       tokens with at least this many centroids are scheduled
+ *                    first in the persistent work queue (default 1024)
+ *  groups_per_cu     persistent work-groups per compute unit; 0 = as many as
+ *                    fit (default 0) */
+typedef struct {
+    int32_t direct_max_kappa;
+    int32_t heavy_kappa;
+    int32_t groups_per_cu;
+} tac_tuning;
+tac_status tac_ctx_set_tuning(tac_ctx ctx, const tac_tuning* tuning);
+tac_status tac_ctx_get_tuning(tac_ctx ctx, tac_tuning* tuning);
+
 /* Wait for the context's stream, then free the workspace and the context. */
 void tac_ctx_destroy(tac_ctx ctx);
 

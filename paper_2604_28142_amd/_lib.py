@@ -26,7 +26,7 @@ _STATUS = {TAC_E_INVAL: "TAC_E_INVAL", TAC_E_INFEASIBLE: "TAC_E_INFEASIBLE", TAC
 EXPORTS = ["tac_ctx_create", "tac_ctx_set_stream", "tac_ctx_destroy", "tac_last_error", "tac_budget",
            "tac_budget_from_stats",
            "tac_init_centroids", "tac_assign", "tac_assign_stats", "tac_update", "tac_residuals", "pq_train",
-           "pq_encode", "tac_ctx_enable_timing", "tac_kernel_ms"]
+           "pq_encode", "tac_ctx_enable_timing", "tac_kernel_ms", "tac_ctx_set_tuning", "tac_ctx_get_tuning"]
 TAC_SLOT_ASSIGN, TAC_SLOT_UPDATE, TAC_SLOT_ENCODE = 0, 1, 2
 
 
@@ -39,6 +39,14 @@ class TacError(RuntimeError):
 class BudgetParams(C.Structure):
     _fields_ = [("mu", C.c_int64), ("tau", C.c_int64), ("eps", C.c_int64), ("theta", C.c_double),
                 ("theta_policy", C.c_int32)]
+
+
+class Tuning(C.Structure):
+    """Launch tuning of tac_assign (results do not depend on it)."""
+    _fields_ = [("direct_max_kappa", C.c_int32), ("heavy_kappa", C.c_int32), ("groups_per_cu", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class AssignCounters(C.Structure):
@@ -55,6 +63,8 @@ _SIGS = {
     "tac_ctx_destroy": (None, [_P]),
     "tac_ctx_enable_timing": (C.c_int, [_P, C.c_int]),
     "tac_kernel_ms": (C.c_int, [_P, C.c_int, C.POINTER(C.c_float)]),
+    "tac_ctx_set_tuning": (C.c_int, [_P, C.POINTER(Tuning)]),
+    "tac_ctx_get_tuning": (C.c_int, [_P, C.POINTER(Tuning)]),
     "tac_last_error": (C.c_char_p, []),
     "tac_budget": (C.c_int, [_P, _P, _P, _I64, _I32, _I32, _I64, C.POINTER(BudgetParams), _P, _P, _P, _P, _P, _P,
                              _P, _P, _P, _P]),
@@ -141,6 +151,25 @@ class Context:
         v = C.c_float()
         _check(load().tac_kernel_ms(self.handle, slot, C.byref(v)))
         return float(v.value)
+
+    def set_tuning(self, direct_max_kappa: int | None = None, heavy_kappa: int | None = None,
+                   groups_per_cu: int | None = None):
+        """Change some fields of the context's tac_assign tuning; returns the new tuning as a dict."""
+        t = Tuning()
+        _check(load().tac_ctx_get_tuning(self.handle, C.byref(t)))
+        if direct_max_kappa is not None:
+            t.direct_max_kappa = direct_max_kappa
+        if heavy_kappa is not None:
+            t.heavy_kappa = heavy_kappa
+        if groups_per_cu is not None:
+            t.groups_per_cu = groups_per_cu
+        _check(load().tac_ctx_set_tuning(self.handle, C.byref(t)))
+        return t.as_dict()
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(load().tac_ctx_get_tuning(self.handle, C.byref(t)))
+        return t.as_dict()
 
     def close(self):
         if getattr(self, "handle", None):

@@ -2,12 +2,13 @@
 // to the nearest of token j's centroids.
 //
 // One persistent launch serves every token.  The work list holds one item per
-// (token, 256-row tile); items of tokens with many centroids come first, so the
-// longest items start early.  Each item takes one of two routes:
+// (token, 512-row tile); items of tokens with many centroids come first, so the
+// longest items start early.  Each item takes one of two routes, split at a
+// tunable kappa limit (default 4, at most 16):
 //
-// * direct (kappa_j <= 4): every centroid is a candidate, so each row computes
+// * direct (few centroids): every centroid is a candidate, so each row computes
 //   the canonical FP32 distance to all of them;
-// * screen (kappa_j > 4): the distance contraction ||c||^2 - 2 x.c runs on the
+// * screen (more centroids): the distance contraction ||c||^2 - 2 x.c runs on the
 //   matrix cores (FP32 v_mfma_f32_16x16x4f32, or BF16 v_mfma_f32_16x16x32_bf16
 //   on hi/lo splits of both operands), centroid tiles are staged through LDS,
 //   and every lane keeps a running top-4 of packed (screen value, index) keys
@@ -39,8 +40,7 @@ constexpr int kDirectRows = kThreads;           // rows per direct work item (on
 constexpr int kStage = 64;                      // centroids per LDS stage
 constexpr int kRowWords = 132;                  // LDS row stride (512 B + 16 B pad)
 constexpr int kEpochBlocks = 64;                // 16-centroid blocks per packed-index epoch
-constexpr int kDirectMax = 4;                   // tokens with at most this many centroids skip the screen
-constexpr int kHeavy = 1024;                    // tokens with this many centroids are scheduled first
+constexpr int kDirectCap = 16;                  // most centroids a direct (screen-free) token may have
 constexpr float kInvalid = 3.0e38f;             // screen value of padding centroids
 constexpr unsigned kCntRows = 0, kCntScreened = 1, kCntFallback = 2, kCntUnassigned = 3;
 constexpr int kFbChunks = 16;                   // centroid chunks per fallback row
@@ -82,12 +82,12 @@ __global__ void reset_call(unsigned long long* __restrict__ work, unsigned long 
 
 // ---- plan: item counts per (class, token) ----
 __global__ void plan_count(const int64_t* __restrict__ seg_off, const int64_t* __restrict__ cent_off, int32_t T,
-                           int64_t* __restrict__ cnt) {
+                           int direct_max, int heavy, int64_t* __restrict__ cnt) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= T) return;
     const int64_t n = seg_off[j + 1] - seg_off[j];
     const int64_t k = cent_off[j + 1] - cent_off[j];
-    const int cls = k <= kDirectMax ? 2 : (k >= kHeavy ? 0 : 1);
+    const int cls = (k == 0 || k <= direct_max) ? 2 : (k >= heavy ? 0 : 1);
     const int64_t rows = cls == 2 ? kDirectRows : kTileRows;
     const int64_t tiles = (n + rows - 1) / rows;
     for (int c = 0; c < 3; ++c) cnt[(int64_t)c * T + j] = c == cls ? tiles : 0;
@@ -227,11 +227,13 @@ __device__ __forceinline__ void direct_item(const Params& P, int32_t j, int64_t 
             P.dist[r] = 0.f;
         } else {
             const float4* xv = reinterpret_cast<const float4*>(P.x + r * kDim);
-            float acc[kDirectMax] = {0.f, 0.f, 0.f, 0.f};
+            float acc[kDirectCap];
+#pragma unroll
+            for (int k = 0; k < kDirectCap; ++k) acc[k] = 0.f;
             for (int i = 0; i < kDim / 4; ++i) {
                 const float4 a = xv[i];
 #pragma unroll
-                for (int k = 0; k < kDirectMax; ++k) {
+                for (int k = 0; k < kDirectCap; ++k) {
                     if (k < kc) {
                         const float4 b = reinterpret_cast<const float4*>(P.C + (k0 + k) * kDim)[i];
                         float t;
@@ -244,7 +246,7 @@ __device__ __forceinline__ void direct_item(const Params& P, int32_t j, int64_t 
             }
             int best = 0;
 #pragma unroll
-            for (int k = 1; k < kDirectMax; ++k)
+            for (int k = 1; k < kDirectCap; ++k)
                 if (k < kc && acc[k] < acc[best]) best = k;
             P.assign[r] = (int32_t)(k0 + best);
             P.dist[r] = acc[best];
@@ -761,7 +763,8 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
         seg = sseg;
         rowmap = in1 ? v1 : v0;
     }
-    plan_count<<<grid_for(T, 256), 256, 0, s>>>(seg, cent_off_d, T, cnt);
+    plan_count<<<grid_for(T, 256), 256, 0, s>>>(seg, cent_off_d, T, ctx->tuning.direct_max_kappa,
+                                                  ctx->tuning.heavy_kappa, cnt);
     TAC_LAUNCH_CHECK("plan_count");
     st = exclusive_scan_i64(s, cnt, cnt, ncls, ws_at<void>(ctx, o_scan));
     if (st != TAC_OK) return st;
@@ -796,7 +799,9 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
         TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], assign_main<TAC_BF16>, kThreads, kLdsBytes));
         for (int i = 0; i < 2; ++i) occ[i] = occ[i] < 1 ? 1 : occ[i];
     }
-    const unsigned grid = (unsigned)ctx->props_cu * (unsigned)occ[precision == TAC_BF16 ? 1 : 0];
+    int per_cu = occ[precision == TAC_BF16 ? 1 : 0];
+    if (ctx->tuning.groups_per_cu > 0 && ctx->tuning.groups_per_cu < per_cu) per_cu = ctx->tuning.groups_per_cu;
+    const unsigned grid = (unsigned)ctx->props_cu * (unsigned)per_cu;
     time_start(ctx, TAC_SLOT_ASSIGN);
     if (precision == TAC_FP32) {
         assign_main<TAC_FP32><<<grid, kThreads, kLdsBytes, s>>>(P);

@@ -100,6 +100,21 @@ extern "C" tac_status tac_ctx_set_stream(tac_ctx ctx, void* hip_stream) {
     return TAC_OK;
 }
 
+extern "C" tac_status tac_ctx_set_tuning(tac_ctx ctx, const tac_tuning* t) {
+    if (!ctx || !t) return set_error(TAC_E_INVAL, "tac_ctx_set_tuning: NULL argument");
+    if (t->direct_max_kappa < 0 || t->direct_max_kappa > 16 || t->heavy_kappa < 1 || t->groups_per_cu < 0)
+        return set_error(TAC_E_INVAL, "tac_ctx_set_tuning: direct_max_kappa in [0, 16], heavy_kappa >= 1, "
+                                      "groups_per_cu >= 0");
+    ctx->tuning = *t;
+    return TAC_OK;
+}
+
+extern "C" tac_status tac_ctx_get_tuning(tac_ctx ctx, tac_tuning* t) {
+    if (!ctx || !t) return set_error(TAC_E_INVAL, "tac_ctx_get_tuning: NULL argument");
+    *t = ctx->tuning;
+    return TAC_OK;
+}
+
 extern "C" tac_status tac_ctx_enable_timing(tac_ctx ctx, int enable) {
     if (!ctx) return set_error(TAC_E_INVAL, "tac_ctx_enable_timing: ctx is NULL");
     TAC_HIP(hipSetDevice(ctx->device));

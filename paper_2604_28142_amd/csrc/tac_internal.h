@@ -54,6 +54,7 @@ struct tac_ctx_s {
     // per-context device counters of the last tac_assign (rows, screened, fallback, unassigned)
     unsigned long long* counters = nullptr;
     int props_cu = 256;
+    tac_tuning tuning = {4, 1024, 0};
     // optional HIP-event timing of each entry point's dominant kernel
     bool timing = false;
     hipEvent_t ev[TAC_KERNEL_SLOTS][2] = {};

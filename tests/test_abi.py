@@ -69,3 +69,17 @@ def test_host_budget_golden():
                              c["policy"])
         got, _ = tac.tac_budget_from_stats(c["counts"], c["spread"], c["K"], p)
         assert got.tolist() == c["kappa"]
+
+
+def test_autotune_workload_key_tracks_structure():
+    pytest.importorskip("paper_2604_28142_amd")
+    from paper_2604_28142_amd import autotune
+    seg = np.array([0, 10, 30, 31], np.int64)
+    cen = np.array([0, 2, 7, 8], np.int64)
+    k = autotune.workload_key(seg, cen, 1)
+    assert k == autotune.workload_key(seg.copy(), cen.copy(), 1)
+    assert k != autotune.workload_key(seg, cen, 0)
+    assert k != autotune.workload_key(np.array([0, 11, 30, 31]), cen, 1)
+    assert k != autotune.workload_key(seg, np.array([0, 3, 7, 8]), 1)
+    assert set(autotune.DEFAULT) == set(autotune.SPACE)
+    assert all(v in autotune.SPACE[n] for n, v in autotune.DEFAULT.items())

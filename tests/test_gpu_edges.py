@@ -172,3 +172,49 @@ def test_graph_replay_equals_eager(ctx):
         assert torch.equal(loop.inertia, J_eager), rep
         # eager work between replays
         run_assign(ctx, c.xs, c.seg_off, c.C0, c.cent_off, tac.TAC_FP32)
+
+
+@pytest.mark.parametrize("tuning", [dict(direct_max_kappa=0, heavy_kappa=1, groups_per_cu=1),
+                                    dict(direct_max_kappa=16, heavy_kappa=64, groups_per_cu=0)])
+def test_tuning_keeps_results(ctx, tuning):
+    """Launch tuning moves tokens between the direct and screened routes and
+    reorders the work queue; the assignments stay those of the oracle."""
+    rng = np.random.default_rng(15)
+    kappas = [1, 3, 4, 5, 16, 17, 70]
+    sizes = [40, 3 * 5 + 7, 200, 513, 90, 1030, 700]
+    xs = np.concatenate([clustered(rng, n, 6) for n in sizes])
+    seg_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    cent_off = np.concatenate([[0], np.cumsum(kappas)]).astype(np.int64)
+    C = np.concatenate([xs[seg_off[j] + rng.choice(sizes[j], kappas[j], replace=False)] for j in range(len(sizes))])
+    before = ctx.get_tuning()
+    try:
+        assert ctx.set_tuning(**tuning) == tuning
+        for prec in (0, 1):
+            a, d, J = run_assign(ctx, xs, seg_off, C, cent_off, prec)
+            check_assign(xs, seg_off, C, cent_off, a, d)
+    finally:
+        ctx.set_tuning(**before)
+    with pytest.raises(tac.TacError):
+        ctx.set_tuning(direct_max_kappa=17)
+
+
+def test_autotune_cache_roundtrip(ctx, tmp_path):
+    from paper_2604_28142_amd import autotune
+    c = Case("small")
+    d = c.device()
+    C = dev(c.C0)
+    path = str(tmp_path / "tune.json")
+    space = {"direct_max_kappa": [0, 4], "heavy_kappa": [256, 1024], "groups_per_cu": [0]}
+    before = ctx.get_tuning()
+    try:
+        r1 = autotune.tune_assign(ctx, d["xs"], C, d["cent_off"], d["seg_off"], precision=tac.TAC_BF16, reps=1,
+                                  cache_path=path, space=space)
+        assert not r1["cached"] and len(r1["trials"]) >= 3
+        assert ctx.get_tuning() == r1["tuning"]
+        r2 = autotune.tune_assign(ctx, d["xs"], C, d["cent_off"], d["seg_off"], precision=tac.TAC_BF16,
+                                  cache_path=path, space=space)
+        assert r2["cached"] and r2["tuning"] == r1["tuning"]
+        a, dd, _ = run_assign(ctx, c.xs, c.seg_off, c.C0, c.cent_off, tac.TAC_BF16)
+        check_assign(c.xs, c.seg_off, c.C0, c.cent_off, a, dd, fp64=False)
+    finally:
+        ctx.set_tuning(**before)

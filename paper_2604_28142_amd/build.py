@@ -24,7 +24,10 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE,
           "-ffp-contract=off",
           # packed FP32 VALU forms are kept out of the generated code
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-PER_FILE: dict = {}
+PER_FILE: dict = {
+    # matrix-core accumulators in VGPRs (the BF16 screen keeps its x operands in AGPRs)
+    "assign.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
 
 
 def sources():

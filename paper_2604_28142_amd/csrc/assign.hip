@@ -36,7 +36,6 @@ constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 constexpr int kNB = 4;                          // 16-row column blocks per wave
 constexpr int kTileRows = kWaves * kNB * 16;    // rows per screened work item
-constexpr int kDirectRows = kThreads;           // rows per direct work item (one per thread)
 constexpr int kStage = 64;                      // centroids per LDS stage
 constexpr int kRowWords = 132;                  // LDS row stride (512 B + 16 B pad)
 constexpr int kEpochBlocks = 64;                // 16-centroid blocks per packed-index epoch
@@ -47,6 +46,7 @@ constexpr int kFbChunks = 16;                   // centroid chunks per fallback 
 // dynamic LDS of the assignment kernel: two centroid stages, their norms, then the
 // per-lane merged top-4 lists (value and index words) of every wave
 constexpr size_t kGlistOffsetWords = (size_t)2 * kStage * kRowWords + (size_t)2 * kStage;
+constexpr size_t kLdsBytes = (kGlistOffsetWords + (size_t)kWaves * kNB * 8 * 64) * 4;
 
 __device__ __forceinline__ float dist32_rows(const float* __restrict__ x, const float* __restrict__ c, float* xx) {
     const float4* xv = reinterpret_cast<const float4*>(x);
@@ -82,13 +82,13 @@ __global__ void reset_call(unsigned long long* __restrict__ work, unsigned long 
 
 // ---- plan: item counts per (class, token) ----
 __global__ void plan_count(const int64_t* __restrict__ seg_off, const int64_t* __restrict__ cent_off, int32_t T,
-                           int direct_max, int heavy, int64_t* __restrict__ cnt) {
+                           int direct_max, int heavy, int screen_rows, int direct_rows, int64_t* __restrict__ cnt) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= T) return;
     const int64_t n = seg_off[j + 1] - seg_off[j];
     const int64_t k = cent_off[j + 1] - cent_off[j];
     const int cls = (k == 0 || k <= direct_max) ? 2 : (k >= heavy ? 0 : 1);
-    const int64_t rows = cls == 2 ? kDirectRows : kTileRows;
+    const int64_t rows = cls == 2 ? direct_rows : screen_rows;
     const int64_t tiles = (n + rows - 1) / rows;
     for (int c = 0; c < 3; ++c) cnt[(int64_t)c * T + j] = c == cls ? tiles : 0;
 }
@@ -168,6 +168,24 @@ __device__ __forceinline__ void list_insert(unsigned (&l)[4], unsigned p) {
     l[0] = min(l[0], p);
 }
 
+// The same running top-4 on keys held as floats: the keys are non-negative
+// finite floats, which order like their bit patterns, and med3 / min of floats
+// select one of their inputs exactly.  The empty slot is FLT_MAX.
+__device__ __forceinline__ void list_insert(float (&l)[4], float p) {
+    l[3] = __builtin_amdgcn_fmed3f(l[2], l[3], p);
+    l[2] = __builtin_amdgcn_fmed3f(l[1], l[2], p);
+    l[1] = __builtin_amdgcn_fmed3f(l[0], l[1], p);
+    l[0] = __builtin_amdgcn_fmed3f(l[0], p, -FLT_MAX);  // min without an IEEE canonicalisation
+}
+__device__ __forceinline__ unsigned key_bits(unsigned k) { return k; }
+__device__ __forceinline__ unsigned key_bits(float k) { return __float_as_uint(k); }
+template <class K>
+__device__ __forceinline__ K key_empty();
+template <>
+__device__ __forceinline__ unsigned key_empty<unsigned>() { return 0xFFFFFFFFu; }
+template <>
+__device__ __forceinline__ float key_empty<float>() { return FLT_MAX; }
+
 // Insert (t, i) into the ascending list (G, I); `lex` breaks value ties by index.
 __device__ __forceinline__ void glist_insert(float (&G)[4], int (&I)[4], float t, int i, bool lex) {
     bool c[4];
@@ -183,21 +201,38 @@ __device__ __forceinline__ void glist_insert(float (&G)[4], int (&I)[4], float t
     I[0] = c[0] ? i : I[0];
 }
 
-template <int PREC>
+// x fragments of the NB column blocks (16 rows each) a wave owns for a whole
+// item: FP32 keeps -2x, BF16 keeps hi/lo BF16 splits of -2x.  Lane group g
+// holds coordinates [32g, 32g + 32) of row `col` of each block.
+template <int PREC, int NB>
 struct Frag;
 
-template <>
-struct Frag<TAC_FP32> {
-    float x[kNB][32];
+template <int NB>
+struct Frag<TAC_FP32, NB> {
+    float x[NB][32];
 };
 
-template <>
-struct Frag<TAC_BF16> {
-    bf8 xh[kNB][4];
-    bf8 xl[kNB][4];
+template <int NB>
+struct Frag<TAC_BF16, NB> {
+    bf8 xh[NB][4];
+    bf8 xl[NB][4];
 };
 
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+
+// Move a BF16 fragment into accumulation registers (AGPRs).  The BF16 screen's
+// x operands stay there for a whole item and feed the matrix cores directly,
+// which leaves the VGPRs to the accumulators, lists and centroid fragments.
+__device__ __forceinline__ bf8 to_agpr(bf8 v) {
+    const u4 u = __builtin_bit_cast(u4, v);
+    unsigned a0, a1, a2, a3;
+    asm("v_accvgpr_write_b32 %0, %1" : "=a"(a0) : "v"(u[0]));
+    asm("v_accvgpr_write_b32 %0, %1" : "=a"(a1) : "v"(u[1]));
+    asm("v_accvgpr_write_b32 %0, %1" : "=a"(a2) : "v"(u[2]));
+    asm("v_accvgpr_write_b32 %0, %1" : "=a"(a3) : "v"(u[3]));
+    const u4 r = {a0, a1, a2, a3};
+    return __builtin_bit_cast(bf8, r);
+}
 
 // hi = bf16(v), lo = bf16(v - hi) for 8 consecutive values (round to nearest even)
 __device__ __forceinline__ void split_bf8(const float* v, bf8& hi, bf8& lo) {
@@ -212,12 +247,13 @@ __device__ __forceinline__ void split_bf8(const float* v, bf8& hi, bf8& lo) {
     lo = __builtin_bit_cast(bf8, l);
 }
 
-template <int PREC>
+// Direct route: one row per thread, every centroid of the token a candidate.
+template <int ROWS>
 __device__ __forceinline__ void direct_item(const Params& P, int32_t j, int64_t tile) {
     const int64_t s0 = P.seg_off[j], s1 = P.seg_off[j + 1];
     const int64_t k0 = P.cent_off[j];
     const int kc = (int)(P.cent_off[j + 1] - k0);
-    const int64_t row0 = s0 + tile * kDirectRows;
+    const int64_t row0 = s0 + tile * ROWS;
     const int64_t v = row0 + threadIdx.x;
     const bool valid = v < s1;
     if (valid) {
@@ -259,27 +295,14 @@ __device__ __forceinline__ void direct_item(const Params& P, int32_t j, int64_t 
     }
 }
 
-template <int PREC>
-__device__ __forceinline__ void screen_item(const Params& P, int32_t j, int64_t tile, unsigned* lds) {
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int g = lane >> 4;
-    const int col = lane & 15;
-    const int64_t s0 = P.seg_off[j], s1 = P.seg_off[j + 1];
-    const int64_t k0 = P.cent_off[j];
-    const int kc = (int)(P.cent_off[j + 1] - k0);
-    const int64_t row0 = s0 + tile * kTileRows + wave * (kNB * 16);
-    const float cnmax = __uint_as_float(P.cstat[0]) * (1.0f + 1e-5f);
-    const float cmax = sqrtf(cnmax) * (1.0f + 1e-6f);
-
-    // LDS: two stages of kStage rows (kRowWords words each) and their norms
-    unsigned* stage_rows = lds;                                  // [2][kStage][kRowWords]
-    float* stage_cn = reinterpret_cast<float*>(lds + 2 * kStage * kRowWords);  // [2][kStage]
-
-    Frag<PREC> F;
+// Load and convert the wave's x fragments (rows row0 .. row0 + 16 NB - 1, those
+// at or past s1 as zeros); returns the largest ||x||^2 over the wave's rows.
+template <int PREC, int NB>
+__device__ __forceinline__ float load_x_frags(const Params& P, int64_t row0, int64_t s1, int g, int col,
+                                              Frag<PREC, NB>& F) {
     float xxmax = 0.f;
 #pragma unroll
-    for (int nb = 0; nb < kNB; ++nb) {
+    for (int nb = 0; nb < NB; ++nb) {
         __builtin_amdgcn_sched_barrier(0);  // convert one column block at a time (bounded live registers)
         const int64_t v = row0 + nb * 16 + col;
         const bool valid = v < s1;
@@ -305,160 +328,87 @@ __device__ __forceinline__ void screen_item(const Params& P, int32_t j, int64_t 
                 xx += a.x * a.x + a.y * a.y + a.z * a.z + a.w * a.w + b.x * b.x + b.y * b.y + b.z * b.z + b.w * b.w;
                 const float v8[8] = {-2.0f * a.x, -2.0f * a.y, -2.0f * a.z, -2.0f * a.w,
                                      -2.0f * b.x, -2.0f * b.y, -2.0f * b.z, -2.0f * b.w};
-                split_bf8(v8, F.xh[nb][s], F.xl[nb][s]);
+                bf8 hi, lo;
+                split_bf8(v8, hi, lo);
+                F.xh[nb][s] = to_agpr(hi);
+                F.xl[nb][s] = to_agpr(lo);
             }
         }
         xx += __shfl_xor(xx, 16);
         xx += __shfl_xor(xx, 32);
         xxmax = fmaxf(xxmax, xx);
     }
-    // One shift for the whole wave makes every screen value positive:
-    // beta >= ||x||^2 + (screen error) for each of its rows, so that
-    // beta + ||c||^2 - 2 x.c >= ||x - c||^2 + margin > 0 and packed keys order as floats.
+    // keep every fragment write far above the first matrix-core read
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int m = 1; m < 16; m <<= 1) xxmax = fmaxf(xxmax, __shfl_xor(xxmax, m));
-    const float beta = xxmax * (1.0f + 0.00390625f) + 0.00390625f * cnmax + 1e-30f;
+    return xxmax;
+}
 
-    // epoch lists in registers; the merged (value, index) lists of each row live in
-    // wave-private LDS, touched only at epoch ends and once per item
-    unsigned el[kNB][4];
-    unsigned* glist = lds + kGlistOffsetWords + (unsigned)wave * (kNB * 8 * 64) + lane;
-    auto gslot = [&](int nb, int e) -> unsigned& { return glist[(nb * 8 + e) * 64]; };
+// The merged (value, index) top-4 list of each row lives in wave-private LDS,
+// touched only at epoch ends and once per item: slot (nb, e) of a lane is
+// glist[(nb * 8 + e) * 64], values for e < 4 and indices for e >= 4.
+template <int NB>
+__device__ __forceinline__ void glist_init(unsigned* glist) {
 #pragma unroll
-    for (int nb = 0; nb < kNB; ++nb)
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            el[nb][e] = 0xFFFFFFFFu;
-            gslot(nb, e) = __float_as_uint(kInvalid);
-            gslot(nb, 4 + e) = 0xFFFFFFFFu;
+            glist[(nb * 8 + e) * 64] = __float_as_uint(kInvalid);
+            glist[(nb * 8 + 4 + e) * 64] = 0xFFFFFFFFu;
         }
+}
 
-    const char* csrc = static_cast<const char*>(P.cstage);
-    const int nst = (kc + kStage - 1) / kStage;
-    // stage loader: 64 rows x 512 B = 2048 float4; each thread moves kStageVec of them
-    constexpr int kStageVec = kStage * 32 / kThreads;
-    auto load_stage = [&](int st, u4 (&reg)[kStageVec], float& rcn) {
+// Fold the epoch's packed keys into the merged lists and reset them.  A key's
+// low 8 bits are (16-block within the epoch) * 4 + r; ebase is the global index
+// of the epoch's first centroid plus 4g.
+template <int NB, class Key>
+__device__ __forceinline__ void epoch_flush(Key (&el)[NB][4], unsigned* glist, int64_t ebase) {
 #pragma unroll
-        for (int it = 0; it < kStageVec; ++it) {
-            const int chunk = it * kThreads + threadIdx.x;
-            const int row = chunk >> 5;
-            const int c16 = chunk & 31;
-            const int kk = st * kStage + row;
-            reg[it] = kk < kc ? reinterpret_cast<const u4*>(csrc + (k0 + kk) * 512)[c16] : u4{0u, 0u, 0u, 0u};
+    for (int nb = 0; nb < NB; ++nb) {
+        float G[4];
+        int I[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            G[e] = __uint_as_float(glist[(nb * 8 + e) * 64]);
+            I[e] = (int)glist[(nb * 8 + 4 + e) * 64];
         }
-        const int kk = st * kStage + (threadIdx.x & 63);
-        rcn = kk < kc ? P.cn[k0 + kk] : kInvalid;
-    };
-    auto store_stage = [&](int buf, const u4 (&reg)[kStageVec], float rcn) {
 #pragma unroll
-        for (int it = 0; it < kStageVec; ++it) {
-            const int chunk = it * kThreads + threadIdx.x;
-            const int row = chunk >> 5;
-            const int c16 = chunk & 31;
-            *reinterpret_cast<u4*>(stage_rows + (buf * kStage + row) * kRowWords + c16 * 4) = reg[it];
+        for (int e = 0; e < 4; ++e) {
+            const unsigned bits = key_bits(el[nb][e]);
+            const float t = __uint_as_float(bits & ~0xFFu);
+            const unsigned loc = bits & 0xFFu;
+            const int gi = (int)(ebase + (int64_t)(loc >> 2) * 16 + (loc & 3u));
+            if (t < 1.0e38f) glist_insert(G, I, t, gi, false);
+            el[nb][e] = key_empty<Key>();
         }
-        if (threadIdx.x < kStage) stage_cn[buf * kStage + threadIdx.x] = rcn;
-    };
-
-    u4 pf[kStageVec];
-    float pcn;
-    load_stage(0, pf, pcn);
-    store_stage(0, pf, pcn);
-    __syncthreads();
-
-    int epoch_first = 0;  // first 16-block of the current epoch (segment-relative)
-    for (int st = 0; st < nst; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < nst) load_stage(st + 1, pf, pcn);
-#pragma unroll 1
-        for (int b = 0; b < kStage / 16; ++b) {
-            const int blk16 = st * (kStage / 16) + b;  // segment-relative 16-block
-            if (blk16 * 16 >= kc) break;
-            const unsigned* crow = stage_rows + (buf * kStage + b * 16 + col) * kRowWords;
-            const f4 cinit = *reinterpret_cast<const f4*>(stage_cn + buf * kStage + b * 16 + 4 * g);
-            f4 acc[kNB];
-            const f4 cb4 = cinit + beta;
 #pragma unroll
-            for (int nb = 0; nb < kNB; ++nb) acc[nb] = cb4;
-            // centroid fragments stream from LDS one k-step group at a time
-            if constexpr (PREC == TAC_FP32) {
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const f4 c4 = *reinterpret_cast<const f4*>(crow + 32 * g + 4 * q);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-#pragma unroll
-                        for (int nb = 0; nb < kNB; ++nb)
-                            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(c4[e], F.x[nb][4 * q + e], acc[nb], 0, 0, 0);
-                }
-            } else {
-#pragma unroll
-                for (int st4 = 0; st4 < 4; ++st4) {
-                    const bf8 ch = *reinterpret_cast<const bf8*>(crow + 16 * g + 4 * st4);
-                    const bf8 cl = *reinterpret_cast<const bf8*>(crow + 64 + 16 * g + 4 * st4);
-#pragma unroll
-                    for (int nb = 0; nb < kNB; ++nb)
-                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, F.xh[nb][st4], acc[nb], 0, 0, 0);
-#pragma unroll
-                    for (int nb = 0; nb < kNB; ++nb)
-                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, F.xl[nb][st4], acc[nb], 0, 0, 0);
-#pragma unroll
-                    for (int nb = 0; nb < kNB; ++nb)
-                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl, F.xh[nb][st4], acc[nb], 0, 0, 0);
-                }
-            }
-            const unsigned lb = (unsigned)(blk16 - epoch_first) * 4u;
-#pragma unroll
-            for (int nb = 0; nb < kNB; ++nb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) list_insert(el[nb], (__float_as_uint(acc[nb][r]) & ~0xFFu) | (lb + r));
-            const bool last = (blk16 + 1) * 16 >= kc;
-            if (blk16 - epoch_first == kEpochBlocks - 1 || last) {
-                const int64_t ebase = k0 + (int64_t)epoch_first * 16 + 4 * g;
-#pragma unroll
-                for (int nb = 0; nb < kNB; ++nb) {
-                    float G[4];
-                    int I[4];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        G[e] = __uint_as_float(gslot(nb, e));
-                        I[e] = (int)gslot(nb, 4 + e);
-                    }
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const unsigned bits = el[nb][e];
-                        const float t = __uint_as_float(bits & ~0xFFu);
-                        const unsigned loc = bits & 0xFFu;
-                        const int gi = (int)(ebase + (int64_t)(loc >> 2) * 16 + (loc & 3u));
-                        if (t < 1.0e38f) glist_insert(G, I, t, gi, false);
-                        el[nb][e] = 0xFFFFFFFFu;
-                    }
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        gslot(nb, e) = __float_as_uint(G[e]);
-                        gslot(nb, 4 + e) = (unsigned)I[e];
-                    }
-                }
-                epoch_first = blk16 + 1;
-            }
+        for (int e = 0; e < 4; ++e) {
+            glist[(nb * 8 + e) * 64] = __float_as_uint(G[e]);
+            glist[(nb * 8 + 4 + e) * 64] = (unsigned)I[e];
         }
-        if (st + 1 < nst) store_stage(buf ^ 1, pf, pcn);
-        __syncthreads();
     }
+}
 
-    // rescore nominee g of each row with the canonical distance, then certify
+// End of a screened item: merge the four lane groups' lists of every row,
+// rescore nominee g with the canonical distance, keep the best, and certify it
+// with the screen's error bound (else queue the row for exhaustive rescoring).
+template <int PREC, int NB>
+__device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t row0, int64_t s1,
+                                            const unsigned* glist, float beta, float cnmax, float cmax, int g,
+                                            int col, int lane) {
     const double u = 5.9604644775390625e-8;  // 2^-24
     const double g130 = 130.0 * u / (1.0 - 130.0 * u);
     const double g386 = 386.0 * u / (1.0 - 386.0 * u);
     int nscreen = 0;
 #pragma unroll
-    for (int nb = 0; nb < kNB; ++nb) {
+    for (int nb = 0; nb < NB; ++nb) {
         float G[4];
         int I[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            G[e] = __uint_as_float(gslot(nb, e));
-            I[e] = (int)gslot(nb, 4 + e);
+            G[e] = __uint_as_float(glist[(nb * 8 + e) * 64]);
+            I[e] = (int)glist[(nb * 8 + 4 + e) * 64];
         }
         // merge the four lanes that share a row (lane groups g = 0..3)
 #pragma unroll
@@ -529,15 +479,331 @@ __device__ __forceinline__ void screen_item(const Params& P, int32_t j, int64_t 
     }
 }
 
+// ---- FP32 screen: 8 waves x 4 column blocks of 16 rows = 512 rows per item ----
+// Centroid stages of 64 rows are staged through registers into padded LDS rows.
+__device__ __forceinline__ void screen_item_fp32(const Params& P, int32_t j, int64_t tile, unsigned* lds) {
+    constexpr int NB = kNB;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int col = lane & 15;
+    const int64_t s0 = P.seg_off[j], s1 = P.seg_off[j + 1];
+    const int64_t k0 = P.cent_off[j];
+    const int kc = (int)(P.cent_off[j + 1] - k0);
+    const int64_t row0 = s0 + tile * kTileRows + wave * (NB * 16);
+    const float cnmax = __uint_as_float(P.cstat[0]) * (1.0f + 1e-5f);
+    const float cmax = sqrtf(cnmax) * (1.0f + 1e-6f);
+
+    // LDS: two stages of kStage rows (kRowWords words each) and their norms
+    unsigned* stage_rows = lds;                                  // [2][kStage][kRowWords]
+    float* stage_cn = reinterpret_cast<float*>(lds + 2 * kStage * kRowWords);  // [2][kStage]
+
+    Frag<TAC_FP32, NB> F;
+    const float xxmax = load_x_frags<TAC_FP32, NB>(P, row0, s1, g, col, F);
+    // One shift for the whole wave makes every screen value positive:
+    // beta >= ||x||^2 + (screen error) for each of its rows, so that
+    // beta + ||c||^2 - 2 x.c >= ||x - c||^2 + margin > 0 and packed keys order as floats.
+    const float beta = xxmax * (1.0f + 0.00390625f) + 0.00390625f * cnmax + 1e-30f;
+
+    unsigned el[NB][4];
+    unsigned* glist = lds + kGlistOffsetWords + (unsigned)wave * (NB * 8 * 64) + lane;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) el[nb][e] = 0xFFFFFFFFu;
+    glist_init<NB>(glist);
+
+    const char* csrc = static_cast<const char*>(P.cstage);
+    const int nst = (kc + kStage - 1) / kStage;
+    // stage loader: 64 rows x 512 B = 2048 float4; each thread moves kStageVec of them
+    constexpr int kStageVec = kStage * 32 / kThreads;
+    auto load_stage = [&](int st, u4 (&reg)[kStageVec], float& rcn) {
+#pragma unroll
+        for (int it = 0; it < kStageVec; ++it) {
+            const int chunk = it * kThreads + threadIdx.x;
+            const int row = chunk >> 5;
+            const int c16 = chunk & 31;
+            const int kk = st * kStage + row;
+            reg[it] = kk < kc ? reinterpret_cast<const u4*>(csrc + (k0 + kk) * 512)[c16] : u4{0u, 0u, 0u, 0u};
+        }
+        const int kk = st * kStage + (threadIdx.x & 63);
+        rcn = kk < kc ? P.cn[k0 + kk] : kInvalid;
+    };
+    auto store_stage = [&](int buf, const u4 (&reg)[kStageVec], float rcn) {
+#pragma unroll
+        for (int it = 0; it < kStageVec; ++it) {
+            const int chunk = it * kThreads + threadIdx.x;
+            const int row = chunk >> 5;
+            const int c16 = chunk & 31;
+            *reinterpret_cast<u4*>(stage_rows + (buf * kStage + row) * kRowWords + c16 * 4) = reg[it];
+        }
+        if (threadIdx.x < kStage) stage_cn[buf * kStage + threadIdx.x] = rcn;
+    };
+
+    u4 pf[kStageVec];
+    float pcn;
+    load_stage(0, pf, pcn);
+    store_stage(0, pf, pcn);
+    __syncthreads();
+
+    int epoch_first = 0;  // first 16-block of the current epoch (segment-relative)
+    for (int st = 0; st < nst; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nst) load_stage(st + 1, pf, pcn);
+#pragma unroll 1
+        for (int b = 0; b < kStage / 16; ++b) {
+            const int blk16 = st * (kStage / 16) + b;  // segment-relative 16-block
+            if (blk16 * 16 >= kc) break;
+            const unsigned* crow = stage_rows + (buf * kStage + b * 16 + col) * kRowWords;
+            const f4 cinit = *reinterpret_cast<const f4*>(stage_cn + buf * kStage + b * 16 + 4 * g);
+            f4 acc[NB];
+            const f4 cb4 = cinit + beta;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[nb] = cb4;
+            // centroid fragments stream from LDS one k-step group at a time
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const f4 c4 = *reinterpret_cast<const f4*>(crow + 32 * g + 4 * q);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(c4[e], F.x[nb][4 * q + e], acc[nb], 0, 0, 0);
+            }
+            const unsigned lb = (unsigned)(blk16 - epoch_first) * 4u;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) list_insert(el[nb], (__float_as_uint(acc[nb][r]) & ~0xFFu) | (lb + r));
+            const bool last = (blk16 + 1) * 16 >= kc;
+            if (blk16 - epoch_first == kEpochBlocks - 1 || last) {
+                epoch_flush<NB, unsigned>(el, glist, k0 + (int64_t)epoch_first * 16 + 4 * g);
+                epoch_first = blk16 + 1;
+            }
+        }
+        if (st + 1 < nst) store_stage(buf ^ 1, pf, pcn);
+        __syncthreads();
+    }
+    finish_item<TAC_FP32, NB>(P, j, row0, s1, glist, beta, cnmax, cmax, g, col, lane);
+}
+
+// ---- BF16 screen: 4 waves (one per SIMD) x 5 column blocks of 16 rows = 320 rows per item ----
+// The wave's x operands (hi and lo BF16 splits of -2x) stay in AGPRs for the
+// whole item.  Centroid stages of 64 rows (hi and lo halves, 512 B per
+// centroid) go straight from global memory into LDS (global_load_lds_dwordx4,
+// no registers), three buffers deep, with the 16-byte chunks of row r stored
+// at chunk ^ (r & 15) so that the fragment reads of 16 consecutive rows hit
+// distinct banks without padding.  The 16-centroid block loop is software
+// pipelined: while the matrix cores run block b, the wave reads block b + 1's
+// fragments from LDS and folds block b - 1's screen values into its top-4
+// lists, so the three streams (matrix, LDS, vector) overlap.
+constexpr int kBThreads = 256;
+constexpr int kBWaves = kBThreads / 64;
+constexpr int kBNB = 5;
+constexpr int kBTileRows = kBWaves * kBNB * 16;
+constexpr int kBStage = 64;                               // centroids per stage
+constexpr int kBBufs = 3;                                 // stage buffers
+constexpr int kBStageWords = kBStage * 128;               // 512 B per centroid
+constexpr size_t kBCnOffsetWords = (size_t)kBBufs * kBStageWords;
+constexpr size_t kBGlistOffsetWords = kBCnOffsetWords + (size_t)kBBufs * kBStage;
+constexpr size_t kBLdsBytes = (kBGlistOffsetWords + (size_t)kBWaves * kBNB * 8 * 64) * 4;
+static_assert(kBLdsBytes + 16 <= 160 * 1024, "fits the LDS of a CU");
+
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
+// Issue the DMA of stage `st` (centroids st*64 .. st*64+63 of the token) into
+// `buf`: 32 pairs of rows, 1 KiB each, eight pairs per wave.  Lane l moves
+// 16 bytes of row 2*pair + (l >> 5) into physical chunk l & 31.  Rows past the
+// token's last centroid repeat it (their norms mark them invalid).
+__device__ __forceinline__ void bf_stage_issue(const char* __restrict__ chl, int64_t k0, int kc, int st,
+                                               unsigned* buf, int wave, int lane) {
+    static_assert(kBStage / 2 % kBWaves == 0, "row pairs split evenly over the waves");
+#pragma unroll
+    for (int i = 0; i < kBStage / 2 / kBWaves; ++i) {
+        const int pair = wave * (kBStage / 2 / kBWaves) + i;
+        const int row = 2 * pair + (lane >> 5);
+        int kk = st * kBStage + row;
+        kk = kk < kc ? kk : kc - 1;
+        const int chunk = (lane & 31) ^ (row & 15);
+        const char* src = chl + (k0 + kk) * 512 + chunk * 16;
+        __builtin_amdgcn_global_load_lds(src, (lds_void_ptr)(buf + pair * 256), 16, 0, 0);
+    }
+}
+
+// One 16-centroid block's operands in registers: hi/lo fragments for the four
+// k-steps and the accumulator start (norms + beta) of the lane's four columns.
+struct BBlock {
+    bf8 ch[4];
+    bf8 cl[4];
+    f4 cb;
+};
+
+__device__ __forceinline__ void screen_item_bf16(const Params& P, int32_t j, int64_t tile, unsigned* lds) {
+    constexpr int NB = kBNB;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int col = lane & 15;
+    const int64_t s0 = P.seg_off[j], s1 = P.seg_off[j + 1];
+    const int64_t k0 = P.cent_off[j];
+    const int kc = (int)(P.cent_off[j + 1] - k0);
+    const int64_t row0 = s0 + tile * kBTileRows + wave * (NB * 16);
+    const float cnmax = __uint_as_float(P.cstat[0]) * (1.0f + 1e-5f);
+    const float cmax = sqrtf(cnmax) * (1.0f + 1e-6f);
+
+    unsigned* stage = lds;                                               // [3][kBStageWords]
+    float* stage_cn = reinterpret_cast<float*>(lds + kBCnOffsetWords);   // [3][kBStage]
+    unsigned* glist = lds + kBGlistOffsetWords + (unsigned)wave * (NB * 8 * 64) + lane;
+    const char* chl = static_cast<const char*>(P.cstage);
+    const int nst = (kc + kBStage - 1) / kBStage;
+    const int nblk = (kc + 15) / 16;
+
+    // stage 0 and its norms first, so their latency overlaps the x prologue
+    bf_stage_issue(chl, k0, kc, 0, stage, wave, lane);
+    if (threadIdx.x < kBStage) stage_cn[threadIdx.x] = (int)threadIdx.x < kc ? P.cn[k0 + threadIdx.x] : kInvalid;
+    float pcn = kInvalid;  // norms of the next stage to publish (threads < 64)
+    if (nst > 1 && threadIdx.x < kBStage) {
+        const int kk = kBStage + threadIdx.x;
+        pcn = kk < kc ? P.cn[k0 + kk] : kInvalid;
+    }
+
+    Frag<TAC_BF16, NB> F;
+    const float xxmax = load_x_frags<TAC_BF16, NB>(P, row0, s1, g, col, F);
+    // One shift for the whole wave makes every screen value positive (see the FP32 screen).
+    const float beta = xxmax * (1.0f + 0.00390625f) + 0.00390625f * cnmax + 1e-30f;
+    float el[NB][4];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) el[nb][e] = FLT_MAX;
+    glist_init<NB>(glist);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (nst > 1) bf_stage_issue(chl, k0, kc, 1, stage + kBStageWords, wave, lane);
+
+    int epoch_first = 0;
+    auto load_block = [&](int blk, BBlock& B) {
+        const int buf = (blk >> 2) % kBBufs;
+        const int b = blk & 3;
+        const unsigned* srow = stage + buf * kBStageWords + (b * 16 + col) * 128;
+#pragma unroll
+        for (int st4 = 0; st4 < 4; ++st4) {
+            B.ch[st4] = *reinterpret_cast<const bf8*>(srow + 4 * ((4 * g + st4) ^ col));
+            B.cl[st4] = *reinterpret_cast<const bf8*>(srow + 4 * ((16 + 4 * g + st4) ^ col));
+        }
+        B.cb = *reinterpret_cast<const f4*>(stage_cn + buf * kBStage + b * 16 + 4 * g) + beta;
+    };
+    auto mfmas = [&](const BBlock& B, f4 (&acc)[NB]) {
+#pragma unroll
+        for (int st4 = 0; st4 < 4; ++st4) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B.ch[st4], F.xh[nb][st4], st4 == 0 ? B.cb : acc[nb],
+                                                                  0, 0, 0);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B.ch[st4], F.xl[nb][st4], acc[nb], 0, 0, 0);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B.cl[st4], F.xh[nb][st4], acc[nb], 0, 0, 0);
+        }
+    };
+    // top-4 inserts of block blk's screen values; the key's low byte becomes
+    // the value's position in the epoch ((block in epoch) * 4 + r)
+    auto inserts = [&](int blk, const f4 (&acc)[NB]) {
+        const unsigned lb = (unsigned)(blk - epoch_first) * 4u;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                list_insert(el[nb], __uint_as_float(__builtin_amdgcn_perm(__float_as_uint(acc[nb][r]), lb + r,
+                                                                          0x07060500u)));
+    };
+    auto flush_if = [&](int blk) {
+        if (blk - epoch_first == kEpochBlocks - 1 || blk + 1 == nblk) {
+            epoch_flush<NB, float>(el, glist, k0 + (int64_t)epoch_first * 16 + 4 * g);
+            epoch_first = blk + 1;
+        }
+    };
+    // Before block blk = 4s + 3 (its region reads block 4s + 4's operands):
+    // publish stage s + 1 (its DMA was issued during stage s) and start the DMA
+    // of stage s + 2 into the buffer stage s - 1 used.
+    auto stage_turn = [&](int blk) {
+        if ((blk & 3) != 3) return;
+        const int sn = (blk >> 2) + 1;
+        if (sn >= nst) return;
+        if (threadIdx.x < kBStage) stage_cn[(sn % kBBufs) * kBStage + threadIdx.x] = pcn;
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (sn + 1 < nst) {
+            bf_stage_issue(chl, k0, kc, sn + 1, stage + ((sn + 1) % kBBufs) * kBStageWords, wave, lane);
+            if (threadIdx.x < kBStage) {
+                const int kk = (sn + 1) * kBStage + threadIdx.x;
+                pcn = kk < kc ? P.cn[k0 + kk] : kInvalid;
+            }
+        }
+    };
+
+    // Pipeline over the blocks: region(b) = MFMAs of b, operands of b + 1,
+    // inserts of b - 1.  Unrolled by two so that operand and accumulator
+    // sets alternate without copies.
+    BBlock BA, BB;
+    f4 accA[NB], accB[NB];
+    load_block(0, BA);
+    if (nblk == 1) {
+        mfmas(BA, accA);
+        inserts(0, accA);
+        flush_if(0);
+    } else {
+        load_block(1, BB);
+        mfmas(BA, accA);
+        for (int blk = 1;; ++blk) {
+            // odd block: operands BB -> accB, previous block in accA
+            stage_turn(blk);
+            if (blk + 1 >= nblk) {
+                mfmas(BB, accB);
+                inserts(blk - 1, accA);
+                flush_if(blk - 1);
+                inserts(blk, accB);
+                flush_if(blk);
+                break;
+            }
+            load_block(blk + 1, BA);
+            mfmas(BB, accB);
+            inserts(blk - 1, accA);
+            flush_if(blk - 1);
+            ++blk;
+            // even block: operands BA -> accA, previous block in accB
+            stage_turn(blk);
+            if (blk + 1 >= nblk) {
+                mfmas(BA, accA);
+                inserts(blk - 1, accB);
+                flush_if(blk - 1);
+                inserts(blk, accA);
+                flush_if(blk);
+                break;
+            }
+            load_block(blk + 1, BB);
+            mfmas(BA, accA);
+            inserts(blk - 1, accB);
+            flush_if(blk - 1);
+        }
+    }
+    finish_item<TAC_BF16, NB>(P, j, row0, s1, glist, beta, cnmax, cmax, g, col, lane);
+}
+
 template <int PREC>
-__global__ void __launch_bounds__(kThreads) assign_main(Params P) {
-    extern __shared__ unsigned lds[];
-    __shared__ unsigned long long s_item;
+__global__ void __launch_bounds__(PREC == TAC_BF16 ? kBThreads : kThreads) assign_main(Params P) {
+    // All shared memory is dynamic so that it starts 16-byte aligned (a static
+    // variable in front of it would shift every 16-byte LDS access off alignment).
+    extern __shared__ __attribute__((aligned(16))) unsigned lds[];
+    unsigned long long* s_item = reinterpret_cast<unsigned long long*>(
+        lds + (PREC == TAC_BF16 ? kBLdsBytes : kLdsBytes) / 4);
     const int64_t nclass = 3 * (int64_t)P.T;
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(P.work, 1ull);
+        if (threadIdx.x == 0) *s_item = atomicAdd(P.work, 1ull);
         __syncthreads();
-        const int64_t item = (int64_t)s_item;
+        const int64_t item = (int64_t)*s_item;
         __syncthreads();
         if (item >= P.item_off[nclass]) break;
         int64_t lo = 0, hi = nclass;  // largest idx with item_off[idx] <= item
@@ -548,10 +814,17 @@ __global__ void __launch_bounds__(kThreads) assign_main(Params P) {
         const int cls = (int)(lo / P.T);
         const int32_t j = (int32_t)(lo % P.T);
         const int64_t tile = item - P.item_off[lo];
-        if (cls == 2)
-            direct_item<PREC>(P, j, tile);
-        else
-            screen_item<PREC>(P, j, tile, lds);
+        if constexpr (PREC == TAC_BF16) {
+            if (cls == 2)
+                direct_item<kBThreads>(P, j, tile);
+            else
+                screen_item_bf16(P, j, tile, lds);
+        } else {
+            if (cls == 2)
+                direct_item<kThreads>(P, j, tile);
+            else
+                screen_item_fp32(P, j, tile, lds);
+        }
     }
 }
 
@@ -683,7 +956,6 @@ unsigned grid_for(int64_t work, int per_block) {
     return (unsigned)g;
 }
 
-constexpr size_t kLdsBytes = (kGlistOffsetWords + (size_t)kWaves * kNB * 8 * 64) * 4;
 
 }  // namespace
 
@@ -763,8 +1035,12 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
         seg = sseg;
         rowmap = in1 ? v1 : v0;
     }
+    const int threads = precision == TAC_BF16 ? kBThreads : kThreads;
+    // dynamic LDS: the kernel's tiles plus 16 bytes for the work-item slot
+    const size_t lds_bytes = (precision == TAC_BF16 ? kBLdsBytes : kLdsBytes) + 16;
     plan_count<<<grid_for(T, 256), 256, 0, s>>>(seg, cent_off_d, T, ctx->tuning.direct_max_kappa,
-                                                  ctx->tuning.heavy_kappa, cnt);
+                                                  ctx->tuning.heavy_kappa,
+                                                  precision == TAC_BF16 ? kBTileRows : kTileRows, threads, cnt);
     TAC_LAUNCH_CHECK("plan_count");
     st = exclusive_scan_i64(s, cnt, cnt, ncls, ws_at<void>(ctx, o_scan));
     if (st != TAC_OK) return st;
@@ -792,11 +1068,12 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     static int occ[2] = {0, 0};
     if (!occ[0]) {
         TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_FP32>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)kLdsBytes));
+                                    (int)(kLdsBytes + 16)));
         TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_BF16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)kLdsBytes));
-        TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], assign_main<TAC_FP32>, kThreads, kLdsBytes));
-        TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], assign_main<TAC_BF16>, kThreads, kLdsBytes));
+                                    (int)(kBLdsBytes + 16)));
+        TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], assign_main<TAC_FP32>, kThreads, kLdsBytes + 16));
+        TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], assign_main<TAC_BF16>, kBThreads,
+                                                             kBLdsBytes + 16));
         for (int i = 0; i < 2; ++i) occ[i] = occ[i] < 1 ? 1 : occ[i];
     }
     int per_cu = occ[precision == TAC_BF16 ? 1 : 0];
@@ -804,10 +1081,10 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     const unsigned grid = (unsigned)ctx->props_cu * (unsigned)per_cu;
     time_start(ctx, TAC_SLOT_ASSIGN);
     if (precision == TAC_FP32) {
-        assign_main<TAC_FP32><<<grid, kThreads, kLdsBytes, s>>>(P);
+        assign_main<TAC_FP32><<<grid, threads, lds_bytes, s>>>(P);
         TAC_LAUNCH_CHECK("assign_main<fp32>");
     } else {
-        assign_main<TAC_BF16><<<grid, kThreads, kLdsBytes, s>>>(P);
+        assign_main<TAC_BF16><<<grid, threads, lds_bytes, s>>>(P);
         TAC_LAUNCH_CHECK("assign_main<bf16>");
     }
     time_stop(ctx, TAC_SLOT_ASSIGN);

@@ -390,88 +390,88 @@ __device__ __forceinline__ void epoch_flush(Key (&el)[NB][4], unsigned* glist, i
     }
 }
 
-// End of a screened item: merge the four lane groups' lists of every row,
-// rescore nominee g with the canonical distance, keep the best, and certify it
-// with the screen's error bound (else queue the row for exhaustive rescoring).
+// End of a screened item: every lane takes whole rows.  A row's candidates
+// are the 16 entries of its four lane groups' top-4 lists (the lists of lane
+// (g, c) hold the best screen values among the columns that lane saw).  The
+// lane computes the canonical distance of the best-screened candidate, then of
+// every other candidate whose screen lower bound does not exclude it, keeps
+// the lexicographic (distance, index) minimum, and certifies it against every
+// candidate a list dropped: a dropped value is at least its list's 4th entry.
+// Rows whose certificate fails are queued for exhaustive rescoring.
 template <int PREC, int NB>
 __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t row0, int64_t s1,
-                                            const unsigned* glist, float beta, float cnmax, float cmax, int g,
-                                            int col, int lane) {
+                                            const unsigned* glist, float beta, float cnmax, float cmax, int lane) {
     const double u = 5.9604644775390625e-8;  // 2^-24
     const double g130 = 130.0 * u / (1.0 - 130.0 * u);
     const double g386 = 386.0 * u / (1.0 - 386.0 * u);
+    const double bt = (double)beta;
+    const double cm = (double)cmax, cn2 = (double)cnmax;
+    const unsigned* wlist = glist - lane;  // this wave's list slots: lane L's slot (nb, e) at (nb * 8 + e) * 64 + L
     int nscreen = 0;
+    for (int q = lane; q < NB * 16; q += 64) {
+        const int nb = q >> 4, c = q & 15;
+        const int64_t v = row0 + q;
+        if (v >= s1) continue;
+        ++nscreen;
+        // best screen value and the dropped-value bound over the four lane groups
+        float g0 = FLT_MAX, tau = FLT_MAX;
+        int i0 = -1;
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        float G[4];
-        int I[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            G[e] = __uint_as_float(glist[(nb * 8 + e) * 64]);
-            I[e] = (int)glist[(nb * 8 + 4 + e) * 64];
+        for (int g = 0; g < 4; ++g) {
+            const unsigned* sl = wlist + nb * 8 * 64 + 16 * g + c;
+            const float G0 = __uint_as_float(sl[0]);
+            const int I0 = (int)sl[4 * 64];
+            if (I0 >= 0 && (G0 < g0 || (G0 == g0 && I0 < i0))) {
+                g0 = G0;
+                i0 = I0;
+            }
+            tau = fminf(tau, __uint_as_float(sl[3 * 64]));
         }
-        // merge the four lanes that share a row (lane groups g = 0..3)
+        const int64_t r = P.rowmap ? (int64_t)P.rowmap[v] : v;
+        const float* xr = P.x + r * kDim;
+        bool ok = false;
+        float bd = INFINITY;
+        int bi = INT32_MAX;
+        if (i0 >= 0) {
+            float xxc;
+            bd = dist32_rows(xr, P.C + (int64_t)i0 * kDim, &xxc);
+            bi = i0;
+            // canonical ||x - c||^2 >= (screen - E - beta + ||x||^2) (1 - g130) for every candidate
+            const double xx_hi = (double)xxc * (1.0 + g130);
+            const double xx_lo = (double)xxc * (1.0 - g130);
+            const double xn = sqrt(xx_hi);
+            double E;
+            if constexpr (PREC == TAC_FP32)
+                E = 1.1 * (g130 * (2.0 * (cn2 + bt) + 2.0 * xn * cm));
+            else
+                E = 1.1 * (g386 * (2.0 * (cn2 + bt) + 2.2 * xn * cm) + 6.2 * 1.52587890625e-5 * xn * cm);
+            E += 1e-30;
+            const double shift = -E - bt + xx_lo;
+            for (int g = 0; g < 4; ++g) {
+                const unsigned* sl = wlist + nb * 8 * 64 + 16 * g + c;
 #pragma unroll
-        for (int m = 16; m <= 32; m <<= 1) {
-            float pt[4];
-            int pi[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                pt[e] = __shfl_xor(G[e], m);
-                pi[e] = __shfl_xor(I[e], m);
+                for (int e = 0; e < 4; ++e) {
+                    const int I = (int)sl[(4 + e) * 64];
+                    const double G = (double)__uint_as_float(sl[e * 64]);
+                    if (I < 0 || I == i0 || (G + shift) * (1.0 - g130) > (double)bd) continue;
+                    const float d = dist32_rows(xr, P.C + (int64_t)I * kDim, nullptr);
+                    if (d < bd || (d == bd && I < bi)) {
+                        bd = d;
+                        bi = I;
+                    }
+                }
             }
-#pragma unroll
-            for (int e = 0; e < 4; ++e) glist_insert(G, I, pt[e], pi[e], true);
+            ok = (double)tau >= 1.0e38 || ((double)tau + shift) * (1.0 - g130) > (double)bd;
         }
-        const int64_t v = row0 + nb * 16 + col;
-        const bool valid = v < s1;
-        const int64_t r = valid ? (P.rowmap ? (int64_t)P.rowmap[v] : v) : 0;
-        const int nom = g == 0 ? I[0] : g == 1 ? I[1] : g == 2 ? I[2] : I[3];
-        float d32 = INFINITY, xxc = 0.f;
-        if (valid && nom >= 0) d32 = dist32_rows(P.x + r * kDim, P.C + (int64_t)nom * kDim, &xxc);
-        if (valid && nom < 0) dist32_rows(P.x + r * kDim, P.x + r * kDim, &xxc);
-        float bd = d32;
-        int bi = nom < 0 ? INT32_MAX : nom;
-#pragma unroll
-        for (int m = 16; m <= 32; m <<= 1) {
-            const float od = __shfl_xor(bd, m);
-            const int oi = __shfl_xor(bi, m);
-            if (od < bd || (od == bd && oi < bi)) {
-                bd = od;
-                bi = oi;
-            }
-        }
-        const float xxs = __shfl(xxc, col);  // lane group 0 holds the canonical ||x||^2
-        if (valid && g == 0) {
-            ++nscreen;
-            const double tau = (double)G[3];
-            bool ok = tau >= 1.0e38;
-            if (!ok) {
-                const double xx_hi = (double)xxs * (1.0 + g130);
-                const double xx_lo = (double)xxs * (1.0 - g130);
-                const double xn = sqrt(xx_hi);
-                const double bt = (double)beta;
-                const double cm = (double)cmax, cn2 = (double)cnmax;
-                double E;
-                if constexpr (PREC == TAC_FP32)
-                    E = 1.1 * (g130 * (2.0 * (cn2 + bt) + 2.0 * xn * cm));
-                else
-                    E = 1.1 * (g386 * (2.0 * (cn2 + bt) + 2.2 * xn * cm) + 6.2 * 1.52587890625e-5 * xn * cm);
-                E += 1e-30;
-                const double L = (tau - E - bt + xx_lo) * (1.0 - g130);
-                ok = L > (double)bd;
-            }
-            if (ok) {
-                P.assign[r] = bi;
-                P.dist[r] = bd;
-            } else {
-                const unsigned long long q = atomicAdd(&P.counters[kCntFallback], 1ull);
-                P.fb[2 * q] = (int32_t)v;
-                P.fb[2 * q + 1] = j;
-            }
+        if (ok) {
+            P.assign[r] = bi;
+            P.dist[r] = bd;
+        } else {
+            const unsigned long long qf = atomicAdd(&P.counters[kCntFallback], 1ull);
+            P.fb[2 * qf] = (int32_t)v;
+            P.fb[2 * qf + 1] = j;
         }
     }
-    // per-wave counts (lanes of group 0 counted the valid rows)
     for (int m = 32; m > 0; m >>= 1) nscreen += __shfl_xor(nscreen, m);
     if (lane == 0 && nscreen) {
         atomicAdd(&P.counters[kCntRows], (unsigned long long)nscreen);
@@ -584,7 +584,7 @@ __device__ __forceinline__ void screen_item_fp32(const Params& P, int32_t j, int
         if (st + 1 < nst) store_stage(buf ^ 1, pf, pcn);
         __syncthreads();
     }
-    finish_item<TAC_FP32, NB>(P, j, row0, s1, glist, beta, cnmax, cmax, g, col, lane);
+    finish_item<TAC_FP32, NB>(P, j, row0, s1, glist, beta, cnmax, cmax, lane);
 }
 
 // ---- BF16 screen: 4 waves (one per SIMD) x 5 column blocks of 16 rows = 320 rows per item ----
@@ -789,7 +789,7 @@ __device__ __forceinline__ void screen_item_bf16(const Params& P, int32_t j, int
             flush_if(blk - 1);
         }
     }
-    finish_item<TAC_BF16, NB>(P, j, row0, s1, glist, beta, cnmax, cmax, g, col, lane);
+    finish_item<TAC_BF16, NB>(P, j, row0, s1, glist, beta, cnmax, cmax, lane);
 }
 
 template <int PREC>

@@ -168,13 +168,13 @@ __device__ __forceinline__ void list_insert(unsigned (&l)[4], unsigned p) {
     l[0] = min(l[0], p);
 }
 
-// The same running top-4 on keys held as floats: the keys are non-negative
-// finite floats, which order like their bit patterns, and med3 / min of floats
-// select one of their inputs exactly.  The empty slot is FLT_MAX.
+// The same running top-LK (LK <= 4) on keys held as floats: the keys are
+// non-negative finite floats, which order like their bit patterns, and med3 of
+// floats selects one of its inputs exactly.  The empty slot is FLT_MAX.
+template <int LK>
 __device__ __forceinline__ void list_insert(float (&l)[4], float p) {
-    l[3] = __builtin_amdgcn_fmed3f(l[2], l[3], p);
-    l[2] = __builtin_amdgcn_fmed3f(l[1], l[2], p);
-    l[1] = __builtin_amdgcn_fmed3f(l[0], l[1], p);
+#pragma unroll
+    for (int e = LK - 1; e >= 1; --e) l[e] = __builtin_amdgcn_fmed3f(l[e - 1], l[e], p);
     l[0] = __builtin_amdgcn_fmed3f(l[0], p, -FLT_MAX);  // min without an IEEE canonicalisation
 }
 __device__ __forceinline__ unsigned key_bits(unsigned k) { return k; }
@@ -186,17 +186,18 @@ __device__ __forceinline__ unsigned key_empty<unsigned>() { return 0xFFFFFFFFu; 
 template <>
 __device__ __forceinline__ float key_empty<float>() { return FLT_MAX; }
 
-// Insert (t, i) into the ascending list (G, I); `lex` breaks value ties by index.
+// Insert (t, i) into the ascending list (G, I) of length L; `lex` breaks value
+// ties by index.
+template <int L>
 __device__ __forceinline__ void glist_insert(float (&G)[4], int (&I)[4], float t, int i, bool lex) {
-    bool c[4];
+    bool c[L];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) c[e] = t < G[e] || (lex && t == G[e] && (unsigned)i < (unsigned)I[e]);
-    G[3] = c[2] ? G[2] : (c[3] ? t : G[3]);
-    I[3] = c[2] ? I[2] : (c[3] ? i : I[3]);
-    G[2] = c[1] ? G[1] : (c[2] ? t : G[2]);
-    I[2] = c[1] ? I[1] : (c[2] ? i : I[2]);
-    G[1] = c[0] ? G[0] : (c[1] ? t : G[1]);
-    I[1] = c[0] ? I[0] : (c[1] ? i : I[1]);
+    for (int e = 0; e < L; ++e) c[e] = t < G[e] || (lex && t == G[e] && (unsigned)i < (unsigned)I[e]);
+#pragma unroll
+    for (int e = L - 1; e >= 1; --e) {
+        G[e] = c[e - 1] ? G[e - 1] : (c[e] ? t : G[e]);
+        I[e] = c[e - 1] ? I[e - 1] : (c[e] ? i : I[e]);
+    }
     G[0] = c[0] ? t : G[0];
     I[0] = c[0] ? i : I[0];
 }
@@ -362,28 +363,28 @@ __device__ __forceinline__ void glist_init(unsigned* glist) {
 // Fold the epoch's packed keys into the merged lists and reset them.  A key's
 // low 8 bits are (16-block within the epoch) * 4 + r; ebase is the global index
 // of the epoch's first centroid plus 4g.
-template <int NB, class Key>
+template <int NB, int LK, class Key>
 __device__ __forceinline__ void epoch_flush(Key (&el)[NB][4], unsigned* glist, int64_t ebase) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         float G[4];
         int I[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < LK; ++e) {
             G[e] = __uint_as_float(glist[(nb * 8 + e) * 64]);
             I[e] = (int)glist[(nb * 8 + 4 + e) * 64];
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < LK; ++e) {
             const unsigned bits = key_bits(el[nb][e]);
             const float t = __uint_as_float(bits & ~0xFFu);
             const unsigned loc = bits & 0xFFu;
             const int gi = (int)(ebase + (int64_t)(loc >> 2) * 16 + (loc & 3u));
-            if (t < 1.0e38f) glist_insert(G, I, t, gi, false);
+            if (t < 1.0e38f) glist_insert<LK>(G, I, t, gi, false);
             el[nb][e] = key_empty<Key>();
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < LK; ++e) {
             glist[(nb * 8 + e) * 64] = __float_as_uint(G[e]);
             glist[(nb * 8 + 4 + e) * 64] = (unsigned)I[e];
         }
@@ -398,7 +399,7 @@ __device__ __forceinline__ void epoch_flush(Key (&el)[NB][4], unsigned* glist, i
 // the lexicographic (distance, index) minimum, and certifies it against every
 // candidate a list dropped: a dropped value is at least its list's 4th entry.
 // Rows whose certificate fails are queued for exhaustive rescoring.
-template <int PREC, int NB>
+template <int PREC, int NB, int LK>
 __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t row0, int64_t s1,
                                             const unsigned* glist, float beta, float cnmax, float cmax, int lane) {
     const double u = 5.9604644775390625e-8;  // 2^-24
@@ -425,7 +426,7 @@ __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t 
                 g0 = G0;
                 i0 = I0;
             }
-            tau = fminf(tau, __uint_as_float(sl[3 * 64]));
+            tau = fminf(tau, __uint_as_float(sl[(LK - 1) * 64]));
         }
         const int64_t r = P.rowmap ? (int64_t)P.rowmap[v] : v;
         const float* xr = P.x + r * kDim;
@@ -450,7 +451,7 @@ __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t 
             for (int g = 0; g < 4; ++g) {
                 const unsigned* sl = wlist + nb * 8 * 64 + 16 * g + c;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
+                for (int e = 0; e < LK; ++e) {
                     const int I = (int)sl[(4 + e) * 64];
                     const double G = (double)__uint_as_float(sl[e * 64]);
                     if (I < 0 || I == i0 || (G + shift) * (1.0 - g130) > (double)bd) continue;
@@ -577,14 +578,14 @@ __device__ __forceinline__ void screen_item_fp32(const Params& P, int32_t j, int
                 for (int r = 0; r < 4; ++r) list_insert(el[nb], (__float_as_uint(acc[nb][r]) & ~0xFFu) | (lb + r));
             const bool last = (blk16 + 1) * 16 >= kc;
             if (blk16 - epoch_first == kEpochBlocks - 1 || last) {
-                epoch_flush<NB, unsigned>(el, glist, k0 + (int64_t)epoch_first * 16 + 4 * g);
+                epoch_flush<NB, 4, unsigned>(el, glist, k0 + (int64_t)epoch_first * 16 + 4 * g);
                 epoch_first = blk16 + 1;
             }
         }
         if (st + 1 < nst) store_stage(buf ^ 1, pf, pcn);
         __syncthreads();
     }
-    finish_item<TAC_FP32, NB>(P, j, row0, s1, glist, beta, cnmax, cmax, lane);
+    finish_item<TAC_FP32, NB, 4>(P, j, row0, s1, glist, beta, cnmax, cmax, lane);
 }
 
 // ---- BF16 screen: 4 waves (one per SIMD) x 5 column blocks of 16 rows = 320 rows per item ----
@@ -600,6 +601,10 @@ __device__ __forceinline__ void screen_item_fp32(const Params& P, int32_t j, int
 constexpr int kBThreads = 256;
 constexpr int kBWaves = kBThreads / 64;
 constexpr int kBNB = 5;
+#ifndef TAC_BF16_LK
+#define TAC_BF16_LK 4
+#endif
+constexpr int kBLK = TAC_BF16_LK;                         // per-lane top-k list length
 constexpr int kBTileRows = kBWaves * kBNB * 16;
 constexpr int kBStage = 64;                               // centroids per stage
 constexpr int kBBufs = 3;                                 // stage buffers
@@ -716,12 +721,12 @@ __device__ __forceinline__ void screen_item_bf16(const Params& P, int32_t j, int
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                list_insert(el[nb], __uint_as_float(__builtin_amdgcn_perm(__float_as_uint(acc[nb][r]), lb + r,
+                list_insert<kBLK>(el[nb], __uint_as_float(__builtin_amdgcn_perm(__float_as_uint(acc[nb][r]), lb + r,
                                                                           0x07060500u)));
     };
     auto flush_if = [&](int blk) {
         if (blk - epoch_first == kEpochBlocks - 1 || blk + 1 == nblk) {
-            epoch_flush<NB, float>(el, glist, k0 + (int64_t)epoch_first * 16 + 4 * g);
+            epoch_flush<NB, kBLK, float>(el, glist, k0 + (int64_t)epoch_first * 16 + 4 * g);
             epoch_first = blk + 1;
         }
     };
@@ -789,7 +794,7 @@ __device__ __forceinline__ void screen_item_bf16(const Params& P, int32_t j, int
             flush_if(blk - 1);
         }
     }
-    finish_item<TAC_BF16, NB>(P, j, row0, s1, glist, beta, cnmax, cmax, lane);
+    finish_item<TAC_BF16, NB, kBLK>(P, j, row0, s1, glist, beta, cnmax, cmax, lane);
 }
 
 template <int PREC>

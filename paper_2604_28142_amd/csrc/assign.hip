@@ -2,7 +2,7 @@
 // to the nearest of token j's centroids.
 //
 // One persistent launch serves every token.  The work list holds one item per
-// (token, 512-row tile); items of tokens with many centroids come first, so the
+// (token, row tile); items of tokens with many centroids come first, so the
 // longest items start early.  Each item takes one of two routes, split at a
 // tunable kappa limit (default 4, at most 16):
 //
@@ -11,11 +11,13 @@
 // * screen (more centroids): the distance contraction ||c||^2 - 2 x.c runs on the
 //   matrix cores (FP32 v_mfma_f32_16x16x4f32, or BF16 v_mfma_f32_16x16x32_bf16
 //   on hi/lo splits of both operands), centroid tiles are staged through LDS,
-//   and every lane keeps a running top-4 of packed (screen value, index) keys
-//   with one min and three med3 per distance.  The four nominees of each row
-//   are rescored with the canonical FP32 distance; a rigorous bound on the
-//   screen error certifies that no other centroid can win, and rows whose
-//   certificate fails are queued for an exhaustive rescoring kernel.
+//   and every lane keeps a running top-k (4 for FP32, 3 for BF16) of packed
+//   (screen value, index) keys with one min and k - 1 med3 per distance.  At
+//   the end of an item each row's candidates (the lists of its four lanes) are
+//   rescored with the canonical FP32 distance where the screen bound cannot
+//   exclude them; a rigorous bound on the screen error certifies that no other
+//   centroid can win, and rows whose certificate fails are queued for a batched
+//   exhaustive rescoring kernel.
 //
 // The canonical distance is acc = 0; for i: t = x_i - c_i; acc = acc + t*t,
 // each operation rounded to float32 without fusion, so the result is the same
@@ -42,7 +44,6 @@ constexpr int kEpochBlocks = 64;                // 16-centroid blocks per packed
 constexpr int kDirectCap = 16;                  // most centroids a direct (screen-free) token may have
 constexpr float kInvalid = 3.0e38f;             // screen value of padding centroids
 constexpr unsigned kCntRows = 0, kCntScreened = 1, kCntFallback = 2, kCntUnassigned = 3;
-constexpr int kFbChunks = 16;                   // centroid chunks per fallback row
 // dynamic LDS of the assignment kernel: two centroid stages, their norms, then the
 // per-lane merged top-4 lists (value and index words) of every wave
 constexpr size_t kGlistOffsetWords = (size_t)2 * kStage * kRowWords + (size_t)2 * kStage;
@@ -78,15 +79,18 @@ __global__ void reset_call(unsigned long long* __restrict__ work, unsigned long 
     work[0] = 0;
     for (int i = 0; i < 4; ++i) counters[i] = 0;
     cstat[0] = 0;
+    cstat[1] = 0;
 }
 
 // ---- plan: item counts per (class, token) ----
 __global__ void plan_count(const int64_t* __restrict__ seg_off, const int64_t* __restrict__ cent_off, int32_t T,
-                           int direct_max, int heavy, int screen_rows, int direct_rows, int64_t* __restrict__ cnt) {
+                           int direct_max, int heavy, int screen_rows, int direct_rows, int64_t* __restrict__ cnt,
+                           unsigned* __restrict__ kmax) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= T) return;
     const int64_t n = seg_off[j + 1] - seg_off[j];
     const int64_t k = cent_off[j + 1] - cent_off[j];
+    if (n > 0 && k > 0) atomicMax(kmax, (unsigned)k);
     const int cls = (k == 0 || k <= direct_max) ? 2 : (k >= heavy ? 0 : 1);
     const int64_t rows = cls == 2 ? direct_rows : screen_rows;
     const int64_t tiles = (n + rows - 1) / rows;
@@ -346,7 +350,7 @@ __device__ __forceinline__ float load_x_frags(const Params& P, int64_t row0, int
     return xxmax;
 }
 
-// The merged (value, index) top-4 list of each row lives in wave-private LDS,
+// The merged (value, index) top-k list of each lane lives in wave-private LDS,
 // touched only at epoch ends and once per item: slot (nb, e) of a lane is
 // glist[(nb * 8 + e) * 64], values for e < 4 and indices for e >= 4.
 template <int NB>
@@ -392,12 +396,12 @@ __device__ __forceinline__ void epoch_flush(Key (&el)[NB][4], unsigned* glist, i
 }
 
 // End of a screened item: every lane takes whole rows.  A row's candidates
-// are the 16 entries of its four lane groups' top-4 lists (the lists of lane
+// are the entries of its four lane groups' top-LK lists (the lists of lane
 // (g, c) hold the best screen values among the columns that lane saw).  The
 // lane computes the canonical distance of the best-screened candidate, then of
 // every other candidate whose screen lower bound does not exclude it, keeps
 // the lexicographic (distance, index) minimum, and certifies it against every
-// candidate a list dropped: a dropped value is at least its list's 4th entry.
+// candidate a list dropped: a dropped value is at least its list's last entry.
 // Rows whose certificate fails are queued for exhaustive rescoring.
 template <int PREC, int NB, int LK>
 __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t row0, int64_t s1,
@@ -596,15 +600,15 @@ __device__ __forceinline__ void screen_item_fp32(const Params& P, int32_t j, int
 // at chunk ^ (r & 15) so that the fragment reads of 16 consecutive rows hit
 // distinct banks without padding.  The 16-centroid block loop is software
 // pipelined: while the matrix cores run block b, the wave reads block b + 1's
-// fragments from LDS and folds block b - 1's screen values into its top-4
+// fragments from LDS and folds block b - 1's screen values into its top-3
 // lists, so the three streams (matrix, LDS, vector) overlap.
 constexpr int kBThreads = 256;
 constexpr int kBWaves = kBThreads / 64;
 constexpr int kBNB = 5;
-#ifndef TAC_BF16_LK
-#define TAC_BF16_LK 4
-#endif
-constexpr int kBLK = TAC_BF16_LK;                         // per-lane top-k list length
+// Per-lane list length of the BF16 screen: a top-3 costs one med3 less per
+// screen value than a top-4; the certificate then fails on a few more rows
+// (their exhaustive rescoring is batched), which is the cheaper side of the trade.
+constexpr int kBLK = 3;
 constexpr int kBTileRows = kBWaves * kBNB * 16;
 constexpr int kBStage = 64;                               // centroids per stage
 constexpr int kBBufs = 3;                                 // stage buffers
@@ -713,7 +717,7 @@ __device__ __forceinline__ void screen_item_bf16(const Params& P, int32_t j, int
                 acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B.cl[st4], F.xh[nb][st4], acc[nb], 0, 0, 0);
         }
     };
-    // top-4 inserts of block blk's screen values; the key's low byte becomes
+    // top-k inserts of block blk's screen values; the key's low byte becomes
     // the value's position in the epoch ((block in epoch) * 4 + r)
     auto inserts = [&](int blk, const f4 (&acc)[NB]) {
         const unsigned lb = (unsigned)(blk - epoch_first) * 4u;
@@ -833,51 +837,106 @@ __global__ void __launch_bounds__(PREC == TAC_BF16 ? kBThreads : kThreads) assig
     }
 }
 
-// Exhaustive canonical rescoring of the rows whose certificate failed.  Work
-// item (row q, chunk c): a block scans chunk c of the row's token centroids and
-// folds its best (distance, index) into the row's 64-bit slot with atomicMin;
-// non-negative float bits in the high word order like the distances, so the
-// slot ends at the lexicographic minimum whatever the order of the blocks.
+// Exhaustive canonical rescoring of the rows whose certificate failed.  The
+// queue is cut into batches of kFbRows consecutive rows (rows of one work item
+// are queued together, so a batch mostly shares one token); a work item
+// (batch, chunk c) streams centroids [c * kFbChunk, (c + 1) * kFbChunk) of
+// each token in the batch once for all of that token's rows, whose x rows sit
+// in LDS.  Each row's best (distance, index) is folded into its 64-bit slot
+// with atomicMin; non-negative float bits in the high word order like the
+// distances, so the slot ends at the lexicographic minimum whatever the order
+// of the blocks.
+constexpr int kFbRows = 16;
+constexpr int kFbChunk = 512;
+
 __global__ void fb_init(const unsigned long long* __restrict__ counters, unsigned long long* __restrict__ slot) {
     const int64_t nfb = (int64_t)counters[kCntFallback];
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nfb; q += (int64_t)gridDim.x * blockDim.x)
         slot[q] = ~0ull;
 }
 
-__global__ void __launch_bounds__(256) fb_scan(const float* __restrict__ x, const int32_t* __restrict__ rowmap,
-                                               const int64_t* __restrict__ cent_off, const float* __restrict__ C,
-                                               const int32_t* __restrict__ fb,
-                                               const unsigned long long* __restrict__ counters,
-                                               unsigned long long* __restrict__ slot) {
-    __shared__ float xrow[kDim];
-    __shared__ unsigned long long red[256];
-    const int64_t total = (int64_t)counters[kCntFallback] * kFbChunks;
+__device__ __forceinline__ unsigned long long min_u64(unsigned long long a, unsigned long long b) { return a < b ? a : b; }
+
+__global__ void __launch_bounds__(256) fb_batch(const float* __restrict__ x, const int32_t* __restrict__ rowmap,
+                                                const int64_t* __restrict__ cent_off, const float* __restrict__ C,
+                                                const int32_t* __restrict__ fb,
+                                                const unsigned long long* __restrict__ counters,
+                                                const unsigned* __restrict__ kmax,
+                                                unsigned long long* __restrict__ slot) {
+    __shared__ float xs[kFbRows * kDim];
+    __shared__ int tj[kFbRows];
+    __shared__ unsigned long long red[kFbRows * 4];
+    const int64_t nfb = (int64_t)counters[kCntFallback];
+    const int64_t nbatch = (nfb + kFbRows - 1) / kFbRows;
+    const int64_t nchunk = ((int64_t)kmax[0] + kFbChunk - 1) / kFbChunk;
+    const int64_t total = nbatch * nchunk;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-        const int64_t q = w / kFbChunks;
-        const int c = (int)(w % kFbChunks);
-        const int64_t v = fb[2 * q];
-        const int32_t j = fb[2 * q + 1];
-        const int64_t r = rowmap ? (int64_t)rowmap[v] : v;
-        __syncthreads();
-        if (threadIdx.x < kDim) xrow[threadIdx.x] = x[r * kDim + threadIdx.x];
-        __syncthreads();
-        const int64_t k0 = cent_off[j];
-        const int64_t kc = cent_off[j + 1] - k0;
-        const int64_t lo = k0 + kc * c / kFbChunks, hi = k0 + kc * (c + 1) / kFbChunks;
-        unsigned long long best = ~0ull;
-        for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-            const float d = dist32_rows(xrow, C + k * kDim, nullptr);
-            const unsigned long long key = ((unsigned long long)__float_as_uint(d) << 32) | (unsigned)k;
-            best = key < best ? key : best;
+        const int64_t b = w / nchunk;
+        const int64_t chunk = w % nchunk;
+        const int64_t q0 = b * kFbRows;
+        const int nq = (int)min((int64_t)kFbRows, nfb - q0);
+        __syncthreads();  // the previous work item is done with xs, tj and red
+        for (int e = threadIdx.x; e < nq * kDim; e += blockDim.x) {
+            const int rr = e / kDim;
+            const int64_t v = fb[2 * (q0 + rr)];
+            const int64_t r = rowmap ? (int64_t)rowmap[v] : v;
+            xs[e] = x[r * kDim + (e % kDim)];
         }
-        red[threadIdx.x] = best;
+        if ((int)threadIdx.x < nq) tj[threadIdx.x] = fb[2 * (q0 + threadIdx.x) + 1];
         __syncthreads();
-        for (int off = 128; off > 0; off >>= 1) {
-            if (threadIdx.x < off) red[threadIdx.x] = red[threadIdx.x + off] < red[threadIdx.x] ? red[threadIdx.x + off]
-                                                                                             : red[threadIdx.x];
-            __syncthreads();
+        unsigned long long best[kFbRows];
+#pragma unroll
+        for (int r = 0; r < kFbRows; ++r) best[r] = ~0ull;
+        for (int r0 = 0; r0 < nq;) {  // groups of consecutive rows with one token
+            const int jt = tj[r0];
+            int r1 = r0 + 1;
+            while (r1 < nq && tj[r1] == jt) ++r1;
+            const int64_t k1 = cent_off[jt + 1];
+            const int64_t lo = cent_off[jt] + chunk * kFbChunk;
+            const int64_t hi = min(k1, lo + kFbChunk);
+            for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+                float acc[kFbRows];
+#pragma unroll
+                for (int r = 0; r < kFbRows; ++r) acc[r] = 0.f;
+                const float4* cv = reinterpret_cast<const float4*>(C + k * kDim);
+                for (int i4 = 0; i4 < kDim / 4; ++i4) {
+                    const float4 c4 = cv[i4];
+#pragma unroll
+                    for (int r = 0; r < kFbRows; ++r) {
+                        if (r >= r0 && r < r1) {
+                            const float4 a = *reinterpret_cast<const float4*>(xs + r * kDim + 4 * i4);
+                            float t;
+                            t = a.x - c4.x; acc[r] = acc[r] + t * t;
+                            t = a.y - c4.y; acc[r] = acc[r] + t * t;
+                            t = a.z - c4.z; acc[r] = acc[r] + t * t;
+                            t = a.w - c4.w; acc[r] = acc[r] + t * t;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < kFbRows; ++r)
+                    if (r >= r0 && r < r1)
+                        best[r] = min_u64(best[r], ((unsigned long long)__float_as_uint(acc[r]) << 32) | (unsigned)k);
+            }
+            r0 = r1;
         }
-        if (threadIdx.x == 0 && red[0] != ~0ull) atomicMin(&slot[q], red[0]);
+#pragma unroll
+        for (int r = 0; r < kFbRows; ++r) {
+            unsigned long long m = best[r];
+            for (int o = 32; o > 0; o >>= 1) {
+                const unsigned lo32 = __shfl_xor((unsigned)(m & 0xFFFFFFFFull), o);
+                const unsigned hi32 = __shfl_xor((unsigned)(m >> 32), o);
+                m = min_u64(m, ((unsigned long long)hi32 << 32) | lo32);
+            }
+            if (lane == 0) red[r * 4 + wave] = m;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < nq) {
+            unsigned long long m = red[threadIdx.x * 4];
+            for (int wv = 1; wv < 4; ++wv) m = min_u64(m, red[threadIdx.x * 4 + wv]);
+            if (m != ~0ull) atomicMin(&slot[q0 + threadIdx.x], m);
+        }
     }
 }
 
@@ -1045,7 +1104,8 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     const size_t lds_bytes = (precision == TAC_BF16 ? kBLdsBytes : kLdsBytes) + 16;
     plan_count<<<grid_for(T, 256), 256, 0, s>>>(seg, cent_off_d, T, ctx->tuning.direct_max_kappa,
                                                   ctx->tuning.heavy_kappa,
-                                                  precision == TAC_BF16 ? kBTileRows : kTileRows, threads, cnt);
+                                                  precision == TAC_BF16 ? kBTileRows : kTileRows, threads, cnt,
+                                                  cstat + 1);
     TAC_LAUNCH_CHECK("plan_count");
     st = exclusive_scan_i64(s, cnt, cnt, ncls, ws_at<void>(ctx, o_scan));
     if (st != TAC_OK) return st;
@@ -1096,8 +1156,9 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     unsigned long long* slot = ws_at<unsigned long long>(ctx, o_slot);
     fb_init<<<(unsigned)ctx->props_cu, 256, 0, s>>>(ctx->counters, slot);
     TAC_LAUNCH_CHECK("fb_init");
-    fb_scan<<<(unsigned)ctx->props_cu * 4, 256, 0, s>>>(x_d, rowmap, cent_off_d, C_d, P.fb, ctx->counters, slot);
-    TAC_LAUNCH_CHECK("fb_scan");
+    fb_batch<<<(unsigned)ctx->props_cu * 4, 256, 0, s>>>(x_d, rowmap, cent_off_d, C_d, P.fb, ctx->counters, cstat + 1,
+                                                       slot);
+    TAC_LAUNCH_CHECK("fb_batch");
     fb_final<<<(unsigned)ctx->props_cu, 256, 0, s>>>(rowmap, P.fb, ctx->counters, slot, assign_d, dist);
     TAC_LAUNCH_CHECK("fb_final");
     if (inertia_d) {

@@ -328,7 +328,7 @@ def main():
                    "timed_region_ms": wall},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["bf16"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK["bf16"], "traffic": measured_traffic(args.config),
-                     "kernel": "assign_main<bf16> (persistent screen + top-4 + certificate)"},
+                     "kernel": "assign_main<bf16> (persistent screen + per-lane top-3 + certificate)"},
         "cpu_baseline": cpu,
         **extra,
     }

@@ -9,6 +9,7 @@
 // each subspace by code, and average every code's members in float64 in that
 // fixed order (codes with no member keep their value).
 #include <algorithm>
+#include <cfloat>
 
 #include "tac_internal.h"
 
@@ -232,6 +233,193 @@ __global__ void __launch_bounds__(512) train_encode(const float* __restrict__ R,
     }
 }
 
+// ---- matrix-core PQ encoding (M = 32 subspaces, ksub a multiple of 16) ----
+// For subspace m the screen values ||b||^2 + beta - 2 u.b of 16 codes x 16 rows
+// come from one v_mfma_f32_16x16x4f32 (the four coordinates of the subspace
+// are the contraction): lane (g, col) supplies coordinate g of code 16 t + col
+// and of row col, and receives codes 16 t + 4 g + r of row col.  Each lane
+// keeps a top-2 of packed keys over its 64 codes; the four lanes of a row then
+// rescore their candidates with the canonical distance, take the
+// lexicographic minimum and certify it against every code a list dropped
+// (that value is at least the list's second entry); a row that fails is
+// scanned exhaustively.  Codes are bitwise those of the scalar screen.
+// Rows: 8 waves x 4 blocks of 16 rows per block iteration, codebooks in LDS.
+constexpr int kEThreads = 512;
+constexpr int kENB = 4;
+constexpr int kERows = (kEThreads / 64) * kENB * 16;
+static_assert(kENB * 16 == 64, "one prologue row per lane");
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void top2_insert(float& l0, float& l1, float p) {
+    l1 = __builtin_amdgcn_fmed3f(l0, l1, p);
+    l0 = __builtin_amdgcn_fmed3f(l0, p, -FLT_MAX);
+}
+
+template <bool RESID>
+__global__ void __launch_bounds__(kEThreads) encode_screen(const float* __restrict__ x,
+                                                           const int32_t* __restrict__ assign,
+                                                           const float* __restrict__ C, int64_t K, int64_t n,
+                                                           int normalize, const float* __restrict__ cbg, int ksub,
+                                                           uint8_t* __restrict__ codes_rows,
+                                                           uint32_t* __restrict__ codes_sub,
+                                                           float* __restrict__ rnorm) {
+    constexpr int M = kDim / kDsub;
+    extern __shared__ float4 lds4[];
+    float4* lcb = lds4;
+    float* lcn = reinterpret_cast<float*>(lds4 + M * ksub);
+    const float cnmax = load_codebooks_norms(cbg, M, ksub, lcb, lcn);
+    const float* lcbf = reinterpret_cast<const float*>(lcb);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
+    const double uc = 5.9604644775390625e-8;  // 2^-24
+    const double g6 = 6.0 * uc / (1.0 - 6.0 * uc);
+    const double g10 = 10.0 * uc / (1.0 - 10.0 * uc);
+    const double cm2 = (double)cnmax * (1.0 + 1e-5);
+    const int nt = ksub / 16;
+    for (int64_t base = (int64_t)blockIdx.x * kERows; base < n; base += (int64_t)gridDim.x * kERows) {
+        const int64_t wbase = base + wave * (kENB * 16);
+        // lane-per-row prologue: validity, centroid and canonical residual norm
+        const int64_t myrow = wbase + lane;
+        int a = -1;
+        float rho = 0.f;
+        int ok_row = 0;
+        if (myrow < n) {
+            if constexpr (RESID) {
+                a = assign[myrow];
+                ok_row = a >= 0 && a < K;
+                if (ok_row) rho = residual_norm(x + myrow * kDim, C + (int64_t)a * kDim);
+                if (rnorm) rnorm[myrow] = rho;
+            } else {
+                ok_row = 1;
+            }
+        }
+        int arow[kENB], vrow[kENB];
+        float rrow[kENB];
+        uint32_t word[kENB];
+#pragma unroll
+        for (int nb = 0; nb < kENB; ++nb) {
+            arow[nb] = __shfl(a, nb * 16 + col);
+            rrow[nb] = __shfl(rho, nb * 16 + col);
+            vrow[nb] = __shfl(ok_row, nb * 16 + col);
+            word[nb] = 0u;
+        }
+        for (int m = 0; m < M; ++m) {
+            float u[kENB], um = 0.f;
+#pragma unroll
+            for (int nb = 0; nb < kENB; ++nb) {
+                const int64_t row = wbase + nb * 16 + col;
+                float v = 0.f;
+                if (vrow[nb]) {
+                    if constexpr (RESID) {
+                        v = __fsub_rn(x[row * kDim + kDsub * m + g], C[(int64_t)arow[nb] * kDim + kDsub * m + g]);
+                        if (normalize) v = rrow[nb] > 0.f ? __fdiv_rn(v, rrow[nb]) : 0.f;
+                    } else {
+                        v = x[row * kDim + kDsub * m + g];
+                    }
+                }
+                u[nb] = v;
+                float sq = v * v;
+                sq += __shfl_xor(sq, 16);
+                sq += __shfl_xor(sq, 32);
+                um = fmaxf(um, sq);
+            }
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) um = fmaxf(um, __shfl_xor(um, o));
+            // one shift per wave and subspace: beta >= ||u||^2 + (screen error) for each of its rows
+            const float beta = um * (1.0f + 0.00390625f) + 0.00390625f * cnmax + 1e-30f;
+            float l0[kENB], l1[kENB];
+#pragma unroll
+            for (int nb = 0; nb < kENB; ++nb) {
+                l0[nb] = FLT_MAX;
+                l1[nb] = FLT_MAX;
+            }
+            const float* cbm = lcbf + (size_t)m * ksub * kDsub;
+            const float* cnm = lcn + (size_t)m * ksub;
+            for (int t = 0; t < nt; ++t) {
+                const float af = cbm[(16 * t + col) * kDsub + g];
+                const f4 ci = *reinterpret_cast<const f4*>(cnm + 16 * t + 4 * g) + beta;
+#pragma unroll
+                for (int nb = 0; nb < kENB; ++nb) {
+                    const f4 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af, -2.0f * u[nb], ci, 0, 0, 0);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        top2_insert(l0[nb], l1[nb],
+                                    __uint_as_float(__builtin_amdgcn_perm(__float_as_uint(acc[r]),
+                                                                          (unsigned)(16 * t + 4 * g + r), 0x07060500u)));
+                }
+            }
+#pragma unroll
+            for (int nb = 0; nb < kENB; ++nb) {
+                // the row's subvector in every lane of the row
+                float4 uv;
+                uv.x = __shfl(u[nb], col);
+                uv.y = __shfl(u[nb], 16 + col);
+                uv.z = __shfl(u[nb], 32 + col);
+                uv.w = __shfl(u[nb], 48 + col);
+                const unsigned k0 = __float_as_uint(l0[nb]), k1 = __float_as_uint(l1[nb]);
+                float bd = INFINITY;
+                int bi = INT32_MAX;
+                if (k0 != __float_as_uint(FLT_MAX)) {
+                    bd = dist4(uv, lcb[(size_t)m * ksub + (k0 & 0xFFu)]);
+                    bi = (int)(k0 & 0xFFu);
+                }
+                if (k1 != __float_as_uint(FLT_MAX)) {
+                    const float d = dist4(uv, lcb[(size_t)m * ksub + (k1 & 0xFFu)]);
+                    if (d < bd || (d == bd && (int)(k1 & 0xFFu) < bi)) {
+                        bd = d;
+                        bi = (int)(k1 & 0xFFu);
+                    }
+                }
+                float tau = __uint_as_float(k1 & ~0xFFu);
+#pragma unroll
+                for (int o = 16; o <= 32; o <<= 1) {
+                    const float od = __shfl_xor(bd, o);
+                    const int oi = __shfl_xor(bi, o);
+                    if (od < bd || (od == bd && oi < bi)) {
+                        bd = od;
+                        bi = oi;
+                    }
+                    tau = fminf(tau, __shfl_xor(tau, o));
+                }
+                // canonical ||u||^2 and the screen's error bound
+                float ucan = __fmul_rn(uv.x, uv.x);
+                ucan = __fadd_rn(ucan, __fmul_rn(uv.y, uv.y));
+                ucan = __fadd_rn(ucan, __fmul_rn(uv.z, uv.z));
+                ucan = __fadd_rn(ucan, __fmul_rn(uv.w, uv.w));
+                const double un = sqrt((double)ucan * (1.0 + g6));
+                const double bt = (double)beta;
+                const double E = 1.1 * g10 * (2.0 * (cm2 + bt) + 2.0 * un * sqrt(cm2)) + 1e-30;
+                const double L = ((double)tau - E - bt + (double)ucan * (1.0 - g6)) * (1.0 - g6);
+                int code = bi;
+                if (!((double)tau >= 1.0e38 || L > (double)bd)) {
+                    float best = INFINITY;
+                    code = 0;
+                    for (int b = 0; b < ksub; ++b) {
+                        const float d = dist4(uv, lcb[(size_t)m * ksub + b]);
+                        if (d < best) {
+                            best = d;
+                            code = b;
+                        }
+                    }
+                }
+                if (!vrow[nb]) code = 0;
+                const int64_t row = wbase + nb * 16 + col;
+                if constexpr (RESID) {
+                    word[nb] |= (uint32_t)code << (8 * (m & 3));
+                    if ((m & 3) == 3) {
+                        if (g == 0 && row < n) reinterpret_cast<uint32_t*>(codes_rows + row * M)[m >> 2] = word[nb];
+                        word[nb] = 0u;
+                    }
+                } else {
+                    if (g == 0 && row < n) codes_sub[(int64_t)m * n + row] = (uint32_t)code;
+                }
+            }
+        }
+    }
+}
+
+bool g_attr_screen[2] = {false, false};
+
 // off[b] = first sorted position with code >= b, b in [0, ksub]
 __global__ void code_offsets(const uint32_t* __restrict__ keys, int64_t n, int ksub, int64_t* __restrict__ off) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -331,11 +519,25 @@ extern "C" tac_status pq_encode(tac_ctx ctx, const float* x_d, const int32_t* as
                                     (int)kMaxCodebookLds));
         g_attr_encode = true;
     }
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 511) / 512, (int64_t)ctx->props_cu));
     time_start(ctx, TAC_SLOT_ENCODE);
-    encode_kernel<<<grid, 512, lds, ctx->stream>>>(x_d, assign_d, C_d, K, n, normalize, codebooks_d, M, ksub, codes_d,
-                                                   rnorm_d);
-    TAC_LAUNCH_CHECK("encode_kernel");
+    if (ksub % 16 == 0) {
+        if (!g_attr_screen[0]) {
+            TAC_HIP(hipFuncSetAttribute((const void*)encode_screen<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)kMaxCodebookLds));
+            g_attr_screen[0] = true;
+        }
+        const unsigned grid =
+            (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kERows - 1) / kERows, (int64_t)ctx->props_cu));
+        encode_screen<true><<<grid, kEThreads, lds, ctx->stream>>>(x_d, assign_d, C_d, K, n, normalize, codebooks_d,
+                                                                   ksub, codes_d, nullptr, rnorm_d);
+        TAC_LAUNCH_CHECK("encode_screen");
+    } else {
+        const unsigned grid =
+            (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 511) / 512, (int64_t)ctx->props_cu));
+        encode_kernel<<<grid, 512, lds, ctx->stream>>>(x_d, assign_d, C_d, K, n, normalize, codebooks_d, M, ksub,
+                                                       codes_d, rnorm_d);
+        TAC_LAUNCH_CHECK("encode_kernel");
+    }
     time_stop(ctx, TAC_SLOT_ENCODE);
     return TAC_OK;
 }
@@ -370,14 +572,24 @@ extern "C" tac_status pq_train(tac_ctx ctx, const float* R_d, int64_t n, int32_t
     if (!g_attr_train) {
         TAC_HIP(hipFuncSetAttribute((const void*)train_encode, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)kMaxCodebookLds));
+        TAC_HIP(hipFuncSetAttribute((const void*)encode_screen<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kMaxCodebookLds));
         g_attr_train = true;
     }
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 511) / 512, (int64_t)ctx->props_cu));
     const size_t lds = (size_t)M * ksub * (kDsub + 1) * sizeof(float);
     for (int it = 0; it < iters && n > 0; ++it) {
         TAC_HIP(hipMemcpyAsync(cur, codebooks_d, cb_bytes, hipMemcpyDeviceToDevice, s));
-        train_encode<<<grid, 512, lds, s>>>(R_d, n, cur, M, ksub, codes);
-        TAC_LAUNCH_CHECK("train_encode");
+        if (ksub % 16 == 0) {
+            const unsigned sgrid =
+                (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kERows - 1) / kERows, (int64_t)ctx->props_cu));
+            encode_screen<false><<<sgrid, kEThreads, lds, s>>>(R_d, nullptr, nullptr, 0, n, 0, cur, ksub, nullptr,
+                                                               codes, nullptr);
+            TAC_LAUNCH_CHECK("encode_screen");
+        } else {
+            train_encode<<<grid, 512, lds, s>>>(R_d, n, cur, M, ksub, codes);
+            TAC_LAUNCH_CHECK("train_encode");
+        }
         for (int m = 0; m < M; ++m) {
             uint32_t* keys = codes + (int64_t)m * n;  // sorted in place (ping-pong with k1)
             int in1 = 0;

@@ -218,3 +218,49 @@ def test_autotune_cache_roundtrip(ctx, tmp_path):
         check_assign(c.xs, c.seg_off, c.C0, c.cent_off, a, dd, fp64=False)
     finally:
         ctx.set_tuning(**before)
+
+
+@pytest.mark.parametrize("ksub", [16, 48, 20, 1, 256])
+@pytest.mark.parametrize("normalize", [True, False])
+def test_pq_encode_shapes_and_invalid_rows(ctx, ksub, normalize):
+    """Both encode kernels (matrix-core screen for ksub % 16 == 0, scalar
+    otherwise) on ragged row counts, with rows whose assignment is out of range."""
+    rng = np.random.default_rng(100 + ksub)
+    n, K = 1000 + ksub, 37
+    x = clustered(rng, n, 9)
+    C = x[rng.choice(n, K, replace=False)].copy()
+    a = rng.integers(0, K, n).astype(np.int32)
+    a[:5] = -1
+    a[5:9] = K + 2
+    cb = (0.25 * rng.standard_normal((32, ksub, 4))).astype(np.float32)
+    codes = torch.empty((n, 32), dtype=torch.uint8, device="cuda")
+    rho = torch.empty(n, dtype=torch.float32, device="cuda")
+    tac.pq_encode(ctx, dev(x), dev(a), dev(C), dev(cb), codes, normalize=normalize, rnorm=rho)
+    ok = (a >= 0) & (a < K)
+    u32, rho32 = oracle.residuals(x[ok], C[a[ok]], normalize=normalize, mode="fp32")
+    exp = oracle.pq_encode(u32, cb, decide="fp32")
+    got = host(codes)
+    assert np.array_equal(got[ok], exp)
+    assert np.all(got[~ok] == 0) and np.all(host(rho)[~ok] == 0)
+    assert np.array_equal(host(rho)[ok], rho32)
+
+
+def test_pq_encode_ties_and_fallback(ctx):
+    """Duplicate codes tie exactly (the lowest code wins); a codebook of nearly
+    equal codes defeats the screen's certificate and is scanned exhaustively."""
+    rng = np.random.default_rng(21)
+    n, K, ksub = 700, 5, 64
+    x = clustered(rng, n, 5)
+    C = x[:K].copy()
+    a = rng.integers(0, K, n).astype(np.int32)
+    cb = (0.3 * rng.standard_normal((32, ksub, 4))).astype(np.float32)
+    base = (0.3 * rng.standard_normal((4,))).astype(np.float32)
+    cb[7] = base + (1e-7 * rng.standard_normal((ksub, 4))).astype(np.float32)   # near-ties in subspace 7
+    cb[:, 40] = cb[:, 3]                                   # exact duplicates: code 3 must win over 40
+    codes = torch.empty((n, 32), dtype=torch.uint8, device="cuda")
+    tac.pq_encode(ctx, dev(x), dev(a), dev(C), dev(cb), codes)
+    u32, _ = oracle.residuals(x, C[a], mode="fp32")
+    exp = oracle.pq_encode(u32, cb, decide="fp32")
+    got = host(codes)
+    assert np.array_equal(got, exp)
+    assert not np.any(got == 40)

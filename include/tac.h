@@ -95,7 +95,7 @@ tac_status tac_ctx_set_stream(tac_ctx ctx, void* hip_stream);
 /* Kernel timing (measurement aid).  When enabled, each entry point records HIP
  * events on the context's stream around its dominant kernel, one slot each:
  *  TAC_SLOT_ASSIGN  the persistent assignment kernel of tac_assign
- *  TAC_SLOT_UPDATE  the centroid-mean kernel of tac_update
+ *  TAC_SLOT_UPDATE  the centroid-mean kernels of tac_update (flags + means)
  *  TAC_SLOT_ENCODE  the fused residual + PQ encode kernel of pq_encode
  * tac_kernel_ms waits for the slot's stop event and returns the elapsed time of
  * its last recording (TAC_E_INVAL if never recorded).  Keep timing disabled

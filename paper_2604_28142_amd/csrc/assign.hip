@@ -22,6 +22,7 @@
 // The canonical distance is acc = 0; for i: t = x_i - c_i; acc = acc + t*t,
 // each operation rounded to float32 without fusion, so the result is the same
 // for the FP32 and BF16 screens and independent of tile shapes.
+#include <algorithm>
 #include <cfloat>
 
 #include "tac_internal.h"
@@ -1110,7 +1111,9 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     st = exclusive_scan_i64(s, cnt, cnt, ncls, ws_at<void>(ctx, o_scan));
     if (st != TAC_OK) return st;
     if (K > 0) {
-        prep_centroids<<<grid_for(K * 32, 256), 256, 0, s>>>(C_d, K, cn, cstat, chl);
+        // a grid-stride launch of a few blocks per CU keeps the per-block atomicMax on the norm bound cheap
+        const unsigned pgrid = std::min<unsigned>(grid_for(K * 32, 256), (unsigned)ctx->props_cu * 4);
+        prep_centroids<<<pgrid, 256, 0, s>>>(C_d, K, cn, cstat, chl);
         TAC_LAUNCH_CHECK("prep_centroids");
     }
     Params P;

@@ -29,8 +29,31 @@ __global__ void member_offsets(const uint32_t* __restrict__ keys, int64_t n, int
     }
 }
 
-__global__ void __launch_bounds__(256) centroid_means(const float* __restrict__ xs, const int64_t* __restrict__ seg_off,
-                                                      int32_t T, const int32_t* __restrict__ rows,
+constexpr int kUnroll = 8;
+
+// wide[k] = 1 when centroid k's token has more than kFp64Rows rows (the token is
+// found from the centroid's first member); one thread per centroid, so the
+// dependent searches of all centroids overlap.
+__global__ void centroid_flags(const int64_t* __restrict__ seg_off, int32_t T, const int32_t* __restrict__ rows,
+                               const int64_t* __restrict__ off, int64_t K, uint8_t* __restrict__ wide) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = off[k];
+        if (b == off[k + 1]) {
+            wide[k] = 0;
+            continue;
+        }
+        const int64_t r0 = rows[b];
+        int32_t lo = 0, hi = T;
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (seg_off[mid] <= r0) lo = mid; else hi = mid;
+        }
+        wide[k] = seg_off[lo + 1] - seg_off[lo] > kFp64Rows ? 1 : 0;
+    }
+}
+
+__global__ void __launch_bounds__(256) centroid_means(const float* __restrict__ xs, const uint8_t* __restrict__ wide_k,
+                                                      const int32_t* __restrict__ rows,
                                                       const int64_t* __restrict__ off, int64_t K,
                                                       const float* __restrict__ C_old, float* __restrict__ C_new,
                                                       int64_t* __restrict__ count) {
@@ -46,36 +69,45 @@ __global__ void __launch_bounds__(256) centroid_means(const float* __restrict__ 
             out[lane] = reinterpret_cast<const float2*>(C_old + k * kDim)[lane];
             continue;
         }
-        // the token of this centroid: the segment holding its first member row
-        const int64_t r0 = rows[b];
-        int32_t lo = 0, hi = T;
-        while (hi - lo > 1) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (seg_off[mid] <= r0) lo = mid; else hi = mid;
-        }
-        const bool wide = seg_off[lo + 1] - seg_off[lo] > kFp64Rows;
+        const bool wide = wide_k[k] != 0;
         float2 mean;
+        // members are summed in sorted order; the rows of kUnroll members are
+        // loaded before they are added, so that many loads are in flight per wave
         if (wide) {
             double s0 = 0.0, s1 = 0.0;
-            for (int64_t p = b; p < e; ++p) {
-                const float2 v = reinterpret_cast<const float2*>(xs + (int64_t)rows[p] * kDim)[lane];
-                s0 += (double)v.x;
-                s1 += (double)v.y;
+            for (int64_t p = b; p < e; p += kUnroll) {
+                float2 v[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    if (p + u < e) v[u] = reinterpret_cast<const float2*>(xs + (int64_t)rows[p + u] * kDim)[lane];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    if (p + u < e) {
+                        s0 += (double)v[u].x;
+                        s1 += (double)v[u].y;
+                    }
             }
             mean.x = (float)(s0 / (double)cnt);
             mean.y = (float)(s1 / (double)cnt);
         } else {
             float s0 = 0.f, s1 = 0.f, c0 = 0.f, c1 = 0.f;
-            for (int64_t p = b; p < e; ++p) {
-                const float2 v = reinterpret_cast<const float2*>(xs + (int64_t)rows[p] * kDim)[lane];
-                float y = __fsub_rn(v.x, c0);
-                float t = __fadd_rn(s0, y);
-                c0 = __fsub_rn(__fsub_rn(t, s0), y);
-                s0 = t;
-                y = __fsub_rn(v.y, c1);
-                t = __fadd_rn(s1, y);
-                c1 = __fsub_rn(__fsub_rn(t, s1), y);
-                s1 = t;
+            for (int64_t p = b; p < e; p += kUnroll) {
+                float2 v[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    if (p + u < e) v[u] = reinterpret_cast<const float2*>(xs + (int64_t)rows[p + u] * kDim)[lane];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    if (p + u >= e) break;
+                    float y = __fsub_rn(v[u].x, c0);
+                    float t = __fadd_rn(s0, y);
+                    c0 = __fsub_rn(__fsub_rn(t, s0), y);
+                    s0 = t;
+                    y = __fsub_rn(v[u].y, c1);
+                    t = __fadd_rn(s1, y);
+                    c1 = __fsub_rn(__fsub_rn(t, s1), y);
+                    s1 = t;
+                }
             }
             const float fc = (float)cnt;
             mean.x = __fdiv_rn(__fsub_rn(s0, c0), fc);
@@ -116,6 +148,7 @@ extern "C" tac_status tac_update(tac_ctx ctx, const float* xs_d, const int64_t* 
     const size_t o_k1 = cv.take<uint32_t>(N + 1), o_v1 = cv.take<int32_t>(N + 1);
     const size_t o_sort = cv.take<char>(radix_sort_scratch_bytes(N));
     const size_t o_off = cv.take<int64_t>(K + 1);
+    const size_t o_wide = cv.take<uint8_t>(K + 1);
     tac_status st = ws_reserve(ctx, cv.off);
     if (st != TAC_OK) return st;
     uint32_t* k0 = ws_at<uint32_t>(ctx, o_k0);
@@ -135,8 +168,10 @@ extern "C" tac_status tac_update(tac_ctx ctx, const float* xs_d, const int64_t* 
     member_offsets<<<grid_for(N + 1, 256), 256, 0, s>>>(in1 ? k1 : k0, N, K, off);
     TAC_LAUNCH_CHECK("member_offsets");
     time_start(ctx, TAC_SLOT_UPDATE);
-    centroid_means<<<grid_for(K * 64, 256), 256, 0, s>>>(xs_d, seg_off_d, T, in1 ? v1 : v0, off, K, C_old_d, C_new_d,
-                                                         count_d);
+    uint8_t* wide = ws_at<uint8_t>(ctx, o_wide);
+    centroid_flags<<<grid_for(K, 256), 256, 0, s>>>(seg_off_d, T, in1 ? v1 : v0, off, K, wide);
+    TAC_LAUNCH_CHECK("centroid_flags");
+    centroid_means<<<grid_for(K * 64, 256), 256, 0, s>>>(xs_d, wide, in1 ? v1 : v0, off, K, C_old_d, C_new_d, count_d);
     TAC_LAUNCH_CHECK("centroid_means");
     time_stop(ctx, TAC_SLOT_UPDATE);
     return TAC_OK;

@@ -96,6 +96,38 @@ def cpu_baseline(x, tok, w, sample_rows: int, seed: int = 0):
                       f"against their tokens' initial centroids ({dt:.1f}s on {threads} threads)"}
 
 
+def global_baseline(ctx, idx, w, tac_iter_ms: float, rows: int, seed: int = 0):
+    """Plain (global) Lloyd on the same kernels: one segment holding a uniform
+    sample of `rows` vectors and all K centroids of the build, one BF16
+    assignment + update timed with HIP events; compared per vector with the
+    token-aware iteration on the full input."""
+    import torch
+    import paper_2604_28142_amd as tac
+    dev = idx.xs.device
+    N = idx.xs.shape[0]
+    sel = torch.from_numpy(np.sort(np.random.default_rng([seed, 12]).choice(N, rows, replace=False))).to(dev)
+    xg = idx.xs.index_select(0, sel).contiguous()
+    seg = torch.tensor([0, rows], dtype=torch.int64, device=dev)
+    coff = torch.tensor([0, idx.K], dtype=torch.int64, device=dev)
+    a = torch.empty(rows, dtype=torch.int32, device=dev)
+    Cn = torch.empty_like(idx.C)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    stream = ctx.stream
+    tac.tac_assign(ctx, xg, idx.C, coff, a, seg_off=seg, precision=tac.TAC_BF16)   # sizes the workspace
+    tac.tac_update(ctx, xg, seg, a, idx.C, Cn)
+    ev[0].record(stream)
+    tac.tac_assign(ctx, xg, idx.C, coff, a, seg_off=seg, precision=tac.TAC_BF16)
+    tac.tac_update(ctx, xg, seg, a, idx.C, Cn)
+    ev[1].record(stream)
+    ev[1].synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    per_vec_global = ms / rows
+    per_vec_tac = tac_iter_ms / N
+    return {"rows": rows, "centroids": idx.K, "ms_per_iter": ms,
+            "vectors_per_s": rows / (ms / 1e3), "tac_speedup_per_vector": per_vec_global / per_vec_tac,
+            "note": "one segment: a uniform row sample against all K centroids of the build, same BF16 kernels"}
+
+
 def serve_bench(idx, w, requests: int, seed: int = 0):
     """Encode service against the resident index: saturated throughput, then
     Poisson arrivals at 0.3 / 0.6 / 0.9 of it (first 5% of requests discarded)."""
@@ -144,6 +176,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=20_000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--global-baseline", type=int, default=0, metavar="ROWS",
+                    help="also time one plain Lloyd iteration (one segment, all K centroids) on ROWS sampled vectors")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
@@ -301,6 +335,9 @@ def main():
     if "fp32" in kms:
         extra["fp32_roofline_frac"] = F / (kms["fp32"] / 1e3) / 1e12 / PEAK["fp32"]
 
+    if args.global_baseline:
+        extra["global_kmeans"] = global_baseline(ctx, idx, w, lloyd_med / args.iters, args.global_baseline)
+        log(f"global k-means: {extra['global_kmeans']}")
     if not args.no_serve:
         extra["encode_service"] = serve_bench(idx, w, args.serve_requests)
 

@@ -54,7 +54,8 @@ __device__ __forceinline__ float dist32_rows(const float* __restrict__ x, const 
     const float4* xv = reinterpret_cast<const float4*>(x);
     const float4* cv = reinterpret_cast<const float4*>(c);
     float acc = 0.f, sx = 0.f;
-#pragma unroll 4
+    // eight iterations' loads are issued together: four latency rounds per row
+#pragma unroll 8
     for (int i = 0; i < kDim / 4; ++i) {
         const float4 a = xv[i];
         const float4 b = cv[i];
@@ -96,6 +97,15 @@ __global__ void plan_count(const int64_t* __restrict__ seg_off, const int64_t* _
     const int64_t rows = cls == 2 ? direct_rows : screen_rows;
     const int64_t tiles = (n + rows - 1) / rows;
     for (int c = 0; c < 3; ++c) cnt[(int64_t)c * T + j] = c == cls ? tiles : 0;
+}
+
+// item -> (class, token) table from the scanned item offsets
+__global__ void plan_fill(const int64_t* __restrict__ item_off, int64_t ncls, int32_t* __restrict__ table) {
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < ncls;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = item_off[idx], e = item_off[idx + 1];
+        for (int64_t t = b; t < e; ++t) table[t] = (int32_t)idx;
+    }
 }
 
 // ---- centroid preparation: squared norms, max norm, BF16 hi/lo splits ----
@@ -151,6 +161,7 @@ struct Params {
     const float* cn;
     const unsigned* cstat;       // [0] = bits of max ||c||^2
     const int64_t* item_off;     // [3T + 1]
+    const int32_t* item_table;   // item -> class * T + token
     unsigned long long* work;
     int32_t* assign;
     float* dist;
@@ -268,30 +279,20 @@ __device__ __forceinline__ void direct_item(const Params& P, int32_t j, int64_t 
             P.assign[r] = -1;
             P.dist[r] = 0.f;
         } else {
-            const float4* xv = reinterpret_cast<const float4*>(P.x + r * kDim);
-            float acc[kDirectCap];
-#pragma unroll
-            for (int k = 0; k < kDirectCap; ++k) acc[k] = 0.f;
-            for (int i = 0; i < kDim / 4; ++i) {
-                const float4 a = xv[i];
-#pragma unroll
-                for (int k = 0; k < kDirectCap; ++k) {
-                    if (k < kc) {
-                        const float4 b = reinterpret_cast<const float4*>(P.C + (k0 + k) * kDim)[i];
-                        float t;
-                        t = __fsub_rn(a.x, b.x); acc[k] = __fadd_rn(acc[k], __fmul_rn(t, t));
-                        t = __fsub_rn(a.y, b.y); acc[k] = __fadd_rn(acc[k], __fmul_rn(t, t));
-                        t = __fsub_rn(a.z, b.z); acc[k] = __fadd_rn(acc[k], __fmul_rn(t, t));
-                        t = __fsub_rn(a.w, b.w); acc[k] = __fadd_rn(acc[k], __fmul_rn(t, t));
-                    }
+            // centroid by centroid, each a canonical distance with eight float4
+            // iterations' loads in flight; the first minimum wins ties
+            const float* xr = P.x + r * kDim;
+            float bd = INFINITY;
+            int best = 0;
+            for (int k = 0; k < kc; ++k) {
+                const float d = dist32_rows(xr, P.C + (k0 + k) * kDim, nullptr);
+                if (d < bd) {
+                    bd = d;
+                    best = k;
                 }
             }
-            int best = 0;
-#pragma unroll
-            for (int k = 1; k < kDirectCap; ++k)
-                if (k < kc && acc[k] < acc[best]) best = k;
             P.assign[r] = (int32_t)(k0 + best);
-            P.dist[r] = acc[best];
+            P.dist[r] = bd;
         }
     }
     const unsigned long long nval = __popcll(__ballot(valid));
@@ -307,15 +308,15 @@ template <int PREC, int NB>
 __device__ __forceinline__ float load_x_frags(const Params& P, int64_t row0, int64_t s1, int g, int col,
                                               Frag<PREC, NB>& F) {
     float xxmax = 0.f;
+    if constexpr (PREC == TAC_FP32) {
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        __builtin_amdgcn_sched_barrier(0);  // convert one column block at a time (bounded live registers)
-        const int64_t v = row0 + nb * 16 + col;
-        const bool valid = v < s1;
-        const int64_t r = valid ? (P.rowmap ? (int64_t)P.rowmap[v] : v) : 0;
-        const float4* xv = reinterpret_cast<const float4*>(P.x + r * kDim + 32 * g);
-        float xx = 0.f;
-        if constexpr (PREC == TAC_FP32) {
+        for (int nb = 0; nb < NB; ++nb) {
+            __builtin_amdgcn_sched_barrier(0);  // one column block at a time (bounded live registers)
+            const int64_t v = row0 + nb * 16 + col;
+            const bool valid = v < s1;
+            const int64_t r = valid ? (P.rowmap ? (int64_t)P.rowmap[v] : v) : 0;
+            const float4* xv = reinterpret_cast<const float4*>(P.x + r * kDim + 32 * g);
+            float xx = 0.f;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const float4 a = valid ? xv[q] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -325,12 +326,31 @@ __device__ __forceinline__ float load_x_frags(const Params& P, int64_t row0, int
                 F.x[nb][4 * q + 2] = -2.0f * a.z;
                 F.x[nb][4 * q + 3] = -2.0f * a.w;
             }
-        } else {
+            xx += __shfl_xor(xx, 16);
+            xx += __shfl_xor(xx, 32);
+            xxmax = fmaxf(xxmax, xx);
+        }
+    } else {
+        // all of the wave's rows are loaded before any is converted, so that the
+        // loads of the NB column blocks are in flight together
+        float4 ld[NB][8];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int64_t v = row0 + nb * 16 + col;
+            const bool valid = v < s1;
+            const int64_t r = valid ? (P.rowmap ? (int64_t)P.rowmap[v] : v) : 0;
+            const float4* xv = reinterpret_cast<const float4*>(P.x + r * kDim + 32 * g);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) ld[nb][q] = valid ? xv[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            float xx = 0.f;
             // eight coordinates at a time straight into the hi/lo fragments
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                const float4 a = valid ? xv[2 * s] : make_float4(0.f, 0.f, 0.f, 0.f);
-                const float4 b = valid ? xv[2 * s + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+                const float4 a = ld[nb][2 * s];
+                const float4 b = ld[nb][2 * s + 1];
                 xx += a.x * a.x + a.y * a.y + a.z * a.z + a.w * a.w + b.x * b.x + b.y * b.y + b.z * b.z + b.w * b.w;
                 const float v8[8] = {-2.0f * a.x, -2.0f * a.y, -2.0f * a.z, -2.0f * a.w,
                                      -2.0f * b.x, -2.0f * b.y, -2.0f * b.z, -2.0f * b.w};
@@ -339,10 +359,10 @@ __device__ __forceinline__ float load_x_frags(const Params& P, int64_t row0, int
                 F.xh[nb][s] = to_agpr(hi);
                 F.xl[nb][s] = to_agpr(lo);
             }
+            xx += __shfl_xor(xx, 16);
+            xx += __shfl_xor(xx, 32);
+            xxmax = fmaxf(xxmax, xx);
         }
-        xx += __shfl_xor(xx, 16);
-        xx += __shfl_xor(xx, 32);
-        xxmax = fmaxf(xxmax, xx);
     }
     // keep every fragment write far above the first matrix-core read
     __builtin_amdgcn_sched_barrier(0);
@@ -729,6 +749,33 @@ __device__ __forceinline__ void screen_item_bf16(const Params& P, int32_t j, int
                 list_insert<kBLK>(el[nb], __uint_as_float(__builtin_amdgcn_perm(__float_as_uint(acc[nb][r]), lb + r,
                                                                           0x07060500u)));
     };
+    // Steady-state block: the MFMAs of block B interleaved by hand with the
+    // top-k inserts of the previous block (one insert after every third MFMA);
+    // scheduling barriers keep that order, so the vector work fills the
+    // matrix pipeline's gaps instead of bunching up.
+    auto mfmas_inserts = [&](const BBlock& B, f4 (&acc)[NB], int pblk, const f4 (&prev)[NB]) {
+        const unsigned lb = (unsigned)(pblk - epoch_first) * 4u;
+#pragma unroll
+        for (int st4 = 0; st4 < 4; ++st4)
+#pragma unroll
+            for (int pr = 0; pr < 3; ++pr)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const bf8 av = pr == 2 ? B.cl[st4] : B.ch[st4];
+                    const bf8 bv = pr == 1 ? F.xl[nb][st4] : F.xh[nb][st4];
+                    acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, (st4 == 0 && pr == 0) ? B.cb : acc[nb],
+                                                                      0, 0, 0);
+                    const int i = (st4 * 3 + pr) * NB + nb;
+                    if (i % 3 == 2) {
+                        const int v = i / 3;
+                        if (v < 4 * NB)
+                            list_insert<kBLK>(el[v >> 2],
+                                              __uint_as_float(__builtin_amdgcn_perm(
+                                                  __float_as_uint(prev[v >> 2][v & 3]), lb + (v & 3), 0x07060500u)));
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+    };
     auto flush_if = [&](int blk) {
         if (blk - epoch_first == kEpochBlocks - 1 || blk + 1 == nblk) {
             epoch_flush<NB, kBLK, float>(el, glist, k0 + (int64_t)epoch_first * 16 + 4 * g);
@@ -779,8 +826,7 @@ __device__ __forceinline__ void screen_item_bf16(const Params& P, int32_t j, int
                 break;
             }
             load_block(blk + 1, BA);
-            mfmas(BB, accB);
-            inserts(blk - 1, accA);
+            mfmas_inserts(BB, accB, blk - 1, accA);
             flush_if(blk - 1);
             ++blk;
             // even block: operands BA -> accA, previous block in accB
@@ -794,8 +840,7 @@ __device__ __forceinline__ void screen_item_bf16(const Params& P, int32_t j, int
                 break;
             }
             load_block(blk + 1, BB);
-            mfmas(BA, accA);
-            inserts(blk - 1, accB);
+            mfmas_inserts(BA, accA, blk - 1, accB);
             flush_if(blk - 1);
         }
     }
@@ -809,21 +854,19 @@ __global__ void __launch_bounds__(PREC == TAC_BF16 ? kBThreads : kThreads) assig
     extern __shared__ __attribute__((aligned(16))) unsigned lds[];
     unsigned long long* s_item = reinterpret_cast<unsigned long long*>(
         lds + (PREC == TAC_BF16 ? kBLdsBytes : kLdsBytes) / 4);
-    const int64_t nclass = 3 * (int64_t)P.T;
-    for (;;) {
-        if (threadIdx.x == 0) *s_item = atomicAdd(P.work, 1ull);
-        __syncthreads();
-        const int64_t item = (int64_t)*s_item;
-        __syncthreads();
-        if (item >= P.item_off[nclass]) break;
-        int64_t lo = 0, hi = nclass;  // largest idx with item_off[idx] <= item
-        while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (P.item_off[mid] <= item) lo = mid; else hi = mid;
-        }
-        const int cls = (int)(lo / P.T);
-        const int32_t j = (int32_t)(lo % P.T);
-        const int64_t tile = item - P.item_off[lo];
+    const int64_t total = P.item_off[3 * (int64_t)P.T];
+    if (threadIdx.x == 0) *s_item = atomicAdd(P.work, 1ull);
+    __syncthreads();
+    int64_t item = (int64_t)*s_item;
+    __syncthreads();
+    while (item < total) {
+        // the next item is fetched now; the atomic's latency overlaps this item
+        unsigned long long next = 0;
+        if (threadIdx.x == 0) next = atomicAdd(P.work, 1ull);
+        const int32_t idx = P.item_table[item];
+        const int cls = idx / P.T;
+        const int32_t j = idx - cls * P.T;
+        const int64_t tile = item - P.item_off[idx];
         if constexpr (PREC == TAC_BF16) {
             if (cls == 2)
                 direct_item<kBThreads>(P, j, tile);
@@ -835,6 +878,10 @@ __global__ void __launch_bounds__(PREC == TAC_BF16 ? kBThreads : kThreads) assig
             else
                 screen_item_fp32(P, j, tile, lds);
         }
+        if (threadIdx.x == 0) *s_item = next;
+        __syncthreads();
+        item = (int64_t)*s_item;
+        __syncthreads();
     }
 }
 
@@ -1049,6 +1096,7 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     Carve cv;
     const size_t o_cnt = cv.take<int64_t>(ncls + 1);
     const size_t o_scan = cv.take<char>(scan_scratch_bytes(ncls));
+    const size_t o_table = cv.take<int32_t>(N / 256 + (int64_t)T + 1);   // items: at most one partial per token
     const size_t o_work = cv.take<unsigned long long>(1);
     const size_t o_cstat = cv.take<unsigned>(4);
     const size_t o_cn = cv.take<float>(K + 1);
@@ -1110,6 +1158,9 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     TAC_LAUNCH_CHECK("plan_count");
     st = exclusive_scan_i64(s, cnt, cnt, ncls, ws_at<void>(ctx, o_scan));
     if (st != TAC_OK) return st;
+    int32_t* table = ws_at<int32_t>(ctx, o_table);
+    plan_fill<<<grid_for(ncls, 256), 256, 0, s>>>(cnt, ncls, table);
+    TAC_LAUNCH_CHECK("plan_fill");
     if (K > 0) {
         // a grid-stride launch of a few blocks per CU keeps the per-block atomicMax on the norm bound cheap
         const unsigned pgrid = std::min<unsigned>(grid_for(K * 32, 256), (unsigned)ctx->props_cu * 4);
@@ -1127,6 +1178,7 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     P.cn = cn;
     P.cstat = cstat;
     P.item_off = cnt;
+    P.item_table = table;
     P.work = work;
     P.assign = assign_d;
     P.dist = dist;

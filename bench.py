@@ -8,8 +8,9 @@ residual + PQ encoding of every vector.
 
 Metric (vectors assigned per second per Lloyd iteration) = N * iters / Lloyd
 time, Lloyd time measured with HIP events around the graph replay inside each
-step.  The BF16 screen is the headline; the FP32 screen runs the same graph
-for comparison and must give identical assignments.
+step.  The headline runs the BF16 screen (``--headline f16`` times the FP16
+screen instead); the other precisions run the same graph for comparison and
+must give identical final assignments.
 """
 from __future__ import annotations
 
@@ -24,7 +25,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"bf16": 2500.0, "fp32": 157.3}   # dense MFMA TFLOP/s of an MI355X
+PEAK = {"bf16": 2500.0, "f16": 2500.0, "fp32": 157.3}   # dense MFMA TFLOP/s of an MI355X
+PRODUCTS = {"bf16": 3, "f16": 1, "fp32": 1}              # matrix-core products per coordinate of x.c
 HBM_PEAK = 8000.0                         # GB/s
 
 WORKLOAD_TEXT = {
@@ -37,7 +39,7 @@ WORKLOAD_TEXT = {
 }
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assign_main_bf16_c1_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assign_main_{prec}_{config}_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_28142_amd", "csrc", f) for f in ("assign.hip", "tac_internal.h")]
 
 
@@ -50,11 +52,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(config: str):
-    """HBM bytes per launch of the BF16 assignment kernel from the committed counter
-    summary, or None when it was taken on another workload or an older kernel source."""
+def measured_traffic(config: str, prec: str):
+    """HBM bytes per launch of the 16-bit assignment kernel from the committed counter
+    summary, or None when there is none for this workload or it predates the kernel source."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(TRAFFIC_FILE.format(prec=prec, config=config)).read()
     except OSError:
         return None
     vals = dict(ln.split(":", 1) for ln in text.splitlines() if ln.startswith(("traffic_bytes_per_launch:",
@@ -173,6 +175,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-f16", action="store_true", help="skip the FP16-screen comparison leg")
+    ap.add_argument("--headline", default="bf16", choices=["bf16", "f16"],
+                    help="16-bit screen timed in the steps (the other runs as a comparison leg)")
     ap.add_argument("--serve-requests", type=int, default=20_000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -222,10 +227,12 @@ def main():
     F = 2.0 * 128 * float((counts[screen] * kappa[screen]).sum())   # algorithmic contraction flops per assign
     log(f"budget: K={int(kappa.sum())}, max kappa={int(kappa.max())}, screen flops/assign={F:.3e}")
 
+    precs = {"bf16": tac.TAC_BF16, "f16": tac.TAC_F16, "fp32": tac.TAC_FP32}
+    hl = args.headline
+    legs = [hl] + [nm for nm in ("bf16", "f16", "fp32") if nm != hl and not getattr(args, f"no_{nm}", False)]
     loops, tuned, tuning = {}, {}, {}
-    for name, prec in (("bf16", tac.TAC_BF16), ("fp32", tac.TAC_FP32)):
-        if name == "fp32" and args.no_fp32:
-            continue
+    for name in legs:
+        prec = precs[name]
         if not args.no_autotune:
             # launch tuning for this precision, measured on the initial centroids (cached per workload);
             # it is baked into the captured graph
@@ -269,9 +276,9 @@ def main():
         return ((time.perf_counter() - t0) * 1e3, ev[0].elapsed_time(ev[1]),
                 ctx.kernel_ms(tac._lib.TAC_SLOT_ASSIGN), ctx.kernel_ms(tac._lib.TAC_SLOT_ENCODE))
 
-    head = loops["bf16"]
-    ctx.set_tuning(**tuning["bf16"])
-    # kernel events: each step's final assignment (one launch of the persistent BF16 assignment
+    head = loops[hl]
+    ctx.set_tuning(**tuning[hl])
+    # kernel events: each step's final assignment (one launch of the persistent 16-bit assignment
     # kernel) and its encode kernel are timed on the context's stream inside the timed region
     ctx.enable_timing(True)
     for _ in range(args.warmup):
@@ -286,52 +293,59 @@ def main():
     lloyd = [r[1] for r in res]
     assign_kernel_ms = float(np.mean([r[2] for r in res]))
     encode_kernel_ms = float(np.mean([r[3] for r in res]))
-    final_bf16 = idx.assign.clone()
+    final_head = idx.assign.clone()
     lloyd_med = float(np.median(lloyd))
     value = N * args.iters / (lloyd_med / 1e3)
-    log(f"bf16: steps {['%.1f' % s for s in step_ms]} ms, Lloyd {['%.2f' % l for l in lloyd]} ms")
+    log(f"{hl}: steps {['%.1f' % s for s in step_ms]} ms, Lloyd {['%.2f' % l for l in lloyd]} ms")
 
+    # comparison legs: the same captured Lloyd graph and final assignment in the other precisions
     extra = {}
-    if "fp32" in loops:
-        fp32_ms = lloyd_ms(loops["fp32"])
-        IX.final_assign(ctx, idx, precision=tac.TAC_FP32)
-        same = bool(torch.equal(idx.assign, final_bf16))
-        extra["fp32"] = {"lloyd_ms_per_iter": fp32_ms / args.iters,
-                         "value": N * args.iters / (fp32_ms / 1e3)}
-        extra["bf16_over_fp32"] = fp32_ms / lloyd_med
-        extra["final_argmin_identical"] = same
-        log(f"fp32: Lloyd {fp32_ms:.1f} ms; identical final assignments: {same}")
+    leg_ms = {hl: lloyd_med}
+    same_all = True
+    for name in legs[1:]:
+        ctx.set_tuning(**tuning[name])
+        ms = float(np.median([lloyd_ms(loops[name]) for _ in range(2)]))
+        leg_ms[name] = ms
+        IX.final_assign(ctx, idx, precision=precs[name])
+        same = bool(torch.equal(idx.assign, final_head))
+        same_all = same_all and same
+        extra[name] = {"lloyd_ms_per_iter": ms / args.iters, "value": N * args.iters / (ms / 1e3),
+                       "final_argmin_identical_to_" + hl: same}
+        log(f"{name}: Lloyd {ms:.1f} ms; identical final assignments: {same}")
+    ctx.set_tuning(**tuning[hl])
+    if "fp32" in leg_ms:
+        for name in ("bf16", "f16"):
+            if name in leg_ms:
+                extra[f"{name}_over_fp32"] = leg_ms["fp32"] / leg_ms[name]
+    extra["final_argmin_identical"] = same_all
 
     # dominant kernel: the persistent assignment kernel, timed with HIP events on its stream
     ctx.enable_timing(True)
     idx.C.copy_(C0)
-    kms = {}
-    for name, prec in (("bf16", tac.TAC_BF16), ("fp32", tac.TAC_FP32)):
-        if name not in loops:
-            continue
+    kms, stats = {}, {}
+    for name in legs:
         ctx.set_tuning(**tuning[name])
         vals = []
         for _ in range(3):
-            tac.tac_assign(ctx, idx.xs, idx.C, idx.cent_off, idx.assign, seg_off=idx.seg_off, precision=prec)
+            tac.tac_assign(ctx, idx.xs, idx.C, idx.cent_off, idx.assign, seg_off=idx.seg_off, precision=precs[name])
             vals.append(ctx.kernel_ms(tac._lib.TAC_SLOT_ASSIGN))
         kms[name] = float(np.mean(vals))
-        if name == "bf16":
-            stats = tac.tac_assign_stats(ctx)
-    tac.tac_update(ctx, idx.xs, idx.seg_off, idx.assign, idx.C, loops["bf16"].other)
+        stats[name] = tac.tac_assign_stats(ctx)
+    ctx.set_tuning(**tuning[hl])
+    tac.tac_update(ctx, idx.xs, idx.seg_off, idx.assign, idx.C, loops[hl].other)
     upd_ms = ctx.kernel_ms(tac._lib.TAC_SLOT_UPDATE)
     IX.encode_all(ctx, idx)
     enc_ms = ctx.kernel_ms(tac._lib.TAC_SLOT_ENCODE)
     ctx.enable_timing(False)
     achieved = F / (assign_kernel_ms / 1e3) / 1e12
-    extra["kernels_ms"] = {"assign_bf16_timed_region": assign_kernel_ms, "pq_encode_timed_region": encode_kernel_ms,
-                           "assign_bf16": kms.get("bf16"), "assign_fp32": kms.get("fp32"), "update_means": upd_ms,
-                           "pq_encode": enc_ms}
+    extra["kernels_ms"] = {f"assign_{hl}_timed_region": assign_kernel_ms, "pq_encode_timed_region": encode_kernel_ms,
+                           **{f"assign_{nm}": kms[nm] for nm in legs}, "update_means": upd_ms, "pq_encode": enc_ms}
     extra["assign_counters"] = stats
     if tuned:
         extra["autotune"] = tuned
     extra["lloyd_ms_per_iter"] = lloyd_med / args.iters
     extra["screen_flops_per_assign"] = F
-    extra["mfma_executed_tflops_bf16x3"] = 3 * achieved
+    extra["mfma_executed_tflops"] = {nm: PRODUCTS[nm] * F / (kms[nm] / 1e3) / 1e12 for nm in legs}
     if "fp32" in kms:
         extra["fp32_roofline_frac"] = F / (kms["fp32"] / 1e3) / 1e12 / PEAK["fp32"]
 
@@ -358,14 +372,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": hl,
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOAD_TEXT[args.config]}", "vectors": N, "tokens": w.vocab,
                    "centroids": w.k, "lloyd_iters": args.iters, "budget": "mu=128 tau=256 eps=4 theta=39",
                    "timed_region_ms": wall},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["bf16"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["bf16"], "traffic": measured_traffic(args.config),
-                     "kernel": "assign_main<bf16> (persistent screen + per-lane top-3 + certificate)"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[hl], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK[hl], "traffic": measured_traffic(args.config, hl),
+                     "kernel": f"assign_main<{hl}> (persistent screen + per-lane top-3 + certificate)"},
         "cpu_baseline": cpu,
         **extra,
     }

@@ -31,7 +31,7 @@
  *    with every operation rounded to float32 and no fused multiply-add.
  *    Matrix-core screens only nominate candidates; a rigorous error bound
  *    certifies that no other candidate can win, else the vector is rescored
- *    exhaustively.  TAC_FP32 and TAC_BF16 therefore return identical argmins.
+ *    exhaustively.  TAC_FP32, TAC_BF16 and TAC_F16 therefore return identical argmins.
  *  - One context per host thread, or external locking.
  */
 #ifndef TAC_H
@@ -57,8 +57,11 @@ typedef enum {
 
 typedef enum {
     TAC_FP32 = 0,  /* FP32 matrix-core screen (v_mfma_f32_16x16x4f32) */
-    TAC_BF16 = 1   /* BF16 matrix-core screen, FP32 accumulation: x.c from three BF16
+    TAC_BF16 = 1,  /* BF16 matrix-core screen, FP32 accumulation: x.c from three BF16
                       products of hi/lo splits (v_mfma_f32_16x16x32_bf16) */
+    TAC_F16 = 2    /* FP16 matrix-core screen, FP32 accumulation: x.c from one FP16
+                      product per coordinate (v_mfma_f32_16x16x32_f16); the certificate
+                      bounds both operands' rounding by their measured norms */
 } tac_precision;
 
 typedef enum {

@@ -4,10 +4,10 @@ The work runs in libtac.so (HIP kernels behind the C ABI of include/tac.h);
 this package holds the ctypes binding (``_lib``), the in-tree build script
 (``build``) and the drivers that chain the calls (``index``, ``serve``).
 """
-from ._lib import (TAC_BF16, TAC_FP32, TAC_THETA_FILL_THEN_RELAX, TAC_THETA_SOFT, BudgetParams, Context,
+from ._lib import (TAC_BF16, TAC_F16, TAC_FP32, TAC_THETA_FILL_THEN_RELAX, TAC_THETA_SOFT, BudgetParams, Context,
                    TacError, Tuning, load, pq_encode, pq_train, tac_assign, tac_assign_stats, tac_budget,
                    tac_budget_from_stats, tac_init_centroids, tac_residuals, tac_update)
 
-__all__ = ["TAC_BF16", "TAC_FP32", "TAC_THETA_FILL_THEN_RELAX", "TAC_THETA_SOFT", "BudgetParams", "Context",
+__all__ = ["TAC_BF16", "TAC_F16", "TAC_FP32", "TAC_THETA_FILL_THEN_RELAX", "TAC_THETA_SOFT", "BudgetParams", "Context",
            "TacError", "Tuning", "load", "pq_encode", "pq_train", "tac_assign", "tac_assign_stats", "tac_budget",
            "tac_budget_from_stats", "tac_init_centroids", "tac_residuals", "tac_update"]

@@ -17,7 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libtac.so")
 
 TAC_OK, TAC_E_INVAL, TAC_E_INFEASIBLE, TAC_E_NOMEM, TAC_E_HIP, TAC_E_UNSEEN_TOKEN = 0, -1, -2, -3, -4, -5
-TAC_FP32, TAC_BF16 = 0, 1
+TAC_FP32, TAC_BF16, TAC_F16 = 0, 1, 2
 TAC_THETA_FILL_THEN_RELAX, TAC_THETA_SOFT = 0, 1
 
 _STATUS = {TAC_E_INVAL: "TAC_E_INVAL", TAC_E_INFEASIBLE: "TAC_E_INFEASIBLE", TAC_E_NOMEM: "TAC_E_NOMEM",

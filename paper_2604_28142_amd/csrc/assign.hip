@@ -33,6 +33,7 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 512;
@@ -82,6 +83,7 @@ __global__ void reset_call(unsigned long long* __restrict__ work, unsigned long 
     for (int i = 0; i < 4; ++i) counters[i] = 0;
     cstat[0] = 0;
     cstat[1] = 0;
+    cstat[2] = 0;
 }
 
 // ---- plan: item counts per (class, token) ----
@@ -108,12 +110,18 @@ __global__ void plan_fill(const int64_t* __restrict__ item_off, int64_t ncls, in
     }
 }
 
-// ---- centroid preparation: squared norms, max norm, BF16 hi/lo splits ----
+// ---- centroid preparation: squared norms, max norm, 16-bit staging rows ----
+// BF16: hi/lo splits (hi = bf16(c), lo = bf16(c - hi)), 512 B per centroid.
+// FP16: one rounding c16 = f16(c), 256 B per centroid, and the largest
+// ||c - c16||^2 over all centroids into cstat[2] (the FP16 certificate's
+// operand-rounding bound).
 __global__ void __launch_bounds__(256) prep_centroids(const float* __restrict__ C, int64_t K, float* __restrict__ cn,
-                                                      unsigned* __restrict__ cstat, unsigned short* __restrict__ chl) {
+                                                      unsigned* __restrict__ cstat, unsigned short* __restrict__ chl,
+                                                      int prec) {
     __shared__ unsigned red[256];
+    __shared__ unsigned redd[256];
     const int sub = threadIdx.x & 31;
-    unsigned mx = 0;
+    unsigned mx = 0, mxd = 0;
     for (int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5; k < K;
          k += ((int64_t)gridDim.x * blockDim.x) >> 5) {
         const float4 v = reinterpret_cast<const float4*>(C + k * kDim)[sub];
@@ -124,7 +132,24 @@ __global__ void __launch_bounds__(256) prep_centroids(const float* __restrict__ 
         for (int m = 16; m > 0; m >>= 1) s += __shfl_xor(s, m, 32);
         if (sub == 0) cn[k] = s;
         mx = max(mx, __float_as_uint(s));  // non-negative floats order like their bit patterns
-        if (chl) {
+        if (chl && prec == TAC_F16) {
+            const float e[4] = {v.x, v.y, v.z, v.w};
+            unsigned short h[4];
+            float dd = 0.f;
+            for (int i = 0; i < 4; ++i) {
+                const _Float16 q = (_Float16)e[i];
+                h[i] = __builtin_bit_cast(unsigned short, q);
+                const float r = e[i] - (float)q;  // exact: q is e rounded to a coarser grid
+                dd = dd + r * r;
+            }
+            for (int m = 16; m > 0; m >>= 1) dd += __shfl_xor(dd, m, 32);
+            // a non-finite residual (|c| beyond the FP16 range) becomes +inf, so that the bound disables the screen
+            mxd = max(mxd, dd <= FLT_MAX ? __float_as_uint(dd) : 0x7F800000u);
+            uint2 hv;
+            hv.x = h[0] | ((unsigned)h[1] << 16);
+            hv.y = h[2] | ((unsigned)h[3] << 16);
+            reinterpret_cast<uint2*>(chl + k * kDim)[sub] = hv;
+        } else if (chl) {
             const float e[4] = {v.x, v.y, v.z, v.w};
             unsigned short hi[4], lo[4];
             for (int i = 0; i < 4; ++i) {
@@ -142,12 +167,17 @@ __global__ void __launch_bounds__(256) prep_centroids(const float* __restrict__ 
         }
     }
     red[threadIdx.x] = mx;
+    redd[threadIdx.x] = mxd;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + off]);
+        if (threadIdx.x < off) {
+            red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + off]);
+            redd[threadIdx.x] = max(redd[threadIdx.x], redd[threadIdx.x + off]);
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0 && red[0]) atomicMax(cstat, red[0]);
+    if (threadIdx.x == 0 && redd[0]) atomicMax(cstat + 2, redd[0]);
 }
 
 struct Params {
@@ -157,15 +187,22 @@ struct Params {
     const int64_t* cent_off;
     int32_t T;
     const float* C;
-    const void* cstage;          // rows staged into LDS: C (FP32) or hi/lo BF16 pairs
+    const void* cstage;          // rows staged into LDS: C (FP32), hi/lo BF16 pairs or FP16 rows
     const float* cn;
-    const unsigned* cstat;       // [0] = bits of max ||c||^2
+    const unsigned* cstat;       // [0] = bits of max ||c||^2, [1] = max kappa, [2] = bits of max ||c - f16(c)||^2
     const int64_t* item_off;     // [3T + 1]
     const int32_t* item_table;   // item -> class * T + token
     unsigned long long* work;
     int32_t* assign;
     float* dist;
-    int32_t* fb;                 // fallback queue: (sorted position, token) pairs
+    // Fallback queue, grouped by token: the k-th failed row of token j sits at
+    // index seg_off[j] + k (k < fbcnt[j]) with its physical row, its canonical
+    // ||x||^2 and a 64-bit (distance bits, index) slot holding its best exact
+    // candidate so far.
+    int32_t* fbq;
+    float* fbxx;
+    unsigned long long* fbslot;
+    int32_t* fbcnt;
     unsigned long long* counters;
 };
 
@@ -235,12 +272,18 @@ struct Frag<TAC_BF16, NB> {
     bf8 xl[NB][4];
 };
 
+template <int NB>
+struct Frag<TAC_F16, NB> {
+    h8 xh[NB][4];
+};
+
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
 
-// Move a BF16 fragment into accumulation registers (AGPRs).  The BF16 screen's
-// x operands stay there for a whole item and feed the matrix cores directly,
-// which leaves the VGPRs to the accumulators, lists and centroid fragments.
-__device__ __forceinline__ bf8 to_agpr(bf8 v) {
+// Move a 16-bit fragment into accumulation registers (AGPRs).  The 16-bit
+// screens' x operands stay there for a whole item and feed the matrix cores
+// directly, which leaves the VGPRs to the accumulators, lists and centroid fragments.
+template <class V>
+__device__ __forceinline__ V to_agpr(V v) {
     const u4 u = __builtin_bit_cast(u4, v);
     unsigned a0, a1, a2, a3;
     asm("v_accvgpr_write_b32 %0, %1" : "=a"(a0) : "v"(u[0]));
@@ -248,7 +291,7 @@ __device__ __forceinline__ bf8 to_agpr(bf8 v) {
     asm("v_accvgpr_write_b32 %0, %1" : "=a"(a2) : "v"(u[2]));
     asm("v_accvgpr_write_b32 %0, %1" : "=a"(a3) : "v"(u[3]));
     const u4 r = {a0, a1, a2, a3};
-    return __builtin_bit_cast(bf8, r);
+    return __builtin_bit_cast(V, r);
 }
 
 // hi = bf16(v), lo = bf16(v - hi) for 8 consecutive values (round to nearest even)
@@ -304,9 +347,10 @@ __device__ __forceinline__ void direct_item(const Params& P, int32_t j, int64_t 
 
 // Load and convert the wave's x fragments (rows row0 .. row0 + 16 NB - 1, those
 // at or past s1 as zeros); returns the largest ||x||^2 over the wave's rows.
+// FP16 also stores each row's ||-2x - f16(-2x)||^2 at sdx[16 nb + col].
 template <int PREC, int NB>
 __device__ __forceinline__ float load_x_frags(const Params& P, int64_t row0, int64_t s1, int g, int col,
-                                              Frag<PREC, NB>& F) {
+                                              Frag<PREC, NB>& F, float* sdx = nullptr) {
     float xxmax = 0.f;
     if constexpr (PREC == TAC_FP32) {
 #pragma unroll
@@ -345,8 +389,8 @@ __device__ __forceinline__ float load_x_frags(const Params& P, int64_t row0, int
         }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            float xx = 0.f;
-            // eight coordinates at a time straight into the hi/lo fragments
+            float xx = 0.f, dyy = 0.f;
+            // eight coordinates at a time straight into the 16-bit fragments
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const float4 a = ld[nb][2 * s];
@@ -354,14 +398,30 @@ __device__ __forceinline__ float load_x_frags(const Params& P, int64_t row0, int
                 xx += a.x * a.x + a.y * a.y + a.z * a.z + a.w * a.w + b.x * b.x + b.y * b.y + b.z * b.z + b.w * b.w;
                 const float v8[8] = {-2.0f * a.x, -2.0f * a.y, -2.0f * a.z, -2.0f * a.w,
                                      -2.0f * b.x, -2.0f * b.y, -2.0f * b.z, -2.0f * b.w};
-                bf8 hi, lo;
-                split_bf8(v8, hi, lo);
-                F.xh[nb][s] = to_agpr(hi);
-                F.xl[nb][s] = to_agpr(lo);
+                if constexpr (PREC == TAC_BF16) {
+                    bf8 hi, lo;
+                    split_bf8(v8, hi, lo);
+                    F.xh[nb][s] = to_agpr(hi);
+                    F.xl[nb][s] = to_agpr(lo);
+                } else {
+                    h8 h;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        h[e] = (_Float16)v8[e];
+                        const float r = v8[e] - (float)h[e];  // exact: h is v rounded to a coarser grid
+                        dyy = dyy + r * r;
+                    }
+                    F.xh[nb][s] = to_agpr(h);
+                }
             }
             xx += __shfl_xor(xx, 16);
             xx += __shfl_xor(xx, 32);
             xxmax = fmaxf(xxmax, xx);
+            if constexpr (PREC == TAC_F16) {
+                dyy += __shfl_xor(dyy, 16);
+                dyy += __shfl_xor(dyy, 32);
+                if (g == 0) sdx[nb * 16 + col] = dyy;
+            }
         }
     }
     // keep every fragment write far above the first matrix-core read
@@ -387,9 +447,11 @@ __device__ __forceinline__ void glist_init(unsigned* glist) {
 
 // Fold the epoch's packed keys into the merged lists and reset them.  A key's
 // low 8 bits are (16-block within the epoch) * 4 + r; ebase is the global index
-// of the epoch's first centroid plus 4g.
+// of the epoch's first centroid plus 4g, kend one past the token's last centroid.
+// Padding columns past kend carry huge screen values and never enter the merged
+// list; the index check also holds when non-finite operands made them small.
 template <int NB, int LK, class Key>
-__device__ __forceinline__ void epoch_flush(Key (&el)[NB][4], unsigned* glist, int64_t ebase) {
+__device__ __forceinline__ void epoch_flush(Key (&el)[NB][4], unsigned* glist, int64_t ebase, int64_t kend) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         float G[4];
@@ -405,7 +467,7 @@ __device__ __forceinline__ void epoch_flush(Key (&el)[NB][4], unsigned* glist, i
             const float t = __uint_as_float(bits & ~0xFFu);
             const unsigned loc = bits & 0xFFu;
             const int gi = (int)(ebase + (int64_t)(loc >> 2) * 16 + (loc & 3u));
-            if (t < 1.0e38f) glist_insert<LK>(G, I, t, gi, false);
+            if (t < 1.0e38f && gi < kend) glist_insert<LK>(G, I, t, gi, false);
             el[nb][e] = key_empty<Key>();
         }
 #pragma unroll
@@ -424,12 +486,28 @@ __device__ __forceinline__ void epoch_flush(Key (&el)[NB][4], unsigned* glist, i
 // the lexicographic (distance, index) minimum, and certifies it against every
 // candidate a list dropped: a dropped value is at least its list's last entry.
 // Rows whose certificate fails are queued for exhaustive rescoring.
+//
+// The screen error bound E covers, per screen value:
+// * FP32 accumulation: every product and partial sum rounded, the sum of
+//   |terms| at most 2(||c||^2 + beta) + 2 ||x|| ||c|| (with a 10% margin on the
+//   norms); gamma_130 for the FP32 screen, gamma_386 for BF16's three products
+//   per coordinate, gamma_260 for FP16 (one product, doubled for the unknown
+//   summation order inside the matrix core);
+// * operand rounding: BF16 hi/lo splits leave at most 3 * 2^-16 |x_i| |c_i| per
+//   coordinate (6.2 * 2^-16 ||x|| ||c|| after the -2 factor and margin); FP16
+//   rounds y = -2x and c once, and with dy = y - f16(y), dc = c - f16(c) the
+//   dot error y.c - f16(y).f16(c) = f16(y).dc + dy.f16(c) + dy.dc is bounded by
+//   Cauchy-Schwarz with the measured norms ||dy|| (per row) and max ||dc||.
 template <int PREC, int NB, int LK>
 __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t row0, int64_t s1,
-                                            const unsigned* glist, float beta, float cnmax, float cmax, int lane) {
+                                            const unsigned* glist, float beta, float cnmax, float cmax, int lane,
+                                            const float* sdx = nullptr) {
     const double u = 5.9604644775390625e-8;  // 2^-24
     const double g130 = 130.0 * u / (1.0 - 130.0 * u);
+    const double g260 = 260.0 * u / (1.0 - 260.0 * u);
     const double g386 = 386.0 * u / (1.0 - 386.0 * u);
+    // FP16: largest ||c - f16(c)|| over the centroids (upper bound of the FP32 sum)
+    const double dcm = PREC == TAC_F16 ? sqrt((double)__uint_as_float(P.cstat[2]) * (1.0 + 1e-4)) : 0.0;
     const double bt = (double)beta;
     const double cm = (double)cmax, cn2 = (double)cnmax;
     const unsigned* wlist = glist - lane;  // this wave's list slots: lane L's slot (nb, e) at (nb * 8 + e) * 64 + L
@@ -456,24 +534,33 @@ __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t 
         const int64_t r = P.rowmap ? (int64_t)P.rowmap[v] : v;
         const float* xr = P.x + r * kDim;
         bool ok = false;
-        float bd = INFINITY;
+        float bd = INFINITY, xxq = INFINITY;
         int bi = INT32_MAX;
         if (i0 >= 0) {
             float xxc;
             bd = dist32_rows(xr, P.C + (int64_t)i0 * kDim, &xxc);
+            xxq = xxc;
             bi = i0;
             // canonical ||x - c||^2 >= (screen - E - beta + ||x||^2) (1 - g130) for every candidate
             const double xx_hi = (double)xxc * (1.0 + g130);
             const double xx_lo = (double)xxc * (1.0 - g130);
             const double xn = sqrt(xx_hi);
             double E;
-            if constexpr (PREC == TAC_FP32)
+            if constexpr (PREC == TAC_FP32) {
                 E = 1.1 * (g130 * (2.0 * (cn2 + bt) + 2.0 * xn * cm));
-            else
+            } else if constexpr (PREC == TAC_BF16) {
                 E = 1.1 * (g386 * (2.0 * (cn2 + bt) + 2.2 * xn * cm) + 6.2 * 1.52587890625e-5 * xn * cm);
+            } else {
+                const double dyn = sqrt((double)sdx[q] * (1.0 + 1e-4));  // ||-2x - f16(-2x)||, upper bound
+                const double yn = 2.0 * xn + dyn;                         // ||f16(-2x)||
+                E = 1.1 * (g260 * (2.0 * (cn2 + bt) + 2.2 * xn * cm) + yn * dcm + dyn * (cm + dcm) + dyn * dcm);
+            }
             E += 1e-30;
+            // a non-finite bound (operands beyond the 16-bit range, infinite
+            // inputs) proves nothing: the row goes to exhaustive rescoring
+            const bool bounded = E < 1e30;
             const double shift = -E - bt + xx_lo;
-            for (int g = 0; g < 4; ++g) {
+            for (int g = 0; g < (bounded ? 4 : 0); ++g) {
                 const unsigned* sl = wlist + nb * 8 * 64 + 16 * g + c;
 #pragma unroll
                 for (int e = 0; e < LK; ++e) {
@@ -487,15 +574,17 @@ __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t 
                     }
                 }
             }
-            ok = (double)tau >= 1.0e38 || ((double)tau + shift) * (1.0 - g130) > (double)bd;
+            ok = bounded && ((double)tau >= 1.0e38 || ((double)tau + shift) * (1.0 - g130) > (double)bd);
         }
         if (ok) {
             P.assign[r] = bi;
             P.dist[r] = bd;
         } else {
-            const unsigned long long qf = atomicAdd(&P.counters[kCntFallback], 1ull);
-            P.fb[2 * qf] = (int32_t)v;
-            P.fb[2 * qf + 1] = j;
+            const int64_t qi = P.seg_off[j] + atomicAdd(&P.fbcnt[j], 1);
+            P.fbq[qi] = (int32_t)r;
+            P.fbxx[qi] = xxq;
+            P.fbslot[qi] = bi < INT32_MAX ? ((unsigned long long)__float_as_uint(bd) << 32) | (unsigned)bi : ~0ull;
+            atomicAdd(&P.counters[kCntFallback], 1ull);
         }
     }
     for (int m = 32; m > 0; m >>= 1) nscreen += __shfl_xor(nscreen, m);
@@ -603,7 +692,7 @@ __device__ __forceinline__ void screen_item_fp32(const Params& P, int32_t j, int
                 for (int r = 0; r < 4; ++r) list_insert(el[nb], (__float_as_uint(acc[nb][r]) & ~0xFFu) | (lb + r));
             const bool last = (blk16 + 1) * 16 >= kc;
             if (blk16 - epoch_first == kEpochBlocks - 1 || last) {
-                epoch_flush<NB, 4, unsigned>(el, glist, k0 + (int64_t)epoch_first * 16 + 4 * g);
+                epoch_flush<NB, 4, unsigned>(el, glist, k0 + (int64_t)epoch_first * 16 + 4 * g, k0 + kc);
                 epoch_first = blk16 + 1;
             }
         }
@@ -613,63 +702,114 @@ __device__ __forceinline__ void screen_item_fp32(const Params& P, int32_t j, int
     finish_item<TAC_FP32, NB, 4>(P, j, row0, s1, glist, beta, cnmax, cmax, lane);
 }
 
-// ---- BF16 screen: 4 waves (one per SIMD) x 5 column blocks of 16 rows = 320 rows per item ----
-// The wave's x operands (hi and lo BF16 splits of -2x) stay in AGPRs for the
-// whole item.  Centroid stages of 64 rows (hi and lo halves, 512 B per
-// centroid) go straight from global memory into LDS (global_load_lds_dwordx4,
-// no registers), three buffers deep, with the 16-byte chunks of row r stored
-// at chunk ^ (r & 15) so that the fragment reads of 16 consecutive rows hit
-// distinct banks without padding.  The 16-centroid block loop is software
-// pipelined: while the matrix cores run block b, the wave reads block b + 1's
-// fragments from LDS and folds block b - 1's screen values into its top-3
-// lists, so the three streams (matrix, LDS, vector) overlap.
+// ---- 16-bit screens: 4 waves (one per SIMD) x 5 column blocks of 16 rows = 320 rows per item ----
+// The wave's x operands (16-bit fragments of -2x: hi and lo BF16 splits, or
+// one FP16 rounding) stay in AGPRs for the whole item.  Centroid stages of
+// 32 KiB (64 centroids of hi/lo BF16 rows, 512 B each, or 128 centroids of
+// FP16 rows, 256 B each) go straight from global memory into LDS
+// (global_load_lds_dwordx4, no registers), three buffers deep, with the
+// 16-byte chunks of row r stored at chunk ^ (r & 15) so that the fragment
+// reads of 16 consecutive rows hit distinct banks without padding.  The
+// 16-centroid block loop is software pipelined: while the matrix cores run
+// block b, the wave reads block b + 1's fragments from LDS and folds block
+// b - 1's screen values into its top-3 lists, so the three streams (matrix,
+// LDS, vector) overlap.
 constexpr int kBThreads = 256;
 constexpr int kBWaves = kBThreads / 64;
 constexpr int kBNB = 5;
-// Per-lane list length of the BF16 screen: a top-3 costs one med3 less per
+// Per-lane list length of the 16-bit screens: a top-3 costs one med3 less per
 // screen value than a top-4; the certificate then fails on a few more rows
 // (their exhaustive rescoring is batched), which is the cheaper side of the trade.
 constexpr int kBLK = 3;
 constexpr int kBTileRows = kBWaves * kBNB * 16;
-constexpr int kBStage = 64;                               // centroids per stage
 constexpr int kBBufs = 3;                                 // stage buffers
-constexpr int kBStageWords = kBStage * 128;               // 512 B per centroid
+constexpr int kBStageWords = 8192;                        // 32 KiB per stage buffer
+constexpr int kBCnStride = 128;                           // norms per stage buffer (room for FP16's 128)
 constexpr size_t kBCnOffsetWords = (size_t)kBBufs * kBStageWords;
-constexpr size_t kBGlistOffsetWords = kBCnOffsetWords + (size_t)kBBufs * kBStage;
-constexpr size_t kBLdsBytes = (kBGlistOffsetWords + (size_t)kBWaves * kBNB * 8 * 64) * 4;
+constexpr size_t kBGlistOffsetWords = kBCnOffsetWords + (size_t)kBBufs * kBCnStride;
+constexpr size_t kBDxOffsetWords = kBGlistOffsetWords + (size_t)kBWaves * kBNB * 8 * 64;
+constexpr size_t kBLdsBytes = (kBDxOffsetWords + (size_t)kBWaves * kBNB * 16) * 4;
 static_assert(kBLdsBytes + 16 <= 160 * 1024, "fits the LDS of a CU");
+
+// Stage geometry of a 16-bit screen: bytes per centroid row and centroids per stage.
+template <int PREC>
+struct StageGeom {
+    static constexpr int kRowBytes = PREC == TAC_BF16 ? 512 : 256;
+    static constexpr int kCents = kBStageWords * 4 / kRowBytes;  // 64 or 128
+    static constexpr int kBlocks = kCents / 16;                  // 16-centroid blocks per stage
+};
 
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
 
-// Issue the DMA of stage `st` (centroids st*64 .. st*64+63 of the token) into
-// `buf`: 32 pairs of rows, 1 KiB each, eight pairs per wave.  Lane l moves
-// 16 bytes of row 2*pair + (l >> 5) into physical chunk l & 31.  Rows past the
-// token's last centroid repeat it (their norms mark them invalid).
-__device__ __forceinline__ void bf_stage_issue(const char* __restrict__ chl, int64_t k0, int kc, int st,
-                                               unsigned* buf, int wave, int lane) {
-    static_assert(kBStage / 2 % kBWaves == 0, "row pairs split evenly over the waves");
+// Issue the DMA of stage `st` (centroids st*S .. st*S+S-1 of the token) into
+// `buf` and its norms into `bcn`: the rows as 32 wave-wide transfers of 1 KiB
+// (two BF16 or four FP16 rows), eight per wave, and the norms as one 4-byte
+// transfer per wave (S / 4 lanes each), so that every wave issues exactly
+// kStageOps vector-memory instructions per stage.  Lane l moves 16 bytes of row
+// (1 KiB group) * rows + l / chunks into physical chunk l % chunks.  Rows past
+// the token's last centroid repeat it, and their norms come from
+// g_invalid_norm, which makes their screen values huge.
+constexpr int kStageOps = kBStageWords / 256 / kBWaves + 1;
+__device__ const float g_invalid_norm = kInvalid;
+template <int PREC>
+__device__ __forceinline__ void bf_stage_issue(const char* __restrict__ chl, const float* __restrict__ cn, int64_t k0,
+                                               int kc, int st, unsigned* buf, float* bcn, int wave, int lane) {
+    constexpr int RB = StageGeom<PREC>::kRowBytes;
+    constexpr int RPI = 1024 / RB;  // rows per transfer
+    constexpr int CPR = RB / 16;    // chunks per row
+    static_assert(kBStageWords / 256 % kBWaves == 0, "transfers split evenly over the waves");
+    constexpr int PER = kBStageWords / 256 / kBWaves;
 #pragma unroll
-    for (int i = 0; i < kBStage / 2 / kBWaves; ++i) {
-        const int pair = wave * (kBStage / 2 / kBWaves) + i;
-        const int row = 2 * pair + (lane >> 5);
-        int kk = st * kBStage + row;
+    for (int i = 0; i < PER; ++i) {
+        const int grp = wave * PER + i;
+        const int row = RPI * grp + lane / CPR;
+        int kk = st * StageGeom<PREC>::kCents + row;
         kk = kk < kc ? kk : kc - 1;
-        const int chunk = (lane & 31) ^ (row & 15);
-        const char* src = chl + (k0 + kk) * 512 + chunk * 16;
-        __builtin_amdgcn_global_load_lds(src, (lds_void_ptr)(buf + pair * 256), 16, 0, 0);
+        const int chunk = (lane % CPR) ^ (row & 15);
+        const char* src = chl + (k0 + kk) * RB + chunk * 16;
+        __builtin_amdgcn_global_load_lds(src, (lds_void_ptr)(buf + grp * 256), 16, 0, 0);
+    }
+    constexpr int NPW = StageGeom<PREC>::kCents / kBWaves;  // norms per wave
+    if (lane < NPW) {
+        const int kk = st * StageGeom<PREC>::kCents + wave * NPW + lane;
+        const float* src = kk < kc ? cn + k0 + kk : &g_invalid_norm;
+        __builtin_amdgcn_global_load_lds(src, (lds_void_ptr)(bcn + wave * NPW), 4, 0, 0);
     }
 }
 
-// One 16-centroid block's operands in registers: hi/lo fragments for the four
-// k-steps and the accumulator start (norms + beta) of the lane's four columns.
-struct BBlock {
+// Workgroup barrier without a memory fence: the stage pipeline waits for its
+// own transfers with counted vmcnt waits, which a fenced barrier would turn
+// into waits for every transfer in flight.  The empty asm statements keep the
+// compiler from moving memory accesses across it.
+__device__ __forceinline__ void bare_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// One 16-centroid block's operands in registers: the fragments for the four
+// k-steps (hi and lo for BF16) and the accumulator start (norms + beta) of the
+// lane's four columns.
+template <int PREC>
+struct BBlock;
+template <>
+struct BBlock<TAC_BF16> {
     bf8 ch[4];
     bf8 cl[4];
     f4 cb;
 };
+template <>
+struct BBlock<TAC_F16> {
+    h8 ch[4];
+    f4 cb;
+};
 
-__device__ __forceinline__ void screen_item_bf16(const Params& P, int32_t j, int64_t tile, unsigned* lds) {
+template <int PREC>
+__device__ __forceinline__ void screen_item_mx(const Params& P, int32_t j, int64_t tile, unsigned* lds) {
     constexpr int NB = kBNB;
+    constexpr int SC = StageGeom<PREC>::kCents;
+    constexpr int BPS = StageGeom<PREC>::kBlocks;
+    constexpr int RW = StageGeom<PREC>::kRowBytes / 4;  // words per staged row
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4;
@@ -682,23 +822,18 @@ __device__ __forceinline__ void screen_item_bf16(const Params& P, int32_t j, int
     const float cmax = sqrtf(cnmax) * (1.0f + 1e-6f);
 
     unsigned* stage = lds;                                               // [3][kBStageWords]
-    float* stage_cn = reinterpret_cast<float*>(lds + kBCnOffsetWords);   // [3][kBStage]
+    float* stage_cn = reinterpret_cast<float*>(lds + kBCnOffsetWords);   // [3][kBCnStride]
     unsigned* glist = lds + kBGlistOffsetWords + (unsigned)wave * (NB * 8 * 64) + lane;
+    float* sdx = reinterpret_cast<float*>(lds + kBDxOffsetWords) + wave * (NB * 16);
     const char* chl = static_cast<const char*>(P.cstage);
-    const int nst = (kc + kBStage - 1) / kBStage;
+    const int nst = (kc + SC - 1) / SC;
     const int nblk = (kc + 15) / 16;
 
-    // stage 0 and its norms first, so their latency overlaps the x prologue
-    bf_stage_issue(chl, k0, kc, 0, stage, wave, lane);
-    if (threadIdx.x < kBStage) stage_cn[threadIdx.x] = (int)threadIdx.x < kc ? P.cn[k0 + threadIdx.x] : kInvalid;
-    float pcn = kInvalid;  // norms of the next stage to publish (threads < 64)
-    if (nst > 1 && threadIdx.x < kBStage) {
-        const int kk = kBStage + threadIdx.x;
-        pcn = kk < kc ? P.cn[k0 + kk] : kInvalid;
-    }
+    // stage 0 first, so that its latency overlaps the x prologue
+    bf_stage_issue<PREC>(chl, P.cn, k0, kc, 0, stage, stage_cn, wave, lane);
 
-    Frag<TAC_BF16, NB> F;
-    const float xxmax = load_x_frags<TAC_BF16, NB>(P, row0, s1, g, col, F);
+    Frag<PREC, NB> F;
+    const float xxmax = load_x_frags<PREC, NB>(P, row0, s1, g, col, F, sdx);
     // One shift for the whole wave makes every screen value positive (see the FP32 screen).
     const float beta = xxmax * (1.0f + 0.00390625f) + 0.00390625f * cnmax + 1e-30f;
     float el[NB][4];
@@ -709,34 +844,46 @@ __device__ __forceinline__ void screen_item_bf16(const Params& P, int32_t j, int
     glist_init<NB>(glist);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    if (nst > 1) bf_stage_issue(chl, k0, kc, 1, stage + kBStageWords, wave, lane);
+    // stages 1 and 2 in flight: the pipeline keeps two stages ahead of the one being read
+    if (nst > 1) bf_stage_issue<PREC>(chl, P.cn, k0, kc, 1, stage + kBStageWords, stage_cn + kBCnStride, wave, lane);
+    if (nst > 2)
+        bf_stage_issue<PREC>(chl, P.cn, k0, kc, 2, stage + 2 * kBStageWords, stage_cn + 2 * kBCnStride, wave, lane);
 
     int epoch_first = 0;
-    auto load_block = [&](int blk, BBlock& B) {
-        const int buf = (blk >> 2) % kBBufs;
-        const int b = blk & 3;
-        const unsigned* srow = stage + buf * kBStageWords + (b * 16 + col) * 128;
+    auto load_block = [&](int blk, BBlock<PREC>& B) {
+        const int buf = (blk / BPS) % kBBufs;
+        const int b = blk % BPS;
+        const unsigned* srow = stage + buf * kBStageWords + (b * 16 + col) * RW;
 #pragma unroll
         for (int st4 = 0; st4 < 4; ++st4) {
-            B.ch[st4] = *reinterpret_cast<const bf8*>(srow + 4 * ((4 * g + st4) ^ col));
-            B.cl[st4] = *reinterpret_cast<const bf8*>(srow + 4 * ((16 + 4 * g + st4) ^ col));
+            if constexpr (PREC == TAC_BF16) {
+                B.ch[st4] = *reinterpret_cast<const bf8*>(srow + 4 * ((4 * g + st4) ^ col));
+                B.cl[st4] = *reinterpret_cast<const bf8*>(srow + 4 * ((16 + 4 * g + st4) ^ col));
+            } else {
+                B.ch[st4] = *reinterpret_cast<const h8*>(srow + 4 * ((4 * g + st4) ^ col));
+            }
         }
-        B.cb = *reinterpret_cast<const f4*>(stage_cn + buf * kBStage + b * 16 + 4 * g) + beta;
+        B.cb = *reinterpret_cast<const f4*>(stage_cn + buf * kBCnStride + b * 16 + 4 * g) + beta;
     };
-    auto mfmas = [&](const BBlock& B, f4 (&acc)[NB]) {
-#pragma unroll
-        for (int st4 = 0; st4 < 4; ++st4) {
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B.ch[st4], F.xh[nb][st4], st4 == 0 ? B.cb : acc[nb],
-                                                                  0, 0, 0);
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B.ch[st4], F.xl[nb][st4], acc[nb], 0, 0, 0);
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B.cl[st4], F.xh[nb][st4], acc[nb], 0, 0, 0);
+    // the matrix-core products of one k-step term: BF16 has three (hi.hi, hi.lo, lo.hi), FP16 one
+    constexpr int NPR = PREC == TAC_BF16 ? 3 : 1;
+    auto mfma1 = [&](const BBlock<PREC>& B, int st4, int pr, int nb, const f4& c) -> f4 {
+        if constexpr (PREC == TAC_BF16) {
+            const bf8 av = pr == 2 ? B.cl[st4] : B.ch[st4];
+            const bf8 bv = pr == 1 ? F.xl[nb][st4] : F.xh[nb][st4];
+            return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+        } else {
+            return __builtin_amdgcn_mfma_f32_16x16x32_f16(B.ch[st4], F.xh[nb][st4], c, 0, 0, 0);
         }
+    };
+    auto mfmas = [&](const BBlock<PREC>& B, f4 (&acc)[NB]) {
+#pragma unroll
+        for (int st4 = 0; st4 < 4; ++st4)
+#pragma unroll
+            for (int pr = 0; pr < NPR; ++pr)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[nb] = mfma1(B, st4, pr, nb, (st4 == 0 && pr == 0) ? B.cb : acc[nb]);
     };
     // top-k inserts of block blk's screen values; the key's low byte becomes
     // the value's position in the epoch ((block in epoch) * 4 + r)
@@ -750,61 +897,70 @@ __device__ __forceinline__ void screen_item_bf16(const Params& P, int32_t j, int
                                                                           0x07060500u)));
     };
     // Steady-state block: the MFMAs of block B interleaved by hand with the
-    // top-k inserts of the previous block (one insert after every third MFMA);
-    // scheduling barriers keep that order, so the vector work fills the
-    // matrix pipeline's gaps instead of bunching up.
-    auto mfmas_inserts = [&](const BBlock& B, f4 (&acc)[NB], int pblk, const f4 (&prev)[NB]) {
+    // top-k inserts of the previous block (one insert after every third BF16
+    // MFMA, after every FP16 MFMA); scheduling barriers keep that order, so the
+    // vector work fills the matrix pipeline's gaps instead of bunching up.  The
+    // inserts visit the NB lists round-robin (value v goes to list v % NB), and
+    // each key is packed one group ahead of its insert, so no vector
+    // instruction waits on the one issued just before it.
+    auto mfmas_inserts = [&](const BBlock<PREC>& B, f4 (&acc)[NB], int pblk, const f4 (&prev)[NB]) {
         const unsigned lb = (unsigned)(pblk - epoch_first) * 4u;
+        auto key = [&](int v) {
+            return __uint_as_float(
+                __builtin_amdgcn_perm(__float_as_uint(prev[v % NB][v / NB]), lb + (unsigned)(v / NB), 0x07060500u));
+        };
+        float kcur = key(0);
 #pragma unroll
         for (int st4 = 0; st4 < 4; ++st4)
 #pragma unroll
-            for (int pr = 0; pr < 3; ++pr)
+            for (int pr = 0; pr < NPR; ++pr)
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    const bf8 av = pr == 2 ? B.cl[st4] : B.ch[st4];
-                    const bf8 bv = pr == 1 ? F.xl[nb][st4] : F.xh[nb][st4];
-                    acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, (st4 == 0 && pr == 0) ? B.cb : acc[nb],
-                                                                      0, 0, 0);
-                    const int i = (st4 * 3 + pr) * NB + nb;
-                    if (i % 3 == 2) {
-                        const int v = i / 3;
-                        if (v < 4 * NB)
-                            list_insert<kBLK>(el[v >> 2],
-                                              __uint_as_float(__builtin_amdgcn_perm(
-                                                  __float_as_uint(prev[v >> 2][v & 3]), lb + (v & 3), 0x07060500u)));
+                    acc[nb] = mfma1(B, st4, pr, nb, (st4 == 0 && pr == 0) ? B.cb : acc[nb]);
+                    const int i = (st4 * NPR + pr) * NB + nb;
+                    if (i % NPR == NPR - 1) {
+                        const int v = i / NPR;
+                        if (v < 4 * NB) {
+                            const float knext = v + 1 < 4 * NB ? key(v + 1) : 0.f;
+                            list_insert<kBLK>(el[v % NB], kcur);
+                            kcur = knext;
+                        }
                         __builtin_amdgcn_sched_barrier(0);
                     }
                 }
     };
     auto flush_if = [&](int blk) {
         if (blk - epoch_first == kEpochBlocks - 1 || blk + 1 == nblk) {
-            epoch_flush<NB, kBLK, float>(el, glist, k0 + (int64_t)epoch_first * 16 + 4 * g);
+            epoch_flush<NB, kBLK, float>(el, glist, k0 + (int64_t)epoch_first * 16 + 4 * g, k0 + kc);
             epoch_first = blk + 1;
         }
     };
-    // Before block blk = 4s + 3 (its region reads block 4s + 4's operands):
-    // publish stage s + 1 (its DMA was issued during stage s) and start the DMA
-    // of stage s + 2 into the buffer stage s - 1 used.
+    // Before the last block of stage s (its region reads the first block of
+    // stage s + 1's operands): wait until stage s + 1 has landed (each wave
+    // waits for its own transfers, counting out stage s + 2's, which stay in
+    // flight), make sure no wave still reads stage s's buffer (its last
+    // operand reads were issued in the previous region), then start the DMA of
+    // stage s + 3 into that buffer.  Two stages of transfers are thus always
+    // in flight behind the one being read.
     auto stage_turn = [&](int blk) {
-        if ((blk & 3) != 3) return;
-        const int sn = (blk >> 2) + 1;
+        if (blk % BPS != BPS - 1) return;
+        const int sn = blk / BPS + 1;
         if (sn >= nst) return;
-        if (threadIdx.x < kBStage) stage_cn[(sn % kBBufs) * kBStage + threadIdx.x] = pcn;
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        if (sn + 1 < nst) {
-            bf_stage_issue(chl, k0, kc, sn + 1, stage + ((sn + 1) % kBBufs) * kBStageWords, wave, lane);
-            if (threadIdx.x < kBStage) {
-                const int kk = (sn + 1) * kBStage + threadIdx.x;
-                pcn = kk < kc ? P.cn[k0 + kk] : kInvalid;
-            }
-        }
+        static_assert(kStageOps == 9, "the counted wait below matches the transfers per stage");
+        if (sn + 1 < nst)
+            asm volatile("s_waitcnt vmcnt(9) lgkmcnt(0)" ::: "memory");
+        else
+            asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+        bare_barrier();
+        if (sn + 2 < nst)
+            bf_stage_issue<PREC>(chl, P.cn, k0, kc, sn + 2, stage + ((sn + 2) % kBBufs) * kBStageWords,
+                                 stage_cn + ((sn + 2) % kBBufs) * kBCnStride, wave, lane);
     };
 
     // Pipeline over the blocks: region(b) = MFMAs of b, operands of b + 1,
     // inserts of b - 1.  Unrolled by two so that operand and accumulator
     // sets alternate without copies.
-    BBlock BA, BB;
+    BBlock<PREC> BA, BB;
     f4 accA[NB], accB[NB];
     load_block(0, BA);
     if (nblk == 1) {
@@ -844,16 +1000,16 @@ __device__ __forceinline__ void screen_item_bf16(const Params& P, int32_t j, int
             flush_if(blk - 1);
         }
     }
-    finish_item<TAC_BF16, NB, kBLK>(P, j, row0, s1, glist, beta, cnmax, cmax, lane);
+    finish_item<PREC, NB, kBLK>(P, j, row0, s1, glist, beta, cnmax, cmax, lane, sdx);
 }
 
 template <int PREC>
-__global__ void __launch_bounds__(PREC == TAC_BF16 ? kBThreads : kThreads) assign_main(Params P) {
+__global__ void __launch_bounds__(PREC == TAC_FP32 ? kThreads : kBThreads) assign_main(Params P) {
     // All shared memory is dynamic so that it starts 16-byte aligned (a static
     // variable in front of it would shift every 16-byte LDS access off alignment).
     extern __shared__ __attribute__((aligned(16))) unsigned lds[];
     unsigned long long* s_item = reinterpret_cast<unsigned long long*>(
-        lds + (PREC == TAC_BF16 ? kBLdsBytes : kLdsBytes) / 4);
+        lds + (PREC == TAC_FP32 ? kLdsBytes : kBLdsBytes) / 4);
     const int64_t total = P.item_off[3 * (int64_t)P.T];
     if (threadIdx.x == 0) *s_item = atomicAdd(P.work, 1ull);
     __syncthreads();
@@ -867,11 +1023,11 @@ __global__ void __launch_bounds__(PREC == TAC_BF16 ? kBThreads : kThreads) assig
         const int cls = idx / P.T;
         const int32_t j = idx - cls * P.T;
         const int64_t tile = item - P.item_off[idx];
-        if constexpr (PREC == TAC_BF16) {
+        if constexpr (PREC != TAC_FP32) {
             if (cls == 2)
                 direct_item<kBThreads>(P, j, tile);
             else
-                screen_item_bf16(P, j, tile, lds);
+                screen_item_mx<PREC>(P, j, tile, lds);
         } else {
             if (cls == 2)
                 direct_item<kThreads>(P, j, tile);
@@ -885,119 +1041,159 @@ __global__ void __launch_bounds__(PREC == TAC_BF16 ? kBThreads : kThreads) assig
     }
 }
 
-// Exhaustive canonical rescoring of the rows whose certificate failed.  The
-// queue is cut into batches of kFbRows consecutive rows (rows of one work item
-// are queued together, so a batch mostly shares one token); a work item
-// (batch, chunk c) streams centroids [c * kFbChunk, (c + 1) * kFbChunk) of
-// each token in the batch once for all of that token's rows, whose x rows sit
-// in LDS.  Each row's best (distance, index) is folded into its 64-bit slot
-// with atomicMin; non-negative float bits in the high word order like the
-// distances, so the slot ends at the lexicographic minimum whatever the order
-// of the blocks.
-constexpr int kFbRows = 16;
-constexpr int kFbChunk = 512;
+// Rescoring of the rows whose certificate failed, on the matrix cores.  The
+// queue holds each token's failed rows together (see Params), so a work item
+// is (token j, batch of kFbRows of its failed rows, chunk c of its
+// centroids): the chunk's centroid rows stream once for the whole batch, the
+// FP32 matrix-core screen value cn - 2 x.c of every (row, centroid) pair goes
+// to LDS, and each row rescores exactly every centroid of the chunk whose
+// screen lower bound (screen - E + ||x||^2) (1 - g130) does not exceed the
+// distance in its slot (E is the FP32 screen's error bound).  The slot starts
+// at the row's best exact candidate from the screen and takes the 64-bit
+// atomicMin over chunks: non-negative float bits in the high word order like
+// the distances, so it ends at the exact lexicographic (distance, index)
+// minimum whatever the order of the work items.
+constexpr int kFbRows = 64;
+constexpr int kFbChunk = 128;
+constexpr int kFbXStride = kDim + 4;         // LDS row stride of x (fewer bank conflicts)
+constexpr int kFbSStride = kFbChunk + 16;    // LDS row stride of the screen values
 
-__global__ void fb_init(const unsigned long long* __restrict__ counters, unsigned long long* __restrict__ slot) {
-    const int64_t nfb = (int64_t)counters[kCntFallback];
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nfb; q += (int64_t)gridDim.x * blockDim.x)
-        slot[q] = ~0ull;
+__global__ void fb_zero(int32_t* __restrict__ fbcnt, int32_t T) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < T; j += (int64_t)gridDim.x * blockDim.x)
+        fbcnt[j] = 0;
+}
+
+// work items per token: (batches of its failed rows) x (chunks of its centroids)
+__global__ void fb_plan(const int32_t* __restrict__ fbcnt, const int64_t* __restrict__ cent_off, int32_t T,
+                        int64_t* __restrict__ wcnt) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= T) return;
+    const int64_t c = fbcnt[j];
+    const int64_t k = cent_off[j + 1] - cent_off[j];
+    wcnt[j] = c > 0 ? ((c + kFbRows - 1) / kFbRows) * ((k + kFbChunk - 1) / kFbChunk) : 0;
 }
 
 __device__ __forceinline__ unsigned long long min_u64(unsigned long long a, unsigned long long b) { return a < b ? a : b; }
 
-__global__ void __launch_bounds__(256) fb_batch(const float* __restrict__ x, const int32_t* __restrict__ rowmap,
-                                                const int64_t* __restrict__ cent_off, const float* __restrict__ C,
-                                                const int32_t* __restrict__ fb,
-                                                const unsigned long long* __restrict__ counters,
-                                                const unsigned* __restrict__ kmax,
-                                                unsigned long long* __restrict__ slot) {
-    __shared__ float xs[kFbRows * kDim];
-    __shared__ int tj[kFbRows];
-    __shared__ unsigned long long red[kFbRows * 4];
-    const int64_t nfb = (int64_t)counters[kCntFallback];
-    const int64_t nbatch = (nfb + kFbRows - 1) / kFbRows;
-    const int64_t nchunk = ((int64_t)kmax[0] + kFbChunk - 1) / kFbChunk;
-    const int64_t total = nbatch * nchunk;
+__global__ void __launch_bounds__(256) fb_screen(const float* __restrict__ x, const int64_t* __restrict__ seg_off,
+                                                 const int64_t* __restrict__ cent_off, int32_t T,
+                                                 const float* __restrict__ C, const float* __restrict__ cn,
+                                                 const unsigned* __restrict__ cstat, const int64_t* __restrict__ woff,
+                                                 const int32_t* __restrict__ fbcnt, const int32_t* __restrict__ fbq,
+                                                 const float* __restrict__ fbxx,
+                                                 unsigned long long* __restrict__ fbslot) {
+    __shared__ __attribute__((aligned(16))) float xs[kFbRows * kFbXStride];
+    __shared__ float sv[kFbRows * kFbSStride];
+    const double u = 5.9604644775390625e-8;  // 2^-24
+    const double g130 = 130.0 * u / (1.0 - 130.0 * u);
+    const float cnmax = __uint_as_float(cstat[0]) * (1.0f + 1e-5f);
+    const double cn2 = (double)cnmax, cm = (double)(sqrtf(cnmax) * (1.0f + 1e-6f));
+    const int64_t total = woff[T];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    constexpr int kTpr = 256 / kFbRows;  // row phase: threads per row
+    const int rr = threadIdx.x / kTpr, sub = threadIdx.x % kTpr;
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-        const int64_t b = w / nchunk;
-        const int64_t chunk = w % nchunk;
-        const int64_t q0 = b * kFbRows;
-        const int nq = (int)min((int64_t)kFbRows, nfb - q0);
-        __syncthreads();  // the previous work item is done with xs, tj and red
-        for (int e = threadIdx.x; e < nq * kDim; e += blockDim.x) {
-            const int rr = e / kDim;
-            const int64_t v = fb[2 * (q0 + rr)];
-            const int64_t r = rowmap ? (int64_t)rowmap[v] : v;
-            xs[e] = x[r * kDim + (e % kDim)];
+        // token: the last j with woff[j] <= w
+        int lo_j = 0, hi_j = T;
+        while (hi_j - lo_j > 1) {
+            const int mid = (lo_j + hi_j) >> 1;
+            if (woff[mid] <= w) lo_j = mid; else hi_j = mid;
         }
-        if ((int)threadIdx.x < nq) tj[threadIdx.x] = fb[2 * (q0 + threadIdx.x) + 1];
+        const int j = lo_j;
+        const int64_t k0 = cent_off[j];
+        const int64_t kc = cent_off[j + 1] - k0;
+        const int64_t nch = (kc + kFbChunk - 1) / kFbChunk;
+        const int64_t local = w - woff[j];
+        const int64_t e0 = (local / nch) * kFbRows;
+        const int64_t lo = k0 + (local % nch) * kFbChunk;
+        const int n = (int)min((int64_t)kFbChunk, k0 + kc - lo);
+        const int nr = (int)min((int64_t)kFbRows, (int64_t)fbcnt[j] - e0);
+        const int64_t qb = seg_off[j] + e0;
+        __syncthreads();  // the previous work item is done with xs and sv
+        for (int e = threadIdx.x; e < kFbRows * (kDim / 4); e += blockDim.x) {
+            const int r = e / (kDim / 4);
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r < nr) v = reinterpret_cast<const float4*>(x + (int64_t)fbq[qb + r] * kDim)[e % (kDim / 4)];
+            *reinterpret_cast<float4*>(xs + r * kFbXStride + 4 * (e % (kDim / 4))) = v;
+        }
         __syncthreads();
-        unsigned long long best[kFbRows];
+        // screen: wave w takes 16-centroid blocks w, w + 4; lane (g, col) holds the
+        // block's centroid row col (coordinates 32 g + [0, 32)) and runs it against
+        // every 16-row block of the batch
+        const int nrb = (nr + 15) / 16;
+        for (int cb = wave; cb * 16 < n; cb += 4) {
+            const int64_t kb = lo + cb * 16;
+            const float4* cr = reinterpret_cast<const float4*>(C + min(kb + col, lo + n - 1) * kDim + 32 * g);
+            float4 c4[8];
 #pragma unroll
-        for (int r = 0; r < kFbRows; ++r) best[r] = ~0ull;
-        for (int r0 = 0; r0 < nq;) {  // groups of consecutive rows with one token
-            const int jt = tj[r0];
-            int r1 = r0 + 1;
-            while (r1 < nq && tj[r1] == jt) ++r1;
-            const int64_t k1 = cent_off[jt + 1];
-            const int64_t lo = cent_off[jt] + chunk * kFbChunk;
-            const int64_t hi = min(k1, lo + kFbChunk);
-            for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-                float acc[kFbRows];
+            for (int q = 0; q < 8; ++q) c4[q] = cr[q];
+            f4 cinit;
 #pragma unroll
-                for (int r = 0; r < kFbRows; ++r) acc[r] = 0.f;
-                const float4* cv = reinterpret_cast<const float4*>(C + k * kDim);
-                for (int i4 = 0; i4 < kDim / 4; ++i4) {
-                    const float4 c4 = cv[i4];
+            for (int r = 0; r < 4; ++r) cinit[r] = cb * 16 + 4 * g + r < n ? cn[kb + 4 * g + r] : 0.f;
+            for (int rb = 0; rb < nrb; ++rb) {
+                const float* xr = xs + (rb * 16 + col) * kFbXStride + 32 * g;
+                f4 acc = cinit;
 #pragma unroll
-                    for (int r = 0; r < kFbRows; ++r) {
-                        if (r >= r0 && r < r1) {
-                            const float4 a = *reinterpret_cast<const float4*>(xs + r * kDim + 4 * i4);
-                            float t;
-                            t = a.x - c4.x; acc[r] = acc[r] + t * t;
-                            t = a.y - c4.y; acc[r] = acc[r] + t * t;
-                            t = a.z - c4.z; acc[r] = acc[r] + t * t;
-                            t = a.w - c4.w; acc[r] = acc[r] + t * t;
-                        }
-                    }
+                for (int q = 0; q < 8; ++q) {
+                    const float4 x4 = *reinterpret_cast<const float4*>(xr + 4 * q);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(c4[q].x, -2.0f * x4.x, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(c4[q].y, -2.0f * x4.y, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(c4[q].z, -2.0f * x4.z, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(c4[q].w, -2.0f * x4.w, acc, 0, 0, 0);
                 }
 #pragma unroll
-                for (int r = 0; r < kFbRows; ++r)
-                    if (r >= r0 && r < r1)
-                        best[r] = min_u64(best[r], ((unsigned long long)__float_as_uint(acc[r]) << 32) | (unsigned)k);
+                for (int r = 0; r < 4; ++r) {
+                    const int kl = cb * 16 + 4 * g + r;
+                    if (kl < n) sv[(rb * 16 + col) * kFbSStride + kl] = acc[r];
+                }
             }
-            r0 = r1;
-        }
-#pragma unroll
-        for (int r = 0; r < kFbRows; ++r) {
-            unsigned long long m = best[r];
-            for (int o = 32; o > 0; o >>= 1) {
-                const unsigned lo32 = __shfl_xor((unsigned)(m & 0xFFFFFFFFull), o);
-                const unsigned hi32 = __shfl_xor((unsigned)(m >> 32), o);
-                m = min_u64(m, ((unsigned long long)hi32 << 32) | lo32);
-            }
-            if (lane == 0) red[r * 4 + wave] = m;
         }
         __syncthreads();
-        if ((int)threadIdx.x < nq) {
-            unsigned long long m = red[threadIdx.x * 4];
-            for (int wv = 1; wv < 4; ++wv) m = min_u64(m, red[threadIdx.x * 4 + wv]);
-            if (m != ~0ull) atomicMin(&slot[q0 + threadIdx.x], m);
+        if (rr < nr) {  // whole kTpr-lane groups
+            const int64_t qi = qb + rr;
+            const unsigned long long s0 = fbslot[qi];
+            float bd = s0 == ~0ull ? INFINITY : __uint_as_float((unsigned)(s0 >> 32));
+            const double xx = (double)fbxx[qi];
+            const double E = 1.1 * (g130 * (2.0 * cn2 + 2.0 * sqrt(xx * (1.0 + g130)) * cm)) + 1e-30;
+            const double shift = -E + xx * (1.0 - g130);
+            const float* srow = sv + rr * kFbSStride;
+            const float* xrow = xs + rr * kFbXStride;
+            float lbd = INFINITY;
+            int lbk = INT32_MAX;
+            for (int k = sub; k < n; k += kTpr) {
+                if (((double)srow[k] + shift) * (1.0 - g130) > (double)bd) continue;
+                const float d = dist32_rows(xrow, C + (lo + k) * kDim, nullptr);
+                if (d < lbd || (d == lbd && k < lbk)) {
+                    lbd = d;
+                    lbk = k;
+                }
+            }
+            unsigned long long key = lbk < n ? ((unsigned long long)__float_as_uint(lbd) << 32) | (unsigned)(lo + lbk)
+                                             : ~0ull;
+            for (int m = kTpr / 2; m > 0; m >>= 1) {
+                const unsigned lo32 = __shfl_xor((unsigned)(key & 0xFFFFFFFFull), m, kTpr);
+                const unsigned hi32 = __shfl_xor((unsigned)(key >> 32), m, kTpr);
+                key = min_u64(key, ((unsigned long long)hi32 << 32) | lo32);
+            }
+            if (sub == 0 && key < s0) atomicMin(&fbslot[qi], key);
         }
     }
 }
 
-__global__ void fb_final(const int32_t* __restrict__ rowmap, const int32_t* __restrict__ fb,
-                         const unsigned long long* __restrict__ counters, const unsigned long long* __restrict__ slot,
+// the queued rows take their slots' exact minima
+__global__ void fb_final(const int64_t* __restrict__ seg_off, int32_t T, const int32_t* __restrict__ fbcnt,
+                         const int32_t* __restrict__ fbq, const unsigned long long* __restrict__ fbslot,
                          int32_t* __restrict__ assign, float* __restrict__ dist) {
-    const int64_t nfb = (int64_t)counters[kCntFallback];
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nfb; q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t v = fb[2 * q];
-        const int64_t r = rowmap ? (int64_t)rowmap[v] : v;
-        const unsigned long long key = slot[q];
-        assign[r] = (int32_t)(unsigned)(key & 0xFFFFFFFFull);
-        dist[r] = __uint_as_float((unsigned)(key >> 32));
+    for (int64_t j = blockIdx.x; j < T; j += gridDim.x) {
+        const int c = fbcnt[j];
+        for (int e = threadIdx.x; e < c; e += blockDim.x) {
+            const int64_t qi = seg_off[j] + e;
+            const unsigned long long key = fbslot[qi];
+            const int32_t r = fbq[qi];
+            assign[r] = (int32_t)(unsigned)(key & 0xFFFFFFFFull);
+            dist[r] = __uint_as_float((unsigned)(key >> 32));
+        }
     }
 }
 
@@ -1085,7 +1281,8 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     if (K < 0 || K > INT32_MAX) return set_error(TAC_E_INVAL, "tac_assign: K out of range");
     if ((seg_off_d == nullptr) == (tok_d == nullptr))
         return set_error(TAC_E_INVAL, "tac_assign: pass exactly one of seg_off_d and tok_d");
-    if (precision != TAC_FP32 && precision != TAC_BF16) return set_error(TAC_E_INVAL, "tac_assign: bad precision");
+    if (precision != TAC_FP32 && precision != TAC_BF16 && precision != TAC_F16)
+        return set_error(TAC_E_INVAL, "tac_assign: bad precision");
     if (!cent_off_d || (N > 0 && (!x_d || !assign_d)) || (K > 0 && !C_d))
         return set_error(TAC_E_INVAL, "tac_assign: NULL pointer");
     TAC_HIP(hipSetDevice(ctx->device));
@@ -1100,9 +1297,12 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     const size_t o_work = cv.take<unsigned long long>(1);
     const size_t o_cstat = cv.take<unsigned>(4);
     const size_t o_cn = cv.take<float>(K + 1);
-    const size_t o_chl = precision == TAC_BF16 ? cv.take<unsigned short>((K + 1) * 2 * kDim) : 0;
-    const size_t o_fb = cv.take<int32_t>(2 * (N + 1));
+    const bool mx16 = precision != TAC_FP32;
+    const size_t o_chl = mx16 ? cv.take<unsigned short>((K + 1) * (precision == TAC_BF16 ? 2 : 1) * kDim) : 0;
+    const size_t o_fbq = cv.take<int32_t>(N + 1);
+    const size_t o_fbxx = cv.take<float>(N + 1);
     const size_t o_slot = cv.take<unsigned long long>(N + 1);
+    const size_t o_fbcnt = cv.take<int32_t>((int64_t)T + 1);
     const size_t o_dist = dist_d ? 0 : cv.take<float>(N + 1);
     const int64_t nred = (N + kRedThreads * kRedItems - 1) / (kRedThreads * kRedItems);
     const size_t o_red = cv.take<double>(nred + 1);
@@ -1120,7 +1320,7 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     float* dist = dist_d ? dist_d : ws_at<float>(ctx, o_dist);
     unsigned* cstat = ws_at<unsigned>(ctx, o_cstat);
     float* cn = ws_at<float>(ctx, o_cn);
-    unsigned short* chl = precision == TAC_BF16 ? ws_at<unsigned short>(ctx, o_chl) : nullptr;
+    unsigned short* chl = mx16 ? ws_at<unsigned short>(ctx, o_chl) : nullptr;
     int64_t* cnt = ws_at<int64_t>(ctx, o_cnt);
     unsigned long long* work = ws_at<unsigned long long>(ctx, o_work);
 
@@ -1148,12 +1348,12 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
         seg = sseg;
         rowmap = in1 ? v1 : v0;
     }
-    const int threads = precision == TAC_BF16 ? kBThreads : kThreads;
+    const int threads = mx16 ? kBThreads : kThreads;
     // dynamic LDS: the kernel's tiles plus 16 bytes for the work-item slot
-    const size_t lds_bytes = (precision == TAC_BF16 ? kBLdsBytes : kLdsBytes) + 16;
+    const size_t lds_bytes = (mx16 ? kBLdsBytes : kLdsBytes) + 16;
     plan_count<<<grid_for(T, 256), 256, 0, s>>>(seg, cent_off_d, T, ctx->tuning.direct_max_kappa,
                                                   ctx->tuning.heavy_kappa,
-                                                  precision == TAC_BF16 ? kBTileRows : kTileRows, threads, cnt,
+                                                  mx16 ? kBTileRows : kTileRows, threads, cnt,
                                                   cstat + 1);
     TAC_LAUNCH_CHECK("plan_count");
     st = exclusive_scan_i64(s, cnt, cnt, ncls, ws_at<void>(ctx, o_scan));
@@ -1164,7 +1364,7 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     if (K > 0) {
         // a grid-stride launch of a few blocks per CU keeps the per-block atomicMax on the norm bound cheap
         const unsigned pgrid = std::min<unsigned>(grid_for(K * 32, 256), (unsigned)ctx->props_cu * 4);
-        prep_centroids<<<pgrid, 256, 0, s>>>(C_d, K, cn, cstat, chl);
+        prep_centroids<<<pgrid, 256, 0, s>>>(C_d, K, cn, cstat, chl, precision);
         TAC_LAUNCH_CHECK("prep_centroids");
     }
     Params P;
@@ -1174,7 +1374,7 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     P.cent_off = cent_off_d;
     P.T = T;
     P.C = C_d;
-    P.cstage = precision == TAC_BF16 ? (const void*)chl : (const void*)C_d;
+    P.cstage = mx16 ? (const void*)chl : (const void*)C_d;
     P.cn = cn;
     P.cstat = cstat;
     P.item_off = cnt;
@@ -1182,39 +1382,56 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     P.work = work;
     P.assign = assign_d;
     P.dist = dist;
-    P.fb = ws_at<int32_t>(ctx, o_fb);
+    P.fbq = ws_at<int32_t>(ctx, o_fbq);
+    P.fbxx = ws_at<float>(ctx, o_fbxx);
+    P.fbslot = ws_at<unsigned long long>(ctx, o_slot);
+    P.fbcnt = ws_at<int32_t>(ctx, o_fbcnt);
+    fb_zero<<<grid_for(T, 256), 256, 0, s>>>(P.fbcnt, T);
+    TAC_LAUNCH_CHECK("fb_zero");
     P.counters = ctx->counters;
     // persistent grid: as many work-group slots as the device holds at once
-    static int occ[2] = {0, 0};
+    static int occ[3] = {0, 0, 0};
     if (!occ[0]) {
         TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_FP32>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)(kLdsBytes + 16)));
         TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_BF16>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)(kBLdsBytes + 16)));
-        TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], assign_main<TAC_FP32>, kThreads, kLdsBytes + 16));
+        TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_F16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(kBLdsBytes + 16)));
         TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], assign_main<TAC_BF16>, kBThreads,
                                                              kBLdsBytes + 16));
-        for (int i = 0; i < 2; ++i) occ[i] = occ[i] < 1 ? 1 : occ[i];
+        TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], assign_main<TAC_F16>, kBThreads,
+                                                             kBLdsBytes + 16));
+        TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], assign_main<TAC_FP32>, kThreads, kLdsBytes + 16));
+        for (int i = 0; i < 3; ++i) occ[i] = occ[i] < 1 ? 1 : occ[i];
     }
-    int per_cu = occ[precision == TAC_BF16 ? 1 : 0];
+    int per_cu = occ[precision];
     if (ctx->tuning.groups_per_cu > 0 && ctx->tuning.groups_per_cu < per_cu) per_cu = ctx->tuning.groups_per_cu;
     const unsigned grid = (unsigned)ctx->props_cu * (unsigned)per_cu;
     time_start(ctx, TAC_SLOT_ASSIGN);
     if (precision == TAC_FP32) {
         assign_main<TAC_FP32><<<grid, threads, lds_bytes, s>>>(P);
         TAC_LAUNCH_CHECK("assign_main<fp32>");
-    } else {
+    } else if (precision == TAC_BF16) {
         assign_main<TAC_BF16><<<grid, threads, lds_bytes, s>>>(P);
         TAC_LAUNCH_CHECK("assign_main<bf16>");
+    } else {
+        assign_main<TAC_F16><<<grid, threads, lds_bytes, s>>>(P);
+        TAC_LAUNCH_CHECK("assign_main<f16>");
     }
     time_stop(ctx, TAC_SLOT_ASSIGN);
-    unsigned long long* slot = ws_at<unsigned long long>(ctx, o_slot);
-    fb_init<<<(unsigned)ctx->props_cu, 256, 0, s>>>(ctx->counters, slot);
-    TAC_LAUNCH_CHECK("fb_init");
-    fb_batch<<<(unsigned)ctx->props_cu * 4, 256, 0, s>>>(x_d, rowmap, cent_off_d, C_d, P.fb, ctx->counters, cstat + 1,
-                                                       slot);
-    TAC_LAUNCH_CHECK("fb_batch");
-    fb_final<<<(unsigned)ctx->props_cu, 256, 0, s>>>(rowmap, P.fb, ctx->counters, slot, assign_d, dist);
+    // rows whose certificate failed: per-token work plan (the item plan's
+    // buffers are free again), matrix-core rescoring, write-back
+    int64_t* woff = cnt;
+    fb_plan<<<grid_for(T, 256), 256, 0, s>>>(P.fbcnt, cent_off_d, T, woff);
+    TAC_LAUNCH_CHECK("fb_plan");
+    st = exclusive_scan_i64(s, woff, woff, T, ws_at<void>(ctx, o_scan));
+    if (st != TAC_OK) return st;
+    fb_screen<<<(unsigned)ctx->props_cu * 2, 256, 0, s>>>(x_d, seg, cent_off_d, T, C_d, cn, cstat, woff, P.fbcnt, P.fbq,
+                                                        P.fbxx, P.fbslot);
+    TAC_LAUNCH_CHECK("fb_screen");
+    fb_final<<<std::min<unsigned>((unsigned)T, (unsigned)ctx->props_cu * 8), 256, 0, s>>>(seg, T, P.fbcnt, P.fbq,
+                                                                                        P.fbslot, assign_d, dist);
     TAC_LAUNCH_CHECK("fb_final");
     if (inertia_d) {
         double* part = ws_at<double>(ctx, o_red);

@@ -52,7 +52,7 @@ def test_empty_inputs(ctx):
 
 
 @pytest.mark.parametrize("kappa", [1, 2, 4, 5, 16, 17, 63, 64, 65, 300])
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_class_boundaries_and_ragged_tiles(ctx, kappa, prec):
     rng = np.random.default_rng(kappa)
     sizes = [kappa, 3 * kappa + 7, 513, 1030]        # ragged against 16-row blocks and 512-row tiles
@@ -73,7 +73,7 @@ def test_heavy_token_epoch_flush(ctx):
     C = xs[rng.choice(6000, 2500, replace=False)].copy()
     seg_off = np.array([0, 6000], np.int64)
     cent_off = np.array([0, 2500], np.int64)
-    for prec in (0, 1):
+    for prec in (0, 1, 2):
         a, d, J = run_assign(ctx, xs, seg_off, C, cent_off, prec)
         check_assign(xs, seg_off, C, cent_off, a, d)
 
@@ -89,10 +89,31 @@ def test_forced_certificate_fallback(ctx):
     xs = (1e-7 * rng.standard_normal((300, 128))).astype(np.float32)
     seg_off = np.array([0, 300], np.int64)
     cent_off = np.array([0, k], np.int64)
-    for prec in (0, 1):
+    for prec in (0, 1, 2):
         a, d, J = run_assign(ctx, xs, seg_off, C, cent_off, prec)
         assert tac.tac_assign_stats(ctx)["fallback"] > 0
         check_assign(xs, seg_off, C, cent_off, a, d, fp64=False)
+
+
+def test_f16_operand_range(ctx):
+    """The FP16 screen rounds x and c to FP16; rows and centroids beyond its
+    range (or deep in its subnormals) leave no finite bound, so those rows are
+    rescored exhaustively, and every row still gets the exact FP32 argmin."""
+    rng = np.random.default_rng(16)
+    sizes = [300, 260, 250]
+    xs = np.concatenate([clustered(rng, n, 5) for n in sizes])
+    xs[:20] *= 1.0e5                        # token 0: some rows past the FP16 range (|2x| > 65504)
+    xs[300:560] *= 1.0e-6                   # token 1: tiny rows, FP16 subnormals
+    seg_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    kap = [40, 40, 40]
+    cent_off = np.concatenate([[0], np.cumsum(kap)]).astype(np.int64)
+    C = np.concatenate([xs[seg_off[j] + rng.choice(sizes[j], kap[j], replace=False)] for j in range(3)])
+    C[-1] *= 1.0e5                          # one centroid past the range: the bound is infinite everywhere
+    a, d, J = run_assign(ctx, xs, seg_off, C, cent_off, tac.TAC_F16)
+    assert tac.tac_assign_stats(ctx)["fallback"] > 0
+    check_assign(xs, seg_off, C, cent_off, a, d, fp64=False)
+    a0, d0, J0 = run_assign(ctx, xs, seg_off, C, cent_off, tac.TAC_FP32)
+    assert np.array_equal(a, a0) and np.array_equal(d, d0)
 
 
 def test_dyadic_exact_ties_bitwise(ctx):
@@ -114,7 +135,7 @@ def test_dyadic_exact_ties_bitwise(ctx):
     seg_off = np.concatenate([[0], np.cumsum([len(v) for v, _ in toks])]).astype(np.int64)
     cent_off = np.concatenate([[0], np.cumsum([len(c) for _, c in toks])]).astype(np.int64)
     ref = oracle.assign(xs, seg_off, C, cent_off, decide="fp64")
-    for prec in (0, 1):
+    for prec in (0, 1, 2):
         a, d, J = run_assign(ctx, xs, seg_off, C, cent_off, prec)
         assert np.array_equal(a, ref["a"])
         assert np.array_equal(d.astype(np.float64), ref["D"])
@@ -137,7 +158,7 @@ def test_serving_path_groups_unsorted_rows(ctx):
     t[:7] = c.T + 3                                    # invalid ids
     a = torch.empty(x.shape[0], dtype=torch.int32, device="cuda")
     d = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
-    for prec in (0, 1):
+    for prec in (0, 1, 2):
         tac.tac_assign(ctx, dev(x), dev(c.C0), dev(c.cent_off), a, tok=dev(t), precision=prec, dist=d)
         ga = host(a)
         assert np.all(ga[:7] == -1)
@@ -189,7 +210,7 @@ def test_tuning_keeps_results(ctx, tuning):
     before = ctx.get_tuning()
     try:
         assert ctx.set_tuning(**tuning) == tuning
-        for prec in (0, 1):
+        for prec in (0, 1, 2):
             a, d, J = run_assign(ctx, xs, seg_off, C, cent_off, prec)
             check_assign(xs, seg_off, C, cent_off, a, d)
     finally:

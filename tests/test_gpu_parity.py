@@ -93,7 +93,7 @@ def test_lloyd_per_step(ctx, name, steps):
     d = c.device()
     traj = oracle.lloyd(c.xs, c.seg_off, c.cent_off, c.C0, iters=steps, decide="fp32")
     for t, st in enumerate(traj):
-        for prec in (tac.TAC_FP32, tac.TAC_BF16):
+        for prec in (tac.TAC_FP32, tac.TAC_BF16, tac.TAC_F16):
             a, dist, J = _gpu_assign(ctx, d, st["C"], prec)
             ties, r64 = check_assign(c.xs, c.seg_off, st["C"], c.cent_off, a, dist)
             assert abs(J - r64["J"]) <= REL_TOL * r64["J"]
@@ -116,8 +116,10 @@ def test_determinism_and_precision_identity(ctx):
     a1, d1, J1 = _gpu_assign(ctx, d, c.C0, tac.TAC_FP32)
     a2, d2, J2 = _gpu_assign(ctx, d, c.C0, tac.TAC_FP32)
     a3, d3, J3 = _gpu_assign(ctx, d, c.C0, tac.TAC_BF16)
+    a4, d4, J4 = _gpu_assign(ctx, d, c.C0, tac.TAC_F16)
     assert np.array_equal(a1, a2) and np.array_equal(d1, d2) and J1 == J2
     assert np.array_equal(a1, a3) and np.array_equal(d1, d3) and J1 == J3
+    assert np.array_equal(a1, a4) and np.array_equal(d1, d4) and J1 == J4
     C1 = torch.empty((c.K, 128), dtype=torch.float32, device="cuda")
     C2 = torch.empty_like(C1)
     ad = dev(a1)

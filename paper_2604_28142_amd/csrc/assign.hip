@@ -70,6 +70,26 @@ __device__ __forceinline__ float dist32_rows(const float* __restrict__ x, const 
     return acc;
 }
 
+// The same canonical distance with the x row already in registers (a row
+// rescored against several candidates is loaded once, all of it in flight at
+// once); the loop is fully unrolled so that the row stays in registers.
+__device__ __forceinline__ float dist32_xreg(const float4 (&xv)[kDim / 4], const float* __restrict__ c, float* xx) {
+    const float4* cv = reinterpret_cast<const float4*>(c);
+    float acc = 0.f, sx = 0.f;
+#pragma unroll
+    for (int i = 0; i < kDim / 4; ++i) {
+        const float4 a = xv[i];
+        const float4 b = cv[i];
+        float t;
+        t = __fsub_rn(a.x, b.x); acc = __fadd_rn(acc, __fmul_rn(t, t)); sx = __fadd_rn(sx, __fmul_rn(a.x, a.x));
+        t = __fsub_rn(a.y, b.y); acc = __fadd_rn(acc, __fmul_rn(t, t)); sx = __fadd_rn(sx, __fmul_rn(a.y, a.y));
+        t = __fsub_rn(a.z, b.z); acc = __fadd_rn(acc, __fmul_rn(t, t)); sx = __fadd_rn(sx, __fmul_rn(a.z, a.z));
+        t = __fsub_rn(a.w, b.w); acc = __fadd_rn(acc, __fmul_rn(t, t)); sx = __fadd_rn(sx, __fmul_rn(a.w, a.w));
+    }
+    if (xx) *xx = sx;
+    return acc;
+}
+
 __device__ __forceinline__ unsigned short bf16_rne(float v) {
     const unsigned u = __float_as_uint(v);
     return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
@@ -533,12 +553,25 @@ __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t 
         }
         const int64_t r = P.rowmap ? (int64_t)P.rowmap[v] : v;
         const float* xr = P.x + r * kDim;
+        // 16-bit screens: the row in registers, loaded once for all of its candidates
+        // (the FP32 screen's two waves per SIMD leave no room for it)
+        float4 xv[PREC == TAC_FP32 ? 1 : kDim / 4];
+        if constexpr (PREC != TAC_FP32) {
+#pragma unroll
+            for (int i = 0; i < kDim / 4; ++i) xv[i] = reinterpret_cast<const float4*>(xr)[i];
+        }
+        auto dist = [&](int64_t k, float* xx) {
+            if constexpr (PREC == TAC_FP32)
+                return dist32_rows(xr, P.C + k * kDim, xx);
+            else
+                return dist32_xreg(xv, P.C + k * kDim, xx);
+        };
         bool ok = false;
         float bd = INFINITY, xxq = INFINITY;
         int bi = INT32_MAX;
         if (i0 >= 0) {
             float xxc;
-            bd = dist32_rows(xr, P.C + (int64_t)i0 * kDim, &xxc);
+            bd = dist((int64_t)i0, &xxc);
             xxq = xxc;
             bi = i0;
             // canonical ||x - c||^2 >= (screen - E - beta + ||x||^2) (1 - g130) for every candidate
@@ -567,7 +600,7 @@ __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t 
                     const int I = (int)sl[(4 + e) * 64];
                     const double G = (double)__uint_as_float(sl[e * 64]);
                     if (I < 0 || I == i0 || (G + shift) * (1.0 - g130) > (double)bd) continue;
-                    const float d = dist32_rows(xr, P.C + (int64_t)I * kDim, nullptr);
+                    const float d = dist((int64_t)I, nullptr);
                     if (d < bd || (d == bd && I < bi)) {
                         bd = d;
                         bi = I;

@@ -176,6 +176,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-f16", action="store_true", help="skip the FP16-screen comparison leg")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-screen comparison leg")
     ap.add_argument("--headline", default="bf16", choices=["bf16", "f16"],
                     help="16-bit screen timed in the steps (the other runs as a comparison leg)")
     ap.add_argument("--serve-requests", type=int, default=20_000)

@@ -750,10 +750,13 @@ __device__ __forceinline__ void screen_item_fp32(const Params& P, int32_t j, int
 constexpr int kBThreads = 256;
 constexpr int kBWaves = kBThreads / 64;
 constexpr int kBNB = 5;
-// Per-lane list length of the 16-bit screens: a top-3 costs one med3 less per
-// screen value than a top-4; the certificate then fails on a few more rows
-// (their exhaustive rescoring is batched), which is the cheaper side of the trade.
-constexpr int kBLK = 3;
+// Per-lane list length of the 16-bit screens.  For BF16 a top-3 costs one med3
+// less per screen value than a top-4 and its certificate rarely fails either
+// way; the FP16 screen's wider error bound makes a top-3 fail about five times
+// as often as a top-4, and the rescoring of those rows costs more than the
+// extra med3.
+template <int PREC>
+constexpr int kBLK = PREC == TAC_F16 ? 4 : 3;
 constexpr int kBTileRows = kBWaves * kBNB * 16;
 constexpr int kBBufs = 3;                                 // stage buffers
 constexpr int kBStageWords = 8192;                        // 32 KiB per stage buffer
@@ -926,7 +929,7 @@ __device__ __forceinline__ void screen_item_mx(const Params& P, int32_t j, int64
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                list_insert<kBLK>(el[nb], __uint_as_float(__builtin_amdgcn_perm(__float_as_uint(acc[nb][r]), lb + r,
+                list_insert<kBLK<PREC>>(el[nb], __uint_as_float(__builtin_amdgcn_perm(__float_as_uint(acc[nb][r]), lb + r,
                                                                           0x07060500u)));
     };
     // Steady-state block: the MFMAs of block B interleaved by hand with the
@@ -955,7 +958,7 @@ __device__ __forceinline__ void screen_item_mx(const Params& P, int32_t j, int64
                         const int v = i / NPR;
                         if (v < 4 * NB) {
                             const float knext = v + 1 < 4 * NB ? key(v + 1) : 0.f;
-                            list_insert<kBLK>(el[v % NB], kcur);
+                            list_insert<kBLK<PREC>>(el[v % NB], kcur);
                             kcur = knext;
                         }
                         __builtin_amdgcn_sched_barrier(0);
@@ -964,7 +967,7 @@ __device__ __forceinline__ void screen_item_mx(const Params& P, int32_t j, int64
     };
     auto flush_if = [&](int blk) {
         if (blk - epoch_first == kEpochBlocks - 1 || blk + 1 == nblk) {
-            epoch_flush<NB, kBLK, float>(el, glist, k0 + (int64_t)epoch_first * 16 + 4 * g, k0 + kc);
+            epoch_flush<NB, kBLK<PREC>, float>(el, glist, k0 + (int64_t)epoch_first * 16 + 4 * g, k0 + kc);
             epoch_first = blk + 1;
         }
     };
@@ -1033,7 +1036,7 @@ __device__ __forceinline__ void screen_item_mx(const Params& P, int32_t j, int64
             flush_if(blk - 1);
         }
     }
-    finish_item<PREC, NB, kBLK>(P, j, row0, s1, glist, beta, cnmax, cmax, lane, sdx);
+    finish_item<PREC, NB, kBLK<PREC>>(P, j, row0, s1, glist, beta, cnmax, cmax, lane, sdx);
 }
 
 template <int PREC>
@@ -1396,7 +1399,7 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     TAC_LAUNCH_CHECK("plan_fill");
     if (K > 0) {
         // a grid-stride launch of a few blocks per CU keeps the per-block atomicMax on the norm bound cheap
-        const unsigned pgrid = std::min<unsigned>(grid_for(K * 32, 256), (unsigned)ctx->props_cu * 4);
+        const unsigned pgrid = std::min<unsigned>(grid_for(K * 32, 256), (unsigned)ctx->props_cu * 16);
         prep_centroids<<<pgrid, 256, 0, s>>>(C_d, K, cn, cstat, chl, precision);
         TAC_LAUNCH_CHECK("prep_centroids");
     }

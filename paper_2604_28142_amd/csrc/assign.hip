@@ -121,12 +121,41 @@ __global__ void plan_count(const int64_t* __restrict__ seg_off, const int64_t* _
     for (int c = 0; c < 3; ++c) cnt[(int64_t)c * T + j] = c == cls ? tiles : 0;
 }
 
-// item -> (class, token) table from the scanned item offsets
-__global__ void plan_fill(const int64_t* __restrict__ item_off, int64_t ncls, int32_t* __restrict__ table) {
+// Everything a work item needs, in one 32-byte record, so that an item's first
+// memory access is its x rows (the persistent loop fetches the next item's
+// record while the current item runs).
+struct ItemDesc {
+    int64_t row0;  // first sorted row of the item
+    int64_t s1;    // end of the token's rows
+    int64_t k0;    // first centroid of the token
+    int32_t kc;    // centroids of the token
+    int32_t jc;    // class << 24 | token
+};
+static_assert(sizeof(ItemDesc) == 32, "one 32-byte record per item");
+
+// item descriptors from the scanned item offsets: items of (class, token) pair
+// idx = class * T + token cut the token's rows into tiles of the class's size
+__global__ void plan_fill(const int64_t* __restrict__ item_off, const int64_t* __restrict__ seg_off,
+                          const int64_t* __restrict__ cent_off, int32_t T, int screen_rows, int direct_rows,
+                          ItemDesc* __restrict__ desc) {
+    const int64_t ncls = 3 * (int64_t)T;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < ncls;
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = item_off[idx], e = item_off[idx + 1];
-        for (int64_t t = b; t < e; ++t) table[t] = (int32_t)idx;
+        if (b == e) continue;
+        const int cls = (int)(idx / T);
+        const int32_t j = (int32_t)(idx - (int64_t)cls * T);
+        const int64_t rows = cls == 2 ? direct_rows : screen_rows;
+        ItemDesc d;
+        d.s1 = seg_off[j + 1];
+        d.k0 = cent_off[j];
+        d.kc = (int32_t)(cent_off[j + 1] - d.k0);
+        d.jc = (cls << 24) | j;
+        const int64_t s0 = seg_off[j];
+        for (int64_t t = b; t < e; ++t) {
+            d.row0 = s0 + (t - b) * rows;
+            desc[t] = d;
+        }
     }
 }
 
@@ -211,7 +240,7 @@ struct Params {
     const float* cn;
     const unsigned* cstat;       // [0] = bits of max ||c||^2, [1] = max kappa, [2] = bits of max ||c - f16(c)||^2
     const int64_t* item_off;     // [3T + 1]
-    const int32_t* item_table;   // item -> class * T + token
+    const ItemDesc* desc;        // per item
     unsigned long long* work;
     int32_t* assign;
     float* dist;
@@ -329,11 +358,11 @@ __device__ __forceinline__ void split_bf8(const float* v, bf8& hi, bf8& lo) {
 
 // Direct route: one row per thread, every centroid of the token a candidate.
 template <int ROWS>
-__device__ __forceinline__ void direct_item(const Params& P, int32_t j, int64_t tile) {
-    const int64_t s0 = P.seg_off[j], s1 = P.seg_off[j + 1];
-    const int64_t k0 = P.cent_off[j];
-    const int kc = (int)(P.cent_off[j + 1] - k0);
-    const int64_t row0 = s0 + tile * ROWS;
+__device__ __forceinline__ void direct_item(const Params& P, const ItemDesc& D) {
+    const int64_t s1 = D.s1;
+    const int64_t k0 = D.k0;
+    const int kc = D.kc;
+    const int64_t row0 = D.row0;
     const int64_t v = row0 + threadIdx.x;
     const bool valid = v < s1;
     if (valid) {
@@ -629,16 +658,17 @@ __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t 
 
 // ---- FP32 screen: 8 waves x 4 column blocks of 16 rows = 512 rows per item ----
 // Centroid stages of 64 rows are staged through registers into padded LDS rows.
-__device__ __forceinline__ void screen_item_fp32(const Params& P, int32_t j, int64_t tile, unsigned* lds) {
+__device__ __forceinline__ void screen_item_fp32(const Params& P, const ItemDesc& D, unsigned* lds) {
     constexpr int NB = kNB;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4;
     const int col = lane & 15;
-    const int64_t s0 = P.seg_off[j], s1 = P.seg_off[j + 1];
-    const int64_t k0 = P.cent_off[j];
-    const int kc = (int)(P.cent_off[j + 1] - k0);
-    const int64_t row0 = s0 + tile * kTileRows + wave * (NB * 16);
+    const int32_t j = D.jc & 0xFFFFFF;
+    const int64_t s1 = D.s1;
+    const int64_t k0 = D.k0;
+    const int kc = D.kc;
+    const int64_t row0 = D.row0 + wave * (NB * 16);
     const float cnmax = __uint_as_float(P.cstat[0]) * (1.0f + 1e-5f);
     const float cmax = sqrtf(cnmax) * (1.0f + 1e-6f);
 
@@ -765,7 +795,9 @@ constexpr size_t kBCnOffsetWords = (size_t)kBBufs * kBStageWords;
 constexpr size_t kBGlistOffsetWords = kBCnOffsetWords + (size_t)kBBufs * kBCnStride;
 constexpr size_t kBDxOffsetWords = kBGlistOffsetWords + (size_t)kBWaves * kBNB * 8 * 64;
 constexpr size_t kBLdsBytes = (kBDxOffsetWords + (size_t)kBWaves * kBNB * 16) * 4;
-static_assert(kBLdsBytes + 16 <= 160 * 1024, "fits the LDS of a CU");
+// after the tiles: the persistent loop's work-item slots (two descriptors, two indices)
+constexpr size_t kSlotBytes = 80;
+static_assert(kBLdsBytes + kSlotBytes <= 160 * 1024, "fits the LDS of a CU");
 
 // Stage geometry of a 16-bit screen: bytes per centroid row and centroids per stage.
 template <int PREC>
@@ -841,7 +873,7 @@ struct BBlock<TAC_F16> {
 };
 
 template <int PREC>
-__device__ __forceinline__ void screen_item_mx(const Params& P, int32_t j, int64_t tile, unsigned* lds) {
+__device__ __forceinline__ void screen_item_mx(const Params& P, const ItemDesc& D, unsigned* lds) {
     constexpr int NB = kBNB;
     constexpr int SC = StageGeom<PREC>::kCents;
     constexpr int BPS = StageGeom<PREC>::kBlocks;
@@ -850,10 +882,11 @@ __device__ __forceinline__ void screen_item_mx(const Params& P, int32_t j, int64
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4;
     const int col = lane & 15;
-    const int64_t s0 = P.seg_off[j], s1 = P.seg_off[j + 1];
-    const int64_t k0 = P.cent_off[j];
-    const int kc = (int)(P.cent_off[j + 1] - k0);
-    const int64_t row0 = s0 + tile * kBTileRows + wave * (NB * 16);
+    const int32_t j = D.jc & 0xFFFFFF;
+    const int64_t s1 = D.s1;
+    const int64_t k0 = D.k0;
+    const int kc = D.kc;
+    const int64_t row0 = D.row0 + wave * (NB * 16);
     const float cnmax = __uint_as_float(P.cstat[0]) * (1.0f + 1e-5f);
     const float cmax = sqrtf(cnmax) * (1.0f + 1e-6f);
 
@@ -1044,35 +1077,52 @@ __global__ void __launch_bounds__(PREC == TAC_FP32 ? kThreads : kBThreads) assig
     // All shared memory is dynamic so that it starts 16-byte aligned (a static
     // variable in front of it would shift every 16-byte LDS access off alignment).
     extern __shared__ __attribute__((aligned(16))) unsigned lds[];
-    unsigned long long* s_item = reinterpret_cast<unsigned long long*>(
-        lds + (PREC == TAC_FP32 ? kLdsBytes : kBLdsBytes) / 4);
+    // the work-item slots after the kernel's tiles: descriptors of the current
+    // and next item (by parity), then the indices of the next two items
+    ItemDesc* s_desc = reinterpret_cast<ItemDesc*>(lds + (PREC == TAC_FP32 ? kLdsBytes : kBLdsBytes) / 4);
+    long long* s_idx = reinterpret_cast<long long*>(s_desc + 2);
     const int64_t total = P.item_off[3 * (int64_t)P.T];
-    if (threadIdx.x == 0) *s_item = atomicAdd(P.work, 1ull);
+    if (threadIdx.x == 0) {
+        const long long a = (long long)atomicAdd(P.work, 1ull);
+        const long long b = (long long)atomicAdd(P.work, 1ull);
+        s_idx[0] = a;
+        s_idx[1] = b;
+        if (a < total) s_desc[0] = P.desc[a];
+    }
     __syncthreads();
-    int64_t item = (int64_t)*s_item;
-    __syncthreads();
-    while (item < total) {
-        // the next item is fetched now; the atomic's latency overlaps this item
-        unsigned long long next = 0;
-        if (threadIdx.x == 0) next = atomicAdd(P.work, 1ull);
-        const int32_t idx = P.item_table[item];
-        const int cls = idx / P.T;
-        const int32_t j = idx - cls * P.T;
-        const int64_t tile = item - P.item_off[idx];
+    for (int par = 0;; par ^= 1) {
+        const int64_t item = s_idx[0];
+        if (item >= total) break;
+        const int64_t nxt = s_idx[1];
+        const ItemDesc D = s_desc[par];
+        // one item of look-ahead: the item after next is claimed and the next
+        // item's descriptor copied into its slot (LDS DMA, no registers held)
+        // now, so both latencies overlap this item
+        long long nn = 0;
+        if (threadIdx.x < 2) {
+            if (threadIdx.x == 0) nn = (long long)atomicAdd(P.work, 1ull);
+            if (nxt < total)
+                __builtin_amdgcn_global_load_lds(reinterpret_cast<const char*>(P.desc + nxt) + 16 * threadIdx.x,
+                                                 (lds_void_ptr)(s_desc + (par ^ 1)), 16, 0, 0);
+        }
+        const int cls = D.jc >> 24;
         if constexpr (PREC != TAC_FP32) {
             if (cls == 2)
-                direct_item<kBThreads>(P, j, tile);
+                direct_item<kBThreads>(P, D);
             else
-                screen_item_mx<PREC>(P, j, tile, lds);
+                screen_item_mx<PREC>(P, D, lds);
         } else {
             if (cls == 2)
-                direct_item<kThreads>(P, j, tile);
+                direct_item<kThreads>(P, D);
             else
-                screen_item_fp32(P, j, tile, lds);
+                screen_item_fp32(P, D, lds);
         }
-        if (threadIdx.x == 0) *s_item = next;
-        __syncthreads();
-        item = (int64_t)*s_item;
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the descriptor copy has landed
+        __syncthreads();  // every thread has read this item's slots
+        if (threadIdx.x == 0) {
+            s_idx[0] = nxt;
+            s_idx[1] = nn;
+        }
         __syncthreads();
     }
 }
@@ -1329,7 +1379,7 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     Carve cv;
     const size_t o_cnt = cv.take<int64_t>(ncls + 1);
     const size_t o_scan = cv.take<char>(scan_scratch_bytes(ncls));
-    const size_t o_table = cv.take<int32_t>(N / 256 + (int64_t)T + 1);   // items: at most one partial per token
+    const size_t o_table = cv.take<ItemDesc>(N / 256 + (int64_t)T + 1);  // items: at most one partial per token
     const size_t o_work = cv.take<unsigned long long>(1);
     const size_t o_cstat = cv.take<unsigned>(4);
     const size_t o_cn = cv.take<float>(K + 1);
@@ -1385,8 +1435,8 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
         rowmap = in1 ? v1 : v0;
     }
     const int threads = mx16 ? kBThreads : kThreads;
-    // dynamic LDS: the kernel's tiles plus 16 bytes for the work-item slot
-    const size_t lds_bytes = (mx16 ? kBLdsBytes : kLdsBytes) + 16;
+    // dynamic LDS: the kernel's tiles plus the work-item slots
+    const size_t lds_bytes = (mx16 ? kBLdsBytes : kLdsBytes) + kSlotBytes;
     plan_count<<<grid_for(T, 256), 256, 0, s>>>(seg, cent_off_d, T, ctx->tuning.direct_max_kappa,
                                                   ctx->tuning.heavy_kappa,
                                                   mx16 ? kBTileRows : kTileRows, threads, cnt,
@@ -1394,8 +1444,9 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     TAC_LAUNCH_CHECK("plan_count");
     st = exclusive_scan_i64(s, cnt, cnt, ncls, ws_at<void>(ctx, o_scan));
     if (st != TAC_OK) return st;
-    int32_t* table = ws_at<int32_t>(ctx, o_table);
-    plan_fill<<<grid_for(ncls, 256), 256, 0, s>>>(cnt, ncls, table);
+    ItemDesc* table = ws_at<ItemDesc>(ctx, o_table);
+    plan_fill<<<grid_for(ncls, 256), 256, 0, s>>>(cnt, seg, cent_off_d, T, mx16 ? kBTileRows : kTileRows, threads,
+                                                    table);
     TAC_LAUNCH_CHECK("plan_fill");
     if (K > 0) {
         // a grid-stride launch of a few blocks per CU keeps the per-block atomicMax on the norm bound cheap
@@ -1414,7 +1465,7 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     P.cn = cn;
     P.cstat = cstat;
     P.item_off = cnt;
-    P.item_table = table;
+    P.desc = table;
     P.work = work;
     P.assign = assign_d;
     P.dist = dist;
@@ -1429,16 +1480,17 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     static int occ[3] = {0, 0, 0};
     if (!occ[0]) {
         TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_FP32>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(kLdsBytes + 16)));
+                                    (int)(kLdsBytes + kSlotBytes)));
         TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_BF16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(kBLdsBytes + 16)));
+                                    (int)(kBLdsBytes + kSlotBytes)));
         TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_F16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(kBLdsBytes + 16)));
+                                    (int)(kBLdsBytes + kSlotBytes)));
         TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], assign_main<TAC_BF16>, kBThreads,
-                                                             kBLdsBytes + 16));
+                                                             kBLdsBytes + kSlotBytes));
         TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], assign_main<TAC_F16>, kBThreads,
-                                                             kBLdsBytes + 16));
-        TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], assign_main<TAC_FP32>, kThreads, kLdsBytes + 16));
+                                                             kBLdsBytes + kSlotBytes));
+        TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], assign_main<TAC_FP32>, kThreads,
+                                                             kLdsBytes + kSlotBytes));
         for (int i = 0; i < 3; ++i) occ[i] = occ[i] < 1 ? 1 : occ[i];
     }
     int per_cu = occ[precision];

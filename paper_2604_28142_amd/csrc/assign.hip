@@ -396,10 +396,12 @@ __device__ __forceinline__ void direct_item(const Params& P, const ItemDesc& D) 
 
 // Load and convert the wave's x fragments (rows row0 .. row0 + 16 NB - 1, those
 // at or past s1 as zeros); returns the largest ||x||^2 over the wave's rows.
-// FP16 also stores each row's ||-2x - f16(-2x)||^2 at sdx[16 nb + col].
+// FP16 also stores each row's ||-2x - f16(-2x)||^2 at sdx[16 nb + col].  The
+// 16-bit screens pass xt, the wave's transpose area (16 rows of kXtStride words).
+constexpr int kXtStride = kDim + 4;
 template <int PREC, int NB>
 __device__ __forceinline__ float load_x_frags(const Params& P, int64_t row0, int64_t s1, int g, int col,
-                                              Frag<PREC, NB>& F, float* sdx = nullptr) {
+                                              Frag<PREC, NB>& F, float* sdx = nullptr, float* xt = nullptr) {
     float xxmax = 0.f;
     if constexpr (PREC == TAC_FP32) {
 #pragma unroll
@@ -424,26 +426,41 @@ __device__ __forceinline__ float load_x_frags(const Params& P, int64_t row0, int
             xxmax = fmaxf(xxmax, xx);
         }
     } else {
-        // all of the wave's rows are loaded before any is converted, so that the
-        // loads of the NB column blocks are in flight together
+        // All of the wave's rows are loaded before any is converted, so that the
+        // loads of the NB column blocks are in flight together.  Each load
+        // instruction reads 1 KiB of contiguous memory (lane l: 16 bytes of row
+        // 2 i + l / 32), and each 16-row block is turned into the fragment
+        // layout through the wave's transpose area in LDS (rows padded to 528
+        // bytes); a fragment-layout load straight from memory would touch 64
+        // cache lines per instruction.
         float4 ld[NB][8];
+        const int lane = threadIdx.x & 63;
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const int64_t v = row0 + nb * 16 + col;
-            const bool valid = v < s1;
-            const int64_t r = valid ? (P.rowmap ? (int64_t)P.rowmap[v] : v) : 0;
-            const float4* xv = reinterpret_cast<const float4*>(P.x + r * kDim + 32 * g);
+        for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-            for (int q = 0; q < 8; ++q) ld[nb][q] = valid ? xv[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
+            for (int i = 0; i < 8; ++i) {
+                const int64_t v = row0 + nb * 16 + 2 * i + (lane >> 5);
+                const bool valid = v < s1;
+                const int64_t r = valid ? (P.rowmap ? (int64_t)P.rowmap[v] : v) : 0;
+                ld[nb][i] = valid ? reinterpret_cast<const float4*>(P.x + r * kDim)[lane & 31]
+                                  : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             float xx = 0.f, dyy = 0.f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                *reinterpret_cast<float4*>(xt + (2 * i + (lane >> 5)) * kXtStride + 4 * (lane & 31)) = ld[nb][i];
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            float4 fr[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) fr[q] = *reinterpret_cast<const float4*>(xt + col * kXtStride + 32 * g + 4 * q);
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the next block rewrites the area
             // eight coordinates at a time straight into the 16-bit fragments
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                const float4 a = ld[nb][2 * s];
-                const float4 b = ld[nb][2 * s + 1];
+                const float4 a = fr[2 * s];
+                const float4 b = fr[2 * s + 1];
                 xx += a.x * a.x + a.y * a.y + a.z * a.z + a.w * a.w + b.x * b.x + b.y * b.y + b.z * b.z + b.w * b.w;
                 const float v8[8] = {-2.0f * a.x, -2.0f * a.y, -2.0f * a.z, -2.0f * a.w,
                                      -2.0f * b.x, -2.0f * b.y, -2.0f * b.z, -2.0f * b.w};
@@ -902,7 +919,10 @@ __device__ __forceinline__ void screen_item_mx(const Params& P, const ItemDesc& 
     bf_stage_issue<PREC>(chl, P.cn, k0, kc, 0, stage, stage_cn, wave, lane);
 
     Frag<PREC, NB> F;
-    const float xxmax = load_x_frags<PREC, NB>(P, row0, s1, g, col, F, sdx);
+    // the x transpose areas sit in stage buffers 1 and 2, whose DMAs start after the prologue
+    float* xt = reinterpret_cast<float*>(stage + kBStageWords) + wave * (16 * kXtStride);
+    static_assert(kBWaves * 16 * kXtStride <= 2 * kBStageWords, "transpose areas fit in two stage buffers");
+    const float xxmax = load_x_frags<PREC, NB>(P, row0, s1, g, col, F, sdx, xt);
     // One shift for the whole wave makes every screen value positive (see the FP32 screen).
     const float beta = xxmax * (1.0f + 0.00390625f) + 0.00390625f * cnmax + 1e-30f;
     float el[NB][4];

@@ -435,16 +435,32 @@ __device__ __forceinline__ float load_x_frags(const Params& P, int64_t row0, int
         // cache lines per instruction.
         float4 ld[NB][8];
         const int lane = threadIdx.x & 63;
+        // physical rows first (the serving path's row map), all lookups in flight together
+        int64_t rr[NB][8];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int64_t v = row0 + nb * 16 + 2 * i + (lane >> 5);
-                const bool valid = v < s1;
-                const int64_t r = valid ? (P.rowmap ? (int64_t)P.rowmap[v] : v) : 0;
-                ld[nb][i] = valid ? reinterpret_cast<const float4*>(P.x + r * kDim)[lane & 31]
-                                  : make_float4(0.f, 0.f, 0.f, 0.f);
+                rr[nb][i] = v < s1 ? v : -1;
             }
+        if (P.rowmap) {  // unconditional lookups (rows past s1 read the last row's entry) keep them in flight together
+            int32_t m[NB][8];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) m[nb][i] = P.rowmap[rr[nb][i] >= 0 ? rr[nb][i] : s1 - 1];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) rr[nb][i] = rr[nb][i] >= 0 ? (int64_t)m[nb][i] : -1;
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                ld[nb][i] = rr[nb][i] >= 0 ? reinterpret_cast<const float4*>(P.x + rr[nb][i] * kDim)[lane & 31]
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             float xx = 0.f, dyy = 0.f;

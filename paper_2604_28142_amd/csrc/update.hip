@@ -4,8 +4,12 @@
 // Determinism without float atomics: rows are stably sorted by assigned
 // centroid (radix sort on the assignment), so every centroid's members form a
 // contiguous run in ascending row order, and one wavefront sums each run in
-// that fixed order (two dimensions per lane).  Tokens with more than 65,536
-// rows sum in float64; smaller ones use compensated (Kahan) float32 sums.
+// that fixed order (two dimensions per lane).  Runs longer than kChunk members
+// are cut into chunks of kChunk that separate wavefronts sum, and the chunk
+// sums are then added in chunk order, so one large cluster does not hold the
+// whole update up; the cut points depend only on the counts.  Tokens with more
+// than 65,536 rows sum in float64; smaller ones use compensated (Kahan)
+// float32 sums, chunk sums included.
 #include "tac_internal.h"
 
 namespace tac {
@@ -30,6 +34,7 @@ __global__ void member_offsets(const uint32_t* __restrict__ keys, int64_t n, int
 }
 
 constexpr int kUnroll = 8;
+constexpr int64_t kChunk = 256;  // members per chunk of a long run
 
 // wide[k] = 1 when centroid k's token has more than kFp64Rows rows (the token is
 // found from the centroid's first member); one thread per centroid, so the
@@ -52,6 +57,58 @@ __global__ void centroid_flags(const int64_t* __restrict__ seg_off, int32_t T, c
     }
 }
 
+// Sum of members [b, e) of a run (two dimensions per lane, lane's pair of x
+// columns), in member order; the rows of kUnroll members are loaded before
+// they are added, so that many loads are in flight per wave.  Wide: float64;
+// else a compensated float32 sum, returned as its corrected value.
+__device__ __forceinline__ double2 run_sum(const float* __restrict__ xs, const int32_t* __restrict__ rows, int64_t b,
+                                           int64_t e, bool wide, int lane) {
+    if (wide) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int64_t p = b; p < e; p += kUnroll) {
+            float2 v[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                if (p + u < e) v[u] = reinterpret_cast<const float2*>(xs + (int64_t)rows[p + u] * kDim)[lane];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                if (p + u < e) {
+                    s0 += (double)v[u].x;
+                    s1 += (double)v[u].y;
+                }
+        }
+        return make_double2(s0, s1);
+    }
+    float s0 = 0.f, s1 = 0.f, c0 = 0.f, c1 = 0.f;
+    for (int64_t p = b; p < e; p += kUnroll) {
+        float2 v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (p + u < e) v[u] = reinterpret_cast<const float2*>(xs + (int64_t)rows[p + u] * kDim)[lane];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (p + u >= e) break;
+            float y = __fsub_rn(v[u].x, c0);
+            float t = __fadd_rn(s0, y);
+            c0 = __fsub_rn(__fsub_rn(t, s0), y);
+            s0 = t;
+            y = __fsub_rn(v[u].y, c1);
+            t = __fadd_rn(s1, y);
+            c1 = __fsub_rn(__fsub_rn(t, s1), y);
+            s1 = t;
+        }
+    }
+    return make_double2((double)__fsub_rn(s0, c0), (double)__fsub_rn(s1, c1));
+}
+
+__device__ __forceinline__ float2 run_mean(double2 sum, int64_t cnt, bool wide) {
+    if (wide) return make_float2((float)(sum.x / (double)cnt), (float)(sum.y / (double)cnt));
+    const float fc = (float)cnt;
+    return make_float2(__fdiv_rn((float)sum.x, fc), __fdiv_rn((float)sum.y, fc));
+}
+
+// Centroids with at most kChunk members: one wave each.  Longer runs are left
+// to chunk_sums / chunk_means.
 __global__ void __launch_bounds__(256) centroid_means(const float* __restrict__ xs, const uint8_t* __restrict__ wide_k,
                                                       const int32_t* __restrict__ rows,
                                                       const int64_t* __restrict__ off, int64_t K,
@@ -64,56 +121,85 @@ __global__ void __launch_bounds__(256) centroid_means(const float* __restrict__ 
         const int64_t b = off[k], e = off[k + 1];
         const int64_t cnt = e - b;
         if (count && lane == 0) count[k] = cnt;
+        if (cnt > kChunk) continue;
         float2* out = reinterpret_cast<float2*>(C_new + k * kDim);
         if (cnt == 0) {
             out[lane] = reinterpret_cast<const float2*>(C_old + k * kDim)[lane];
             continue;
         }
         const bool wide = wide_k[k] != 0;
-        float2 mean;
-        // members are summed in sorted order; the rows of kUnroll members are
-        // loaded before they are added, so that many loads are in flight per wave
+        out[lane] = run_mean(run_sum(xs, rows, b, e, wide, lane), cnt, wide);
+    }
+}
+
+// chunk slots of the long runs: nch[k] = number of kChunk chunks of centroid k
+// when it has more than kChunk members, else 0 (exclusive-scanned afterwards)
+__global__ void chunk_count(const int64_t* __restrict__ off, int64_t K, int64_t* __restrict__ nch) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t cnt = off[k + 1] - off[k];
+        nch[k] = cnt > kChunk ? (cnt + kChunk - 1) / kChunk : 0;
+    }
+}
+
+// one wave per chunk of a long run: its sum into part[chunk] (128 values)
+__global__ void __launch_bounds__(256) chunk_sums(const float* __restrict__ xs, const uint8_t* __restrict__ wide_k,
+                                                  const int32_t* __restrict__ rows, const int64_t* __restrict__ off,
+                                                  int64_t K, const int64_t* __restrict__ choff,
+                                                  double* __restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t total = choff[K];
+    for (int64_t c = wave0; c < total; c += nwaves) {
+        int64_t lo = 0, hi = K;  // centroid: the last k with choff[k] <= c
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (choff[mid] <= c) lo = mid; else hi = mid;
+        }
+        const int64_t k = lo;
+        const int64_t b = off[k] + (c - choff[k]) * kChunk;
+        const int64_t e = min(off[k + 1], b + kChunk);
+        reinterpret_cast<double2*>(part + c * kDim)[lane] = run_sum(xs, rows, b, e, wide_k[k] != 0, lane);
+    }
+}
+
+// one wave per long run: its chunk sums added in chunk order (float64 for wide
+// tokens, compensated float32 otherwise), then the mean
+__global__ void __launch_bounds__(256) chunk_means(const uint8_t* __restrict__ wide_k, const int64_t* __restrict__ off,
+                                                   int64_t K, const int64_t* __restrict__ choff,
+                                                   const double* __restrict__ part, float* __restrict__ C_new) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t k = wave0; k < K; k += nwaves) {
+        const int64_t c0 = choff[k], c1 = choff[k + 1];
+        if (c0 == c1) continue;
+        const bool wide = wide_k[k] != 0;
+        double2 sum;
         if (wide) {
             double s0 = 0.0, s1 = 0.0;
-            for (int64_t p = b; p < e; p += kUnroll) {
-                float2 v[kUnroll];
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
-                    if (p + u < e) v[u] = reinterpret_cast<const float2*>(xs + (int64_t)rows[p + u] * kDim)[lane];
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
-                    if (p + u < e) {
-                        s0 += (double)v[u].x;
-                        s1 += (double)v[u].y;
-                    }
+            for (int64_t c = c0; c < c1; ++c) {
+                const double2 v = reinterpret_cast<const double2*>(part + c * kDim)[lane];
+                s0 += v.x;
+                s1 += v.y;
             }
-            mean.x = (float)(s0 / (double)cnt);
-            mean.y = (float)(s1 / (double)cnt);
+            sum = make_double2(s0, s1);
         } else {
-            float s0 = 0.f, s1 = 0.f, c0 = 0.f, c1 = 0.f;
-            for (int64_t p = b; p < e; p += kUnroll) {
-                float2 v[kUnroll];
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
-                    if (p + u < e) v[u] = reinterpret_cast<const float2*>(xs + (int64_t)rows[p + u] * kDim)[lane];
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    if (p + u >= e) break;
-                    float y = __fsub_rn(v[u].x, c0);
-                    float t = __fadd_rn(s0, y);
-                    c0 = __fsub_rn(__fsub_rn(t, s0), y);
-                    s0 = t;
-                    y = __fsub_rn(v[u].y, c1);
-                    t = __fadd_rn(s1, y);
-                    c1 = __fsub_rn(__fsub_rn(t, s1), y);
-                    s1 = t;
-                }
+            float s0 = 0.f, s1 = 0.f, e0 = 0.f, e1 = 0.f;
+            for (int64_t c = c0; c < c1; ++c) {
+                const double2 v = reinterpret_cast<const double2*>(part + c * kDim)[lane];
+                float y = __fsub_rn((float)v.x, e0);
+                float t = __fadd_rn(s0, y);
+                e0 = __fsub_rn(__fsub_rn(t, s0), y);
+                s0 = t;
+                y = __fsub_rn((float)v.y, e1);
+                t = __fadd_rn(s1, y);
+                e1 = __fsub_rn(__fsub_rn(t, s1), y);
+                s1 = t;
             }
-            const float fc = (float)cnt;
-            mean.x = __fdiv_rn(__fsub_rn(s0, c0), fc);
-            mean.y = __fdiv_rn(__fsub_rn(s1, c1), fc);
+            sum = make_double2((double)__fsub_rn(s0, e0), (double)__fsub_rn(s1, e1));
         }
-        out[lane] = mean;
+        reinterpret_cast<float2*>(C_new + k * kDim)[lane] = run_mean(sum, off[k + 1] - off[k], wide);
     }
 }
 
@@ -149,6 +235,10 @@ extern "C" tac_status tac_update(tac_ctx ctx, const float* xs_d, const int64_t* 
     const size_t o_sort = cv.take<char>(radix_sort_scratch_bytes(N));
     const size_t o_off = cv.take<int64_t>(K + 1);
     const size_t o_wide = cv.take<uint8_t>(K + 1);
+    const size_t o_choff = cv.take<int64_t>(K + 1);
+    const size_t o_cscan = cv.take<char>(scan_scratch_bytes(K));
+    // chunks of the long runs: each has more than kChunk members, so there are at most 2 N / kChunk
+    const size_t o_part = cv.take<double>((2 * N / kChunk + 1) * kDim);
     tac_status st = ws_reserve(ctx, cv.off);
     if (st != TAC_OK) return st;
     uint32_t* k0 = ws_at<uint32_t>(ctx, o_k0);
@@ -171,8 +261,19 @@ extern "C" tac_status tac_update(tac_ctx ctx, const float* xs_d, const int64_t* 
     uint8_t* wide = ws_at<uint8_t>(ctx, o_wide);
     centroid_flags<<<grid_for(K, 256), 256, 0, s>>>(seg_off_d, T, in1 ? v1 : v0, off, K, wide);
     TAC_LAUNCH_CHECK("centroid_flags");
-    centroid_means<<<grid_for(K * 64, 256), 256, 0, s>>>(xs_d, wide, in1 ? v1 : v0, off, K, C_old_d, C_new_d, count_d);
+    const int32_t* srows = in1 ? v1 : v0;
+    centroid_means<<<grid_for(K * 64, 256), 256, 0, s>>>(xs_d, wide, srows, off, K, C_old_d, C_new_d, count_d);
     TAC_LAUNCH_CHECK("centroid_means");
+    int64_t* choff = ws_at<int64_t>(ctx, o_choff);
+    double* part = ws_at<double>(ctx, o_part);
+    chunk_count<<<grid_for(K, 256), 256, 0, s>>>(off, K, choff);
+    TAC_LAUNCH_CHECK("chunk_count");
+    st = exclusive_scan_i64(s, choff, choff, K, ws_at<void>(ctx, o_cscan));
+    if (st != TAC_OK) return st;
+    chunk_sums<<<(unsigned)ctx->props_cu * 32, 256, 0, s>>>(xs_d, wide, srows, off, K, choff, part);
+    TAC_LAUNCH_CHECK("chunk_sums");
+    chunk_means<<<grid_for(K * 64, 256), 256, 0, s>>>(wide, off, K, choff, part, C_new_d);
+    TAC_LAUNCH_CHECK("chunk_means");
     time_stop(ctx, TAC_SLOT_UPDATE);
     return TAC_OK;
 }

@@ -116,6 +116,37 @@ def test_f16_operand_range(ctx):
     assert np.array_equal(a, a0) and np.array_equal(d, d0)
 
 
+def test_update_long_runs(ctx):
+    """Clusters far longer than one summation chunk, in a float64 token
+    (more than 65,536 rows) and in a compensated-float32 token: means within
+    1e-5 of the float64 oracle, exact counts, bitwise-equal repeated calls, and
+    empty clusters keep their old centroid."""
+    rng = np.random.default_rng(17)
+    sizes = [70000, 3000, 40]
+    xs = np.concatenate([clustered(rng, n, 3, spread=0.5) for n in sizes])
+    seg_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    kap = [3, 4, 2]
+    cent_off = np.concatenate([[0], np.cumsum(kap)]).astype(np.int64)
+    K = int(cent_off[-1])
+    C_old = rng.standard_normal((K, 128)).astype(np.float32)
+    a = np.empty(xs.shape[0], np.int64)
+    a[:70000] = rng.choice([0, 1], 70000, p=[0.9, 0.1])        # centroid 2 stays empty
+    a[70000:73000] = 3 + rng.choice([0, 1, 3], 3000)          # 1 of token 1 (centroid 5) stays empty
+    a[73000:] = 7 + rng.integers(0, 2, 40)
+    C1, cnt1 = oracle.update(xs, a, C_old)
+    outs = []
+    for _ in range(2):
+        Cn = torch.empty((K, 128), dtype=torch.float32, device="cuda")
+        cnt = torch.empty(K, dtype=torch.int64, device="cuda")
+        tac.tac_update(ctx, dev(xs), dev(seg_off), dev(a.astype(np.int32)), dev(C_old), Cn, cnt)
+        assert np.array_equal(host(cnt), cnt1)
+        check_centroids(host(Cn), C1)
+        outs.append(host(Cn))
+    assert np.array_equal(outs[0], outs[1])
+    empty = cnt1 == 0
+    assert empty.sum() == 2 and np.array_equal(outs[0][empty], C_old[empty])
+
+
 def test_dyadic_exact_ties_bitwise(ctx):
     """Dyadic 1-D values in coordinate 0 make every float operation exact, so
     equal distances are exact ties; both paths break them to the lowest index

@@ -3,7 +3,8 @@
 TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, deliberately simple
 NumPy implementation of what the GPU library computes, written from the paper
 (Sect. 2.1: tail handling, damped scoring, bounding, budget reconciliation,
-per-token k-means, residual compression with product quantisation).  Only the
+per-token k-means, residual compression with product quantisation), and the
+inverted lists and document layout built from it (Sect. 2.2).  Only the
 test suite, the smoke check and the CPU-baseline leg of the benchmark may
 import it; the product path never does, and it imports nothing from the
 product package.
@@ -25,10 +26,12 @@ from .budget import BudgetParams, budget, cent_offsets
 from .lloyd import (assign, update, inertia, init_centroids, lloyd,
                     assign_rows)
 from .pq import residuals, pq_encode, pq_train, pq_decode
+from .ivf import inverted_lists, doc_layout, decode_layout
 from . import dist32
 
 __all__ = [
     "group_by_token", "spreads", "BudgetParams", "budget", "cent_offsets",
     "assign", "update", "inertia", "init_centroids", "lloyd", "assign_rows",
     "residuals", "pq_encode", "pq_train", "pq_decode", "dist32",
+    "inverted_lists", "doc_layout", "decode_layout",
 ]

@@ -229,6 +229,31 @@ tac_status pq_encode(tac_ctx ctx, const float* x_d, const int32_t* assign_d, con
                      int64_t K, int64_t n, int32_t d, const float* codebooks_d, int32_t M,
                      int32_t ksub, int normalize, uint8_t* codes_d, float* rnorm_d);
 
+/* Inverted lists (Sect. 2.2, "Index Structure"): every centroid keeps the ids
+ * of the documents whose tokens are assigned to it.  assign_d [N] int32 (the
+ * token's centroid; outside [0, K) enters no list), doc_d [N] int32 (the
+ * token's document; outside [0, D) enters no list), in any order.  Output:
+ * list_off_d [K + 1] int64 and list_docs_d (capacity N int32); list k is
+ * list_docs_d[list_off_d[k] .. list_off_d[k + 1]), each document id once, in
+ * increasing order; list_off_d[K] is the number of entries.  The caller owns
+ * all buffers; the workspace grows by about 40 bytes per token.  Asynchronous;
+ * TAC_E_INVAL on bad sizes or NULL pointers. */
+tac_status tac_ivf_build(tac_ctx ctx, const int32_t* assign_d, const int32_t* doc_d, int64_t N, int64_t K,
+                         int64_t D, int64_t* list_off_d, int32_t* list_docs_d);
+
+/* Document layout (Sect. 2.2, "Document Layout"): per document, the centroid
+ * ids of all of its tokens contiguously, followed by all of their PQ codes.
+ * The tokens of document d are rows doc_off_d[d] .. doc_off_d[d + 1] - 1
+ * (doc_off_d [D + 1] int64, non-decreasing from 0 to N); assign_d [N] int32,
+ * codes_d [N, M] uint8.  Output layout_d [N * (4 + M)] uint8: document d
+ * occupies bytes [doc_off_d[d] * (4 + M), doc_off_d[d + 1] * (4 + M)): its
+ * centroid ids as 4-byte little-endian integers, then its codes in token
+ * order (M per token).  Offsets outside [0, N] are clamped, so a malformed
+ * doc_off_d never addresses memory outside the layout (the affected documents'
+ * bytes are then unspecified).  Asynchronous; TAC_E_INVAL on bad sizes. */
+tac_status tac_doc_layout(tac_ctx ctx, const int32_t* assign_d, const uint8_t* codes_d, int32_t M,
+                          const int64_t* doc_off_d, int64_t D, int64_t N, uint8_t* layout_d);
+
 #ifdef __cplusplus
 }
 #endif

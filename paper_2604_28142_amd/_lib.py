@@ -26,7 +26,8 @@ _STATUS = {TAC_E_INVAL: "TAC_E_INVAL", TAC_E_INFEASIBLE: "TAC_E_INFEASIBLE", TAC
 EXPORTS = ["tac_ctx_create", "tac_ctx_set_stream", "tac_ctx_destroy", "tac_last_error", "tac_budget",
            "tac_budget_from_stats",
            "tac_init_centroids", "tac_assign", "tac_assign_stats", "tac_update", "tac_residuals", "pq_train",
-           "pq_encode", "tac_ctx_enable_timing", "tac_kernel_ms", "tac_ctx_set_tuning", "tac_ctx_get_tuning"]
+           "pq_encode", "tac_ctx_enable_timing", "tac_kernel_ms", "tac_ctx_set_tuning", "tac_ctx_get_tuning",
+           "tac_ivf_build", "tac_doc_layout"]
 TAC_SLOT_ASSIGN, TAC_SLOT_UPDATE, TAC_SLOT_ENCODE = 0, 1, 2
 
 
@@ -76,6 +77,8 @@ _SIGS = {
     "tac_residuals": (C.c_int, [_P, _P, _P, _P, _I64, _P, _I64, _I32, C.c_int, _P, _P]),
     "pq_train": (C.c_int, [_P, _P, _I64, _I32, _I32, _I32, _I32, _P, _P]),
     "pq_encode": (C.c_int, [_P, _P, _P, _P, _I64, _I64, _I32, _P, _I32, _I32, C.c_int, _P, _P]),
+    "tac_ivf_build": (C.c_int, [_P, _P, _P, _I64, _I64, _I64, _P, _P]),
+    "tac_doc_layout": (C.c_int, [_P, _P, _P, _I32, _P, _I64, _I64, _P]),
 }
 
 _lib = None
@@ -278,3 +281,31 @@ def pq_encode(ctx: Context, x, assign, C_cent, codebooks, codes, normalize: bool
     _check_dtype(codes, torch.uint8, "codes")
     _check(load().pq_encode(ctx.handle, _dptr(x), _dptr(assign), _dptr(C_cent), C_cent.shape[0], n, d,
                             _dptr(codebooks), M, ksub, int(normalize), _dptr(codes), _dptr(rnorm)))
+
+
+def tac_ivf_build(ctx: Context, assign, doc, K: int, D: int, list_off, list_docs):
+    """Inverted lists (Sect. 2.2): list k = list_docs[list_off[k]:list_off[k + 1]], unique increasing
+    document ids; list_off[K] entries in all.  assign, doc: int32 [N]; list_off int64 [K + 1];
+    list_docs int32 with room for N."""
+    N = assign.shape[0]
+    _check_dtype(assign, torch.int32, "assign")
+    _check_dtype(doc, torch.int32, "doc")
+    _check_dtype(list_off, torch.int64, "list_off")
+    _check_dtype(list_docs, torch.int32, "list_docs")
+    if doc.shape[0] != N or list_off.shape[0] != K + 1 or list_docs.shape[0] < N:
+        raise ValueError("tac_ivf_build: inconsistent shapes")
+    _check(load().tac_ivf_build(ctx.handle, _dptr(assign), _dptr(doc), N, K, D, _dptr(list_off), _dptr(list_docs)))
+
+
+def tac_doc_layout(ctx: Context, assign, codes, doc_off, layout):
+    """Document layout (Sect. 2.2): per document its centroid ids (int32 LE), then its PQ codes.
+    assign int32 [N], codes uint8 [N, M], doc_off int64 [D + 1], layout uint8 [N * (4 + M)]."""
+    N, M = codes.shape
+    D = doc_off.shape[0] - 1
+    _check_dtype(assign, torch.int32, "assign")
+    _check_dtype(codes, torch.uint8, "codes")
+    _check_dtype(doc_off, torch.int64, "doc_off")
+    _check_dtype(layout, torch.uint8, "layout")
+    if assign.shape[0] != N or layout.numel() != N * (4 + M):
+        raise ValueError("tac_doc_layout: inconsistent shapes")
+    _check(load().tac_doc_layout(ctx.handle, _dptr(assign), _dptr(codes), M, _dptr(doc_off), D, N, _dptr(layout)))

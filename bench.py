@@ -165,6 +165,50 @@ def serve_bench(idx, w, requests: int, seed: int = 0):
     return out
 
 
+def index_structures(ctx, idx, w, N):
+    """Inverted lists and document layout (Sect. 2.2) from the step's final
+    assignment and codes; the build's vectors form documents of 30-180
+    consecutive input rows (seeded).  Timed with HIP events on the context's
+    stream; the inputs are mapped back to input order beforehand."""
+    import datagen
+    import torch
+    import paper_2604_28142_amd as tac
+    doc_off_h = datagen.build_doc_offsets(N, w.seed)
+    D = doc_off_h.size - 1
+    dev = idx.xs.device
+    perm = idx.perm.long()
+    doc_in = torch.from_numpy(np.repeat(np.arange(D, dtype=np.int32), np.diff(doc_off_h))).to(dev)
+    doc_sorted = doc_in[perm].contiguous()
+    assign_in = torch.empty_like(idx.assign)
+    assign_in[perm] = idx.assign
+    codes_in = torch.empty_like(idx.codes)
+    codes_in[perm] = idx.codes
+    K = idx.C.shape[0]
+    M = idx.codes.shape[1]
+    list_off = torch.empty(K + 1, dtype=torch.int64, device=dev)
+    list_docs = torch.empty(N, dtype=torch.int32, device=dev)
+    layout = torch.empty(N * (4 + M), dtype=torch.uint8, device=dev)
+    doc_off = torch.from_numpy(doc_off_h).to(dev)
+    stream = ctx.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    tac.tac_ivf_build(ctx, idx.assign, doc_sorted, K, D, list_off, list_docs)    # sizes the workspace
+    ms_ivf, ms_lay = [], []
+    for _ in range(3):
+        ev[0].record(stream)
+        tac.tac_ivf_build(ctx, idx.assign, doc_sorted, K, D, list_off, list_docs)
+        ev[1].record(stream)
+        tac.tac_doc_layout(ctx, assign_in, codes_in, doc_off, layout)
+        ev[2].record(stream)
+        ev[2].synchronize()
+        ms_ivf.append(ev[0].elapsed_time(ev[1]))
+        ms_lay.append(ev[1].elapsed_time(ev[2]))
+    entries = int(list_off[-1].item())
+    lay_bytes = 2.0 * N * (4 + M)
+    return {"documents": D, "list_entries": entries, "ivf_build_ms": float(np.median(ms_ivf)),
+            "doc_layout_ms": float(np.median(ms_lay)),
+            "doc_layout_GBps": lay_bytes / (float(np.median(ms_lay)) / 1e3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -349,6 +393,9 @@ def main():
     extra["mfma_executed_tflops"] = {nm: PRODUCTS[nm] * F / (kms[nm] / 1e3) / 1e12 for nm in legs}
     if "fp32" in kms:
         extra["fp32_roofline_frac"] = F / (kms["fp32"] / 1e3) / 1e12 / PEAK["fp32"]
+
+    extra["index_structures"] = index_structures(ctx, idx, w, N)
+    log(f"inverted lists + document layout: {extra['index_structures']}")
 
     if args.global_baseline:
         extra["global_kmeans"] = global_baseline(ctx, idx, w, lloyd_med / args.iters, args.global_baseline)

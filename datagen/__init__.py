@@ -180,6 +180,18 @@ def pq_init_rows(size: int, ksub: int, seed: int) -> np.ndarray:
     return np.random.default_rng([seed, 6]).permutation(size)[:ksub]
 
 
+def build_doc_offsets(n: int, seed: int = 0, lo: int = 30, hi: int = 180) -> np.ndarray:
+    """int64[D + 1]: the build's vectors, in input order, cut into documents of
+    U{lo..hi} consecutive vectors (the last one shorter; stream 10)."""
+    rng = np.random.default_rng([seed, 10])
+    lens = rng.integers(lo, hi + 1, size=n // lo + 1)
+    off = np.concatenate([[0], np.cumsum(lens)])
+    D = int(np.searchsorted(off, n, side="left"))
+    off = off[:D + 1].copy()
+    off[-1] = n
+    return off.astype(np.int64)
+
+
 def serving_docs(w: Workload | str, ndocs: int, seed: int = 0, lo: int = 30, hi: int = 180):
     """Documents for the encode service: n_d ~ U{lo..hi} vectors each, token ids
     from the workload's Zipf law and vectors around the same centres with fresh

@@ -238,45 +238,84 @@ __global__ void __launch_bounds__(512) train_encode(const float* __restrict__ R,
 // come from one v_mfma_f32_16x16x4f32 (the four coordinates of the subspace
 // are the contraction): lane (g, col) supplies coordinate g of code 16 t + col
 // and of row col, and receives codes 16 t + 4 g + r of row col.  Each lane
-// keeps a top-2 of packed keys over its 64 codes; the four lanes of a row then
-// rescore their candidates with the canonical distance, take the
-// lexicographic minimum and certify it against every code a list dropped
-// (that value is at least the list's second entry); a row that fails is
-// scanned exhaustively.  Codes are bitwise those of the scalar screen.
-// Rows: 8 waves x 4 blocks of 16 rows per block iteration, codebooks in LDS.
+// keeps a top-2 of packed keys over its ksub / 4 codes; the four lanes of a row
+// then rescore their first entries with the canonical distance, take the
+// lexicographic minimum and certify it against every other code, whose screen
+// value is at least the smallest second entry of the four lists (so a second
+// entry can never beat a certified winner and is not rescored); a row that
+// fails is scanned exhaustively after all four row blocks of the wave are
+// certified.
+// Codes are bitwise those of the scalar screen.
+// Work split: the 32 subspaces are encoded by two work-groups per block of
+// 512 rows (16 subspaces each, 80 KiB of codebooks and norms in LDS), so two
+// work-groups share a CU and hide each other's load and shuffle latency.
 constexpr int kEThreads = 512;
 constexpr int kENB = 4;
 constexpr int kERows = (kEThreads / 64) * kENB * 16;
+constexpr int kEHalf = 16;  // subspaces per work-group
 static_assert(kENB * 16 == 64, "one prologue row per lane");
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ void top2_insert(float& l0, float& l1, float p) {
-    l1 = __builtin_amdgcn_fmed3f(l0, l1, p);
-    l0 = __builtin_amdgcn_fmed3f(l0, p, -FLT_MAX);
+// Top-2 (l0 <= l1) of packed keys after two more keys a and b.  The keys are
+// bit patterns of positive floats, so unsigned order is value order.  The new
+// minimum is min(l0, a, b); the new second is min(l1, med3(l0, a, b)), since
+// the second smallest of {l0, l1, a, b} is the smallest of what is left once
+// the overall minimum (which lies in {l0, a, b}) is taken out.
+__device__ __forceinline__ void top2_insert2(unsigned& l0, unsigned& l1, unsigned a, unsigned b) {
+    l1 = min(l1, med3u(l0, a, b));
+    l0 = min(min(l0, a), b);
+}
+
+// Maximum over each row of 16 lanes of non-negative floats (compared as their
+// bit patterns), through DPP lane permutations: swap neighbours, swap pairs,
+// mirror each half row, mirror the row.
+template <int kCtrl>
+__device__ __forceinline__ unsigned dpp_max(unsigned v) {
+    return max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float row16_max(float v) {
+    unsigned b = __float_as_uint(v);
+    b = dpp_max<0xB1>(b);   // quad_perm [1, 0, 3, 2]
+    b = dpp_max<0x4E>(b);   // quad_perm [2, 3, 0, 1]
+    b = dpp_max<0x141>(b);  // row_half_mirror
+    b = dpp_max<0x140>(b);  // row_mirror
+    return __uint_as_float(b);
+}
+
+// Packed key: the screen value's bits with the low byte replaced by byte r of
+// `codes` (four consecutive codes, one per byte).
+template <int r>
+__device__ __forceinline__ unsigned screen_key(float v, unsigned codes) {
+    return __builtin_amdgcn_perm(__float_as_uint(v), codes, 0x07060500u + r);
 }
 
 template <bool RESID>
-__global__ void __launch_bounds__(kEThreads) encode_screen(const float* __restrict__ x,
-                                                           const int32_t* __restrict__ assign,
-                                                           const float* __restrict__ C, int64_t K, int64_t n,
-                                                           int normalize, const float* __restrict__ cbg, int ksub,
-                                                           uint8_t* __restrict__ codes_rows,
-                                                           uint32_t* __restrict__ codes_sub,
-                                                           float* __restrict__ rnorm) {
+__global__ void __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(4))) encode_screen(const float* __restrict__ x,
+                                                              const int32_t* __restrict__ assign,
+                                                              const float* __restrict__ C, int64_t K, int64_t n,
+                                                              int normalize, const float* __restrict__ cbg, int ksub,
+                                                              uint8_t* __restrict__ codes_rows,
+                                                              uint32_t* __restrict__ codes_sub,
+                                                              float* __restrict__ rnorm) {
     constexpr int M = kDim / kDsub;
+    static_assert(M == 2 * kEHalf, "two halves of the subspaces");
+    constexpr unsigned kNoKey = 0x7F7FFFFFu;  // FLT_MAX: an empty list entry
     extern __shared__ float4 lds4[];
+    const int m0 = (int)(blockIdx.x & 1) * kEHalf;
     float4* lcb = lds4;
-    float* lcn = reinterpret_cast<float*>(lds4 + M * ksub);
-    const float cnmax = load_codebooks_norms(cbg, M, ksub, lcb, lcn);
+    float* lcn = reinterpret_cast<float*>(lds4 + kEHalf * ksub);
+    const float cnmax = load_codebooks_norms(cbg + (size_t)m0 * ksub * kDsub, kEHalf, ksub, lcb, lcn);
     const float* lcbf = reinterpret_cast<const float*>(lcb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
     const double uc = 5.9604644775390625e-8;  // 2^-24
     const double g6 = 6.0 * uc / (1.0 - 6.0 * uc);
     const double g10 = 10.0 * uc / (1.0 - 10.0 * uc);
     const double cm2 = (double)cnmax * (1.0 + 1e-5);
+    const double scm = sqrt(cm2);
     const int nt = ksub / 16;
-    for (int64_t base = (int64_t)blockIdx.x * kERows; base < n; base += (int64_t)gridDim.x * kERows) {
+    const int64_t nblk = gridDim.x >> 1;
+    for (int64_t base = (int64_t)(blockIdx.x >> 1) * kERows; base < n; base += nblk * kERows) {
         const int64_t wbase = base + wave * (kENB * 16);
         // lane-per-row prologue: validity, centroid and canonical residual norm
         const int64_t myrow = wbase + lane;
@@ -288,7 +327,7 @@ __global__ void __launch_bounds__(kEThreads) encode_screen(const float* __restri
                 a = assign[myrow];
                 ok_row = a >= 0 && a < K;
                 if (ok_row) rho = residual_norm(x + myrow * kDim, C + (int64_t)a * kDim);
-                if (rnorm) rnorm[myrow] = rho;
+                if (rnorm && m0 == 0) rnorm[myrow] = rho;
             } else {
                 ok_row = 1;
             }
@@ -303,51 +342,71 @@ __global__ void __launch_bounds__(kEThreads) encode_screen(const float* __restri
             vrow[nb] = __shfl(ok_row, nb * 16 + col);
             word[nb] = 0u;
         }
-        for (int m = 0; m < M; ++m) {
-            float u[kENB], um = 0.f;
+        // coordinate 4 m + g of every row block, one subspace ahead of its use
+        float xs[kENB] = {}, cs[kENB] = {};
+        auto fetch = [&](int m) {
 #pragma unroll
             for (int nb = 0; nb < kENB; ++nb) {
-                const int64_t row = wbase + nb * 16 + col;
+                if (vrow[nb]) {
+                    const int64_t row = wbase + nb * 16 + col;
+                    xs[nb] = x[row * kDim + kDsub * m + g];
+                    if constexpr (RESID) cs[nb] = C[(int64_t)arow[nb] * kDim + kDsub * m + g];
+                }
+            }
+        };
+        fetch(m0);
+        for (int mi = 0; mi < kEHalf; ++mi) {
+            const int m = m0 + mi;
+            float u[kENB], sq[kENB], um = 0.f;
+#pragma unroll
+            for (int nb = 0; nb < kENB; ++nb) {
                 float v = 0.f;
                 if (vrow[nb]) {
                     if constexpr (RESID) {
-                        v = __fsub_rn(x[row * kDim + kDsub * m + g], C[(int64_t)arow[nb] * kDim + kDsub * m + g]);
+                        v = __fsub_rn(xs[nb], cs[nb]);
                         if (normalize) v = rrow[nb] > 0.f ? __fdiv_rn(v, rrow[nb]) : 0.f;
                     } else {
-                        v = x[row * kDim + kDsub * m + g];
+                        v = xs[nb];
                     }
                 }
                 u[nb] = v;
-                float sq = v * v;
-                sq += __shfl_xor(sq, 16);
-                sq += __shfl_xor(sq, 32);
-                um = fmaxf(um, sq);
+                float s = v * v;
+                s += __shfl_xor(s, 16);
+                s += __shfl_xor(s, 32);
+                sq[nb] = s;  // the row's ||u||^2, within a relative 3 u of the exact value
+                um = fmaxf(um, s);
             }
-#pragma unroll
-            for (int o = 1; o < 16; o <<= 1) um = fmaxf(um, __shfl_xor(um, o));
+            if (mi + 1 < kEHalf) fetch(m + 1);
+            um = row16_max(um);
             // one shift per wave and subspace: beta >= ||u||^2 + (screen error) for each of its rows
             const float beta = um * (1.0f + 0.00390625f) + 0.00390625f * cnmax + 1e-30f;
-            float l0[kENB], l1[kENB];
+            unsigned l0[kENB], l1[kENB];
 #pragma unroll
             for (int nb = 0; nb < kENB; ++nb) {
-                l0[nb] = FLT_MAX;
-                l1[nb] = FLT_MAX;
+                l0[nb] = kNoKey;
+                l1[nb] = kNoKey;
             }
-            const float* cbm = lcbf + (size_t)m * ksub * kDsub;
-            const float* cnm = lcn + (size_t)m * ksub;
+            const float* cbm = lcbf + (size_t)mi * ksub * kDsub;
+            const float* cnm = lcn + (size_t)mi * ksub;
+            // codes 16 t + 4 g + r, r = 0..3, one per byte (at most 255: no carry between bytes)
+            unsigned cb4 = (unsigned)(4 * g) * 0x01010101u + 0x03020100u;
             for (int t = 0; t < nt; ++t) {
                 const float af = cbm[(16 * t + col) * kDsub + g];
                 const f4 ci = *reinterpret_cast<const f4*>(cnm + 16 * t + 4 * g) + beta;
 #pragma unroll
                 for (int nb = 0; nb < kENB; ++nb) {
                     const f4 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af, -2.0f * u[nb], ci, 0, 0, 0);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        top2_insert(l0[nb], l1[nb],
-                                    __uint_as_float(__builtin_amdgcn_perm(__float_as_uint(acc[r]),
-                                                                          (unsigned)(16 * t + 4 * g + r), 0x07060500u)));
+                    top2_insert2(l0[nb], l1[nb], screen_key<0>(acc[0], cb4), screen_key<1>(acc[1], cb4));
+                    top2_insert2(l0[nb], l1[nb], screen_key<2>(acc[2], cb4), screen_key<3>(acc[3], cb4));
                 }
+                cb4 += 0x10101010u;
             }
+            // The screen's error bound for every row of the wave: um bounds ||u||^2 within 3 u.
+            const double bt = (double)beta;
+            const double E = 1.1 * g10 * (2.0 * (cm2 + bt) + 2.0 * sqrt((double)um * (1.0 + g6)) * scm) + 1e-30;
+            const float4* cbv = lcb + (size_t)mi * ksub;
+            int code[kENB];
+            unsigned fail = 0u;
 #pragma unroll
             for (int nb = 0; nb < kENB; ++nb) {
                 // the row's subvector in every lane of the row
@@ -356,62 +415,60 @@ __global__ void __launch_bounds__(kEThreads) encode_screen(const float* __restri
                 uv.y = __shfl(u[nb], 16 + col);
                 uv.z = __shfl(u[nb], 32 + col);
                 uv.w = __shfl(u[nb], 48 + col);
-                const unsigned k0 = __float_as_uint(l0[nb]), k1 = __float_as_uint(l1[nb]);
-                float bd = INFINITY;
-                int bi = INT32_MAX;
-                if (k0 != __float_as_uint(FLT_MAX)) {
-                    bd = dist4(uv, lcb[(size_t)m * ksub + (k0 & 0xFFu)]);
-                    bi = (int)(k0 & 0xFFu);
-                }
-                if (k1 != __float_as_uint(FLT_MAX)) {
-                    const float d = dist4(uv, lcb[(size_t)m * ksub + (k1 & 0xFFu)]);
-                    if (d < bd || (d == bd && (int)(k1 & 0xFFu) < bi)) {
-                        bd = d;
-                        bi = (int)(k1 & 0xFFu);
-                    }
-                }
-                float tau = __uint_as_float(k1 & ~0xFFu);
+                const unsigned k0 = l0[nb];
+                const int i0 = min((int)(k0 & 0xFFu), ksub - 1);
+                const float e0 = dist4(uv, cbv[i0]);
+                float bd = k0 != kNoKey ? e0 : INFINITY;
+                int bi = k0 != kNoKey ? i0 : INT32_MAX;
+                float tau = __uint_as_float(l1[nb] & ~0xFFu);
 #pragma unroll
                 for (int o = 16; o <= 32; o <<= 1) {
                     const float od = __shfl_xor(bd, o);
                     const int oi = __shfl_xor(bi, o);
-                    if (od < bd || (od == bd && oi < bi)) {
-                        bd = od;
-                        bi = oi;
-                    }
+                    const bool take = od < bd || (od == bd && oi < bi);
+                    bd = take ? od : bd;
+                    bi = take ? oi : bi;
                     tau = fminf(tau, __shfl_xor(tau, o));
                 }
-                // canonical ||u||^2 and the screen's error bound
-                float ucan = __fmul_rn(uv.x, uv.x);
-                ucan = __fadd_rn(ucan, __fmul_rn(uv.y, uv.y));
-                ucan = __fadd_rn(ucan, __fmul_rn(uv.z, uv.z));
-                ucan = __fadd_rn(ucan, __fmul_rn(uv.w, uv.w));
-                const double un = sqrt((double)ucan * (1.0 + g6));
-                const double bt = (double)beta;
-                const double E = 1.1 * g10 * (2.0 * (cm2 + bt) + 2.0 * un * sqrt(cm2)) + 1e-30;
-                const double L = ((double)tau - E - bt + (double)ucan * (1.0 - g6)) * (1.0 - g6);
-                int code = bi;
-                if (!((double)tau >= 1.0e38 || L > (double)bd)) {
-                    float best = INFINITY;
-                    code = 0;
-                    for (int b = 0; b < ksub; ++b) {
-                        const float d = dist4(uv, lcb[(size_t)m * ksub + b]);
-                        if (d < best) {
-                            best = d;
-                            code = b;
+                // every code no list kept has screen >= tau; L bounds its canonical distance from below
+                const double L = ((double)tau - E - bt + (double)sq[nb] * (1.0 - g6)) * (1.0 - g6);
+                code[nb] = bi;
+                if (!(bi != INT32_MAX && L > (double)bd)) fail |= 1u << nb;
+            }
+            if (__ballot(fail != 0u) != 0ull) {
+#pragma unroll
+                for (int nb = 0; nb < kENB; ++nb) {
+                    float4 uv;
+                    uv.x = __shfl(u[nb], col);
+                    uv.y = __shfl(u[nb], 16 + col);
+                    uv.z = __shfl(u[nb], 32 + col);
+                    uv.w = __shfl(u[nb], 48 + col);
+                    if ((fail >> nb) & 1u) {
+                        float best = INFINITY;
+                        int bc = 0;
+                        for (int b = 0; b < ksub; ++b) {
+                            const float d = dist4(uv, cbv[b]);
+                            if (d < best) {
+                                best = d;
+                                bc = b;
+                            }
                         }
+                        code[nb] = bc;
                     }
                 }
-                if (!vrow[nb]) code = 0;
+            }
+#pragma unroll
+            for (int nb = 0; nb < kENB; ++nb) {
+                const int cv = vrow[nb] ? code[nb] : 0;
                 const int64_t row = wbase + nb * 16 + col;
                 if constexpr (RESID) {
-                    word[nb] |= (uint32_t)code << (8 * (m & 3));
+                    word[nb] |= (uint32_t)cv << (8 * (m & 3));
                     if ((m & 3) == 3) {
                         if (g == 0 && row < n) reinterpret_cast<uint32_t*>(codes_rows + row * M)[m >> 2] = word[nb];
                         word[nb] = 0u;
                     }
                 } else {
-                    if (g == 0 && row < n) codes_sub[(int64_t)m * n + row] = (uint32_t)code;
+                    if (g == 0 && row < n) codes_sub[(int64_t)m * n + row] = (uint32_t)cv;
                 }
             }
         }
@@ -419,6 +476,9 @@ __global__ void __launch_bounds__(kEThreads) encode_screen(const float* __restri
 }
 
 bool g_attr_screen[2] = {false, false};
+
+// LDS of one encode_screen work-group: codebooks and norms of its 16 subspaces.
+size_t screen_lds(int ksub) { return (size_t)kEHalf * ksub * (kDsub + 1) * sizeof(float); }
 
 // off[b] = first sorted position with code >= b, b in [0, ksub]
 __global__ void code_offsets(const uint32_t* __restrict__ keys, int64_t n, int ksub, int64_t* __restrict__ off) {
@@ -526,10 +586,10 @@ extern "C" tac_status pq_encode(tac_ctx ctx, const float* x_d, const int32_t* as
                                         (int)kMaxCodebookLds));
             g_attr_screen[0] = true;
         }
-        const unsigned grid =
-            (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kERows - 1) / kERows, (int64_t)ctx->props_cu));
-        encode_screen<true><<<grid, kEThreads, lds, ctx->stream>>>(x_d, assign_d, C_d, K, n, normalize, codebooks_d,
-                                                                   ksub, codes_d, nullptr, rnorm_d);
+        const unsigned grid = 2u * (unsigned)std::max<int64_t>(
+                                       1, std::min<int64_t>((n + kERows - 1) / kERows, (int64_t)ctx->props_cu));
+        encode_screen<true><<<grid, kEThreads, screen_lds(ksub), ctx->stream>>>(
+            x_d, assign_d, C_d, K, n, normalize, codebooks_d, ksub, codes_d, nullptr, rnorm_d);
         TAC_LAUNCH_CHECK("encode_screen");
     } else {
         const unsigned grid =
@@ -581,10 +641,10 @@ extern "C" tac_status pq_train(tac_ctx ctx, const float* R_d, int64_t n, int32_t
     for (int it = 0; it < iters && n > 0; ++it) {
         TAC_HIP(hipMemcpyAsync(cur, codebooks_d, cb_bytes, hipMemcpyDeviceToDevice, s));
         if (ksub % 16 == 0) {
-            const unsigned sgrid =
-                (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kERows - 1) / kERows, (int64_t)ctx->props_cu));
-            encode_screen<false><<<sgrid, kEThreads, lds, s>>>(R_d, nullptr, nullptr, 0, n, 0, cur, ksub, nullptr,
-                                                               codes, nullptr);
+            const unsigned sgrid = 2u * (unsigned)std::max<int64_t>(
+                                            1, std::min<int64_t>((n + kERows - 1) / kERows, (int64_t)ctx->props_cu));
+            encode_screen<false><<<sgrid, kEThreads, screen_lds(ksub), s>>>(R_d, nullptr, nullptr, 0, n, 0, cur, ksub,
+                                                                             nullptr, codes, nullptr);
             TAC_LAUNCH_CHECK("encode_screen");
         } else {
             train_encode<<<grid, 512, lds, s>>>(R_d, n, cur, M, ksub, codes);

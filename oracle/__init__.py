@@ -35,3 +35,4 @@ __all__ = [
     "residuals", "pq_encode", "pq_train", "pq_decode", "dist32",
     "inverted_lists", "doc_layout", "decode_layout",
 ]
+from .refine import distance_tables, doc_block, maxsim_scores

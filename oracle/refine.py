@@ -25,6 +25,7 @@ Readings (where the paper is silent):
 * a document with no token, or whose tokens all carry a centroid id outside
   [0, K), scores -inf (the maximum over an empty set);
 * tokens whose centroid id is outside [0, K) are skipped;
+* a candidate id outside [0, D) names no document and scores NaN;
 * rho is indexed like the layout's tokens: token t of document d is entry
   doc_off[d] + t.
 
@@ -70,8 +71,12 @@ def maxsim_scores(Q, C, codebooks, layout, doc_off, rnorm, cand):
     M = np.asarray(codebooks).shape[0]
     nq = Q.shape[0]
     T = distance_tables(Q, codebooks)
+    D = len(doc_off) - 1
     out = np.empty(len(cand))
     for j, d in enumerate(np.asarray(cand).tolist()):
+        if not 0 <= d < D:
+            out[j] = np.nan
+            continue
         ids, codes = doc_block(layout, doc_off, d, M)
         keep = (ids >= 0) & (ids < K)
         ids, codes = ids[keep], codes[keep]

@@ -23,6 +23,10 @@ def test_hand_example():
     s = oracle.maxsim_scores(fx["Q"], fx["C"], np.asarray(fx["codebooks"], float),
                              np.asarray(fx["layout"], np.uint8), fx["doc_off"], fx["rnorm"], fx["cand"])
     assert s.tolist() == fx["scores"]
+    # candidate ids that name no document score NaN
+    s = oracle.maxsim_scores(fx["Q"], fx["C"], np.asarray(fx["codebooks"], float),
+                             np.asarray(fx["layout"], np.uint8), fx["doc_off"], fx["rnorm"], [4, -1, 0])
+    assert np.isnan(s[0]) and np.isnan(s[1]) and s[2] == 10.0
 
 
 def _problem(seed, dim=16, M=4, ksub=8, K=10, nq=5, D=12, maxlen=6, bad_ids=False):

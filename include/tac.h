@@ -254,6 +254,32 @@ tac_status tac_ivf_build(tac_ctx ctx, const int32_t* assign_d, const int32_t* do
 tac_status tac_doc_layout(tac_ctx ctx, const int32_t* assign_d, const uint8_t* codes_d, int32_t M,
                           const int64_t* doc_off_d, int64_t D, int64_t N, uint8_t* layout_d);
 
+/* Refine phase of retrieval (Sect. 2.3, "Refine Phase: PQ-Optimized MaxSim
+ * Computation"): the MaxSim score of each candidate document for its query,
+ *   S(q, d) = sum_i max_{t in d} <q_i, c_{a_t} + rho_t * u_t>,
+ * with u_t the concatenation of the codewords codebooks[m][code_{t,m}] (the
+ * decoded normalised residual, Sect. 2.1 "Residuals Compression").
+ *  Q_d         [B, nq, d] float32: B queries of nq tokens (1 <= nq <= 32, B <= 65535);
+ *  C_d         [K, d] float32 centroids; codebooks_d [M, ksub, d / M] float32
+ *              (d = 128, M = 32, 1 <= ksub <= 256);
+ *  layout_d    the document layout of tac_doc_layout for the same M (4-byte
+ *              aligned), doc_off_d [D + 1] int64 its token offsets (N tokens);
+ *  rnorm_d     [N] float32: rho of token t of document d is rnorm_d[doc_off_d[d] + t];
+ *  cand_d      [B, nc] int32: the candidate documents of each query (repeats allowed);
+ *  scores_d    [B, nc] float32 output, scores_d[b * nc + j] for cand_d[b * nc + j].
+ * Tokens whose centroid id is outside [0, K) are skipped; a document with no
+ * remaining token scores -inf; a candidate id outside [0, D) scores NaN;
+ * offsets outside [0, N] are clamped and codes at or above ksub read codeword
+ * ksub - 1, so malformed inputs never address memory outside the buffers.
+ * FP32 products and FP32 accumulation on the matrix cores, in a fixed order:
+ * repeated calls give identical scores.  The caller owns every buffer; no
+ * workspace.  Asynchronous; TAC_E_INVAL on bad sizes, NULL pointers or a
+ * misaligned layout. */
+tac_status tac_maxsim(tac_ctx ctx, const float* Q_d, int64_t B, int32_t nq, int32_t d, const float* C_d,
+                      int64_t K, const float* codebooks_d, int32_t M, int32_t ksub, const uint8_t* layout_d,
+                      const int64_t* doc_off_d, int64_t D, int64_t N, const float* rnorm_d,
+                      const int32_t* cand_d, int64_t nc, float* scores_d);
+
 #ifdef __cplusplus
 }
 #endif

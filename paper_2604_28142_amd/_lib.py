@@ -27,7 +27,7 @@ EXPORTS = ["tac_ctx_create", "tac_ctx_set_stream", "tac_ctx_destroy", "tac_last_
            "tac_budget_from_stats",
            "tac_init_centroids", "tac_assign", "tac_assign_stats", "tac_update", "tac_residuals", "pq_train",
            "pq_encode", "tac_ctx_enable_timing", "tac_kernel_ms", "tac_ctx_set_tuning", "tac_ctx_get_tuning",
-           "tac_ivf_build", "tac_doc_layout"]
+           "tac_ivf_build", "tac_doc_layout", "tac_maxsim"]
 TAC_SLOT_ASSIGN, TAC_SLOT_UPDATE, TAC_SLOT_ENCODE = 0, 1, 2
 
 
@@ -79,6 +79,8 @@ _SIGS = {
     "pq_encode": (C.c_int, [_P, _P, _P, _P, _I64, _I64, _I32, _P, _I32, _I32, C.c_int, _P, _P]),
     "tac_ivf_build": (C.c_int, [_P, _P, _P, _I64, _I64, _I64, _P, _P]),
     "tac_doc_layout": (C.c_int, [_P, _P, _P, _I32, _P, _I64, _I64, _P]),
+    "tac_maxsim": (C.c_int, [_P, _P, _I64, _I32, _I32, _P, _I64, _P, _I32, _I32, _P, _P, _I64, _I64, _P, _P,
+                             _I64, _P]),
 }
 
 _lib = None
@@ -309,3 +311,27 @@ def tac_doc_layout(ctx: Context, assign, codes, doc_off, layout):
     if assign.shape[0] != N or layout.numel() != N * (4 + M):
         raise ValueError("tac_doc_layout: inconsistent shapes")
     _check(load().tac_doc_layout(ctx.handle, _dptr(assign), _dptr(codes), M, _dptr(doc_off), D, N, _dptr(layout)))
+
+
+def tac_maxsim(ctx: Context, Q, C_cent, codebooks, layout, doc_off, rnorm, cand, scores):
+    """Refine phase (Sect. 2.3): MaxSim of every candidate document for its query.
+    Q float32 [B, nq, 128]; C_cent [K, 128]; codebooks [32, ksub, 4]; layout uint8 and
+    doc_off int64 [D + 1] from tac_doc_layout; rnorm float32 [N] in layout token order;
+    cand int32 [B, nc]; scores float32 [B, nc] (output)."""
+    B, nq, d = Q.shape
+    M, ksub, _ = codebooks.shape
+    D = doc_off.shape[0] - 1
+    N = rnorm.shape[0]
+    _check_dtype(Q, torch.float32, "Q")
+    _check_dtype(layout, torch.uint8, "layout")
+    _check_dtype(doc_off, torch.int64, "doc_off")
+    _check_dtype(rnorm, torch.float32, "rnorm")
+    _check_dtype(cand, torch.int32, "cand")
+    _check_dtype(scores, torch.float32, "scores")
+    if cand.dim() != 2 or cand.shape[0] != B or tuple(scores.shape) != tuple(cand.shape):
+        raise ValueError("tac_maxsim: cand and scores must be [B, nc]")
+    if layout.shape[0] < N * (4 + M):
+        raise ValueError("tac_maxsim: layout is smaller than N * (4 + M) bytes")
+    _check(load().tac_maxsim(ctx.handle, _dptr(Q), B, nq, d, _dptr(C_cent), C_cent.shape[0], _dptr(codebooks), M,
+                             ksub, _dptr(layout), _dptr(doc_off), D, N, _dptr(rnorm), _dptr(cand), cand.shape[1],
+                             _dptr(scores)))

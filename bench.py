@@ -204,9 +204,49 @@ def index_structures(ctx, idx, w, N):
         ms_lay.append(ev[1].elapsed_time(ev[2]))
     entries = int(list_off[-1].item())
     lay_bytes = 2.0 * N * (4 + M)
-    return {"documents": D, "list_entries": entries, "ivf_build_ms": float(np.median(ms_ivf)),
+    info = {"documents": D, "list_entries": entries, "ivf_build_ms": float(np.median(ms_ivf)),
             "doc_layout_ms": float(np.median(ms_lay)),
             "doc_layout_GBps": lay_bytes / (float(np.median(ms_lay)) / 1e3) / 1e9}
+    rnorm_in = torch.empty_like(idx.rnorm)
+    rnorm_in[perm] = idx.rnorm
+    return info, (layout, doc_off, rnorm_in)
+
+
+def refine(ctx, idx, w, index, nqueries=64, nq=32, ncand=1000):
+    """Refine-phase MaxSim (Sect. 2.3) of synthetic queries against the built
+    index: each of `nqueries` queries of `nq` tokens scores `ncand` candidate
+    documents drawn uniformly.  Timed with HIP events on the context's stream
+    (median of 5 calls).  Algorithmic work per scored document token: 552 bytes
+    from HBM (its centroid row, 36 layout bytes, its norm) and 2 * 128 * nq flops."""
+    import datagen
+    import torch
+    import paper_2604_28142_amd as tac
+    layout, doc_off, rnorm_in = index
+    dev = idx.xs.device
+    D = doc_off.shape[0] - 1
+    Q = torch.from_numpy(datagen.queries(w, nqueries, nq, seed=w.seed)).to(dev)
+    cand_h = datagen.refine_candidates(D, nqueries, ncand, seed=w.seed)
+    cand = torch.from_numpy(cand_h).to(dev)
+    scores = torch.empty(cand.shape, dtype=torch.float32, device=dev)
+    args = (ctx, Q, idx.C, idx.codebooks, layout, doc_off, rnorm_in, cand, scores)
+    tac.tac_maxsim(*args)
+    stream = ctx.stream
+    ms = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        tac.tac_maxsim(*args)
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    t = float(np.median(ms))
+    off_h = doc_off.cpu().numpy()
+    tokens = int((off_h[cand_h + 1] - off_h[cand_h]).sum())
+    return {"queries": nqueries, "query_tokens": nq, "candidates_per_query": ncand, "doc_tokens_scored": tokens,
+            "ms": t, "queries_per_s": nqueries / (t / 1e3), "docs_per_s": nqueries * ncand / (t / 1e3),
+            "GBps_algorithmic": tokens * 552 / (t / 1e3) / 1e9,
+            "TFLOPs_algorithmic": tokens * 2.0 * 128 * nq / (t / 1e3) / 1e12,
+            "finite_scores": bool(torch.isfinite(scores).all().item())}
 
 
 def main():
@@ -394,8 +434,11 @@ def main():
     if "fp32" in kms:
         extra["fp32_roofline_frac"] = F / (kms["fp32"] / 1e3) / 1e12 / PEAK["fp32"]
 
-    extra["index_structures"] = index_structures(ctx, idx, w, N)
+    extra["index_structures"], index = index_structures(ctx, idx, w, N)
     log(f"inverted lists + document layout: {extra['index_structures']}")
+    extra["refine"] = refine(ctx, idx, w, index)
+    log(f"refine (MaxSim over PQ codes): {extra['refine']}")
+    del index
 
     if args.global_baseline:
         extra["global_kmeans"] = global_baseline(ctx, idx, w, lloyd_med / args.iters, args.global_baseline)

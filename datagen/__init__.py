@@ -20,7 +20,8 @@ how many threads generate it.
 
 Streams: 0 token uniforms, 1 per-token means, 2 per-token sub-centres,
 3 vector noise, 4 initial-centroid picks, 5 PQ sample, 6 PQ initial rows,
-7 id permutation, 8 serving documents, 9 serving arrivals, 10 sub-centre pick.
+7 id permutation, 8 serving documents, 9 serving arrivals, 10 sub-centre pick
+and document lengths, 11 queries, 12 refine candidates.
 """
 from __future__ import annotations
 
@@ -213,3 +214,24 @@ def poisson_arrivals(rate: float, count: int, seed: int = 0) -> np.ndarray:
     """float64[count] arrival times (s) of a Poisson process of the given rate (stream 9)."""
     gaps = np.random.default_rng([seed, 9]).exponential(1.0 / rate, size=count)
     return np.cumsum(gaps)
+
+
+def queries(w: Workload | str, count: int, nq: int = 32, seed: int = 0) -> np.ndarray:
+    """float32[count, nq, 128]: query token vectors, token ids from the workload's
+    Zipf law and vectors around the same centres with fresh noise (stream 11).
+    nq = 32 is the fixed query length of ColBERTv2-style encoders."""
+    if isinstance(w, str):
+        w = WORKLOADS[w]
+    rng = np.random.default_rng([seed, 11])
+    cdf = zipf_cdf(w.vocab, w.zipf_s)
+    perm = id_permutation(w.vocab, w.seed)
+    tok = perm[np.searchsorted(cdf, rng.random(count * nq), side="right")].astype(np.int32)
+    cen = centres(w.vocab, w.subcentres, w.seed)
+    x = vectors(tok, cen, w.sigma, seed + 2000, noise_stream=11, pick_stream=11)
+    return x.reshape(count, nq, -1)
+
+
+def refine_candidates(D: int, count: int, per_query: int, seed: int = 0) -> np.ndarray:
+    """int32[count, per_query]: distinct document ids per query, uniformly drawn (stream 12)."""
+    rng = np.random.default_rng([seed, 12])
+    return np.stack([rng.choice(D, size=min(per_query, D), replace=False) for _ in range(count)]).astype(np.int32)

@@ -7,7 +7,8 @@
 // (M x 256 x 4 floats = 128 KiB) stay resident in LDS while a block encodes
 // its rows.  Training runs Lloyd per subspace: encode, stably sort the rows of
 // each subspace by code, and average every code's members in float64 in that
-// fixed order (codes with no member keep their value).
+// fixed order (codes with no member keep their value).  All subspaces are
+// sorted together, keyed by (subspace, code), which keeps that order.
 #include <algorithm>
 #include <cfloat>
 
@@ -480,27 +481,40 @@ bool g_attr_screen[2] = {false, false};
 // LDS of one encode_screen work-group: codebooks and norms of its 16 subspaces.
 size_t screen_lds(int ksub) { return (size_t)kEHalf * ksub * (kDsub + 1) * sizeof(float); }
 
-// off[b] = first sorted position with code >= b, b in [0, ksub]
-__global__ void code_offsets(const uint32_t* __restrict__ keys, int64_t n, int ksub, int64_t* __restrict__ off) {
+// off[t] = first sorted position with key >= t, t in [0, nkeys]
+__global__ void code_offsets(const uint32_t* __restrict__ keys, int64_t n, int nkeys, int64_t* __restrict__ off) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t prev = i == 0 ? -1 : (int64_t)keys[i - 1];
-        const int64_t cur = i == n ? ksub : (int64_t)keys[i];
+        const int64_t cur = i == n ? nkeys : (int64_t)keys[i];
         for (int64_t t = prev + 1; t <= cur; ++t) off[t] = i;
     }
 }
 
-// New code vectors of subspace m: one wavefront per code, lanes stride over its
-// members in sorted order, float64 partials combined by a fixed butterfly.
-__global__ void __launch_bounds__(256) code_means(const float* __restrict__ R, const int32_t* __restrict__ rows,
-                                                  const int64_t* __restrict__ off, int m, int ksub,
-                                                  const float* __restrict__ cb_old, float* __restrict__ cb_new) {
+// Training keys of subspaces m0 .. m0 + G - 1, in place over their m-major
+// codes: entry (m, row) becomes (m - m0) * ksub + code, so that one stable sort
+// orders every subspace's rows by code, ascending row within a code.
+__global__ void train_keys(uint32_t* __restrict__ codes, int64_t n, int G, int ksub) {
+    const int64_t total = (int64_t)G * n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+        codes[i] += (uint32_t)(i / n) * (uint32_t)ksub;
+}
+
+// New code vectors of subspaces m0 .. m0 + G - 1: one wavefront per (subspace,
+// code), lanes stride over its members in sorted order (the sorted values are
+// positions (m - m0) * n + row), float64 partials combined by a fixed butterfly.
+__global__ void __launch_bounds__(256) code_means(const float* __restrict__ R, const int32_t* __restrict__ pos,
+                                                  const int64_t* __restrict__ off, int64_t n, int m0, int G,
+                                                  int ksub, const float* __restrict__ cb_old,
+                                                  float* __restrict__ cb_new) {
     const int lane = threadIdx.x & 63;
-    const int b = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (b >= ksub) return;
-    const int64_t s = off[b], e = off[b + 1];
+    const int w = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (w >= G * ksub) return;
+    const int ml = w / ksub, b = w - ml * ksub, m = m0 + ml;
+    const int64_t s = off[w], e = off[w + 1];
+    const int64_t pbase = (int64_t)ml * n;
     double acc[kDsub] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t p = s + lane; p < e; p += 64) {
-        const float4 v = reinterpret_cast<const float4*>(R + (int64_t)rows[p] * kDim)[m];
+        const float4 v = reinterpret_cast<const float4*>(R + ((int64_t)pos[p] - pbase) * kDim)[m];
         acc[0] += (double)v.x;
         acc[1] += (double)v.y;
         acc[2] += (double)v.z;
@@ -612,12 +626,15 @@ extern "C" tac_status pq_train(tac_ctx ctx, const float* R_d, int64_t n, int32_t
     TAC_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     const size_t cb_bytes = (size_t)M * ksub * kDsub * sizeof(float);
+    // subspaces sorted together per batch: G * n sort positions must fit int32
+    const int G = (int)std::max<int64_t>(1, std::min<int64_t>(M, n > 0 ? (int64_t)INT32_MAX / n : M));
+    const int64_t gn = (int64_t)G * n;
     Carve cv;
     const size_t o_codes = cv.take<uint32_t>((int64_t)M * n + 1);
-    const size_t o_k1 = cv.take<uint32_t>(n + 1);
-    const size_t o_v0 = cv.take<int32_t>(n + 1), o_v1 = cv.take<int32_t>(n + 1);
-    const size_t o_sort = cv.take<char>(radix_sort_scratch_bytes(n));
-    const size_t o_off = cv.take<int64_t>(ksub + 1);
+    const size_t o_k1 = cv.take<uint32_t>(gn + 1);
+    const size_t o_v0 = cv.take<int32_t>(gn + 1), o_v1 = cv.take<int32_t>(gn + 1);
+    const size_t o_sort = cv.take<char>(radix_sort_scratch_bytes(gn));
+    const size_t o_off = cv.take<int64_t>((int64_t)G * ksub + 1);
     const size_t o_cb = cv.take<char>(cb_bytes);
     st = ws_reserve(ctx, cv.off);
     if (st != TAC_OK) return st;
@@ -650,15 +667,22 @@ extern "C" tac_status pq_train(tac_ctx ctx, const float* R_d, int64_t n, int32_t
             train_encode<<<grid, 512, lds, s>>>(R_d, n, cur, M, ksub, codes);
             TAC_LAUNCH_CHECK("train_encode");
         }
-        for (int m = 0; m < M; ++m) {
-            uint32_t* keys = codes + (int64_t)m * n;  // sorted in place (ping-pong with k1)
+        for (int m0 = 0; m0 < M; m0 += G) {
+            const int g = std::min(G, M - m0);
+            const int64_t tot = (int64_t)g * n;
+            const int nkeys = g * ksub;
+            int bits = 1;
+            while ((1 << bits) < nkeys) ++bits;
+            uint32_t* keys = codes + (int64_t)m0 * n;  // sorted in place (ping-pong with k1)
+            train_keys<<<grid_for(tot, 256), 256, 0, s>>>(keys, n, g, ksub);
+            TAC_LAUNCH_CHECK("train_keys");
             int in1 = 0;
-            st = radix_sort(s, n, 8, keys, v0, k1, v1, nullptr, ws_at<void>(ctx, o_sort), &in1);
+            st = radix_sort(s, tot, bits, keys, v0, k1, v1, nullptr, ws_at<void>(ctx, o_sort), &in1);
             if (st != TAC_OK) return st;
-            code_offsets<<<grid_for(n + 1, 256), 256, 0, s>>>(in1 ? k1 : keys, n, ksub, off);
+            code_offsets<<<grid_for(tot + 1, 256), 256, 0, s>>>(in1 ? k1 : keys, tot, nkeys, off);
             TAC_LAUNCH_CHECK("code_offsets");
-            code_means<<<(unsigned)((ksub * 64 + 255) / 256), 256, 0, s>>>(R_d, in1 ? v1 : v0, off, m, ksub, cur,
-                                                                          codebooks_d);
+            code_means<<<(unsigned)(((int64_t)nkeys * 64 + 255) / 256), 256, 0, s>>>(
+                R_d, in1 ? v1 : v0, off, n, m0, g, ksub, cur, codebooks_d);
             TAC_LAUNCH_CHECK("code_means");
         }
     }

@@ -130,9 +130,12 @@ def global_baseline(ctx, idx, w, tac_iter_ms: float, rows: int, seed: int = 0):
             "note": "one segment: a uniform row sample against all K centroids of the build, same BF16 kernels"}
 
 
+SERVE_RATES = (10_000.0, 25_000.0, 40_000.0)   # fixed Poisson arrival rates, documents per second
+
+
 def serve_bench(idx, w, requests: int, seed: int = 0):
     """Encode service against the resident index: saturated throughput, then
-    Poisson arrivals at 0.3 / 0.6 / 0.9 of it (first 5% of requests discarded)."""
+    Poisson arrivals at three fixed rates (first 5% of requests discarded)."""
     import datagen
     from paper_2604_28142_amd.serve import EncodeService, GpuExecutor, ResidentIndex, run_load
 
@@ -149,14 +152,14 @@ def serve_bench(idx, w, requests: int, seed: int = 0):
     log(f"serve: saturated {r_sat:.0f} docs/s")
     out = {"index": f"{w.name}: K={w.k} centroids, PQ 32x256", "requests_per_rate": requests,
            "docs_mean_vectors": float(lens.mean()), "saturated_docs_per_s": r_sat, "rates": []}
-    for f in (0.3, 0.6, 0.9):
-        rate = f * r_sat
-        arr = datagen.poisson_arrivals(rate, len(docs), seed=seed + int(f * 10))
+    for i, rate in enumerate(SERVE_RATES):
+        arr = datagen.poisson_arrivals(rate, len(docs), seed=seed + 3 * (i + 1))
         res, wall = run_load(svc, docs, arr)
         skip = len(docs) // 20
         lat = np.array([r.latency for r in res[skip:]])
         vec = float(lens[skip:].sum())
-        out["rates"].append({"docs_per_s": rate, "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+        out["rates"].append({"docs_per_s": rate, "fraction_of_saturation": rate / r_sat,
+                             "p50_ms": 1e3 * float(np.percentile(lat, 50)),
                              "p99_ms": 1e3 * float(np.percentile(lat, 99)),
                              "vectors_per_s": vec / (wall * (len(docs) - skip) / len(docs))})
         log(f"serve: rate {rate:.0f}/s p50 {out['rates'][-1]['p50_ms']:.2f} ms p99 {out['rates'][-1]['p99_ms']:.2f} ms")

@@ -22,6 +22,7 @@ from __future__ import annotations
 import queue
 import threading
 import time
+from collections import deque
 from concurrent.futures import Future
 from dataclasses import dataclass, field
 
@@ -111,13 +112,12 @@ class GpuExecutor:
         """Stage the rows of a batch into the slot's pinned buffers and enqueue
         copy-in, assignment, PQ encoding and copy-out on the slot's stream."""
         S = self.slots[slot]
-        n = 0
-        xh, th = S["x_h"].numpy(), S["tok_h"].numpy()
-        for x, t in zip(xs, toks):
-            k = x.shape[0]
-            xh[n:n + k] = x
-            th[n:n + k] = t
-            n += k
+        n = sum(x.shape[0] for x in xs)
+        if n > self.max_rows:
+            raise ValueError("batch exceeds the slot's staging rows")
+        if n:
+            np.concatenate(xs, axis=0, out=S["x_h"].numpy()[:n])
+            np.concatenate(toks, axis=0, out=S["tok_h"].numpy()[:n])
         torch, L, ix = self.torch, self.L, self.index
         with torch.cuda.stream(S["stream"]):
             S["x_d"][:n].copy_(S["x_h"][:n], non_blocking=True)
@@ -156,7 +156,7 @@ class EncodeService:
         self.idle_wait = idle_wait
         self.stats = ServiceStats()
         self._in = queue.Queue()
-        self._pending: list[Request] = []
+        self._pending: deque[Request] = deque()
         self._free = list(range(self.n_slots))
         self._inflight = queue.Queue()
         self._lock = threading.Condition()
@@ -228,7 +228,7 @@ class EncodeService:
                     b = k * ROW_BYTES
                     if rows + k > self.max_rows or self.ledger_used + nbytes + b > self.ledger_cap:
                         break
-                    batch.append(self._pending.pop(0))
+                    batch.append(self._pending.popleft())
                     rows += k
                     nbytes += b
                 if not batch:            # nothing fits until memory is released
@@ -250,30 +250,31 @@ class EncodeService:
             if item is None:
                 return
             slot, batch, n, nbytes, err = item
+            lens = np.fromiter((r.x.shape[0] for r in batch), dtype=np.int64, count=len(batch))
+            offs = np.zeros(len(batch) + 1, dtype=np.int64)
+            np.cumsum(lens, out=offs[1:])
             if err is None:
                 try:
-                    a, c, rho = self.ex.wait(slot, n)
+                    # one copy of the batch's outputs (the staging buffers are reused);
+                    # each document's result holds views into it
+                    a, c, rho = (np.array(v, copy=True) for v in self.ex.wait(slot, n))
+                    bad = np.minimum.reduceat(a, offs[:-1]) < 0 if len(batch) else np.zeros(0, bool)
                 except Exception as e:
                     err = e
             now = time.perf_counter()
-            off = 0
-            for r in batch:
-                k = r.x.shape[0]
+            for i, r in enumerate(batch):
                 r.t_done = now
                 if err is not None:
                     r.future.set_exception(err)
                     self.stats.failed += 1
+                elif bad[i]:
+                    r.future.set_exception(TacError(TAC_E_UNSEEN_TOKEN, "a token of this document has no centroid"))
+                    self.stats.failed += 1
                 else:
-                    ra = a[off:off + k].copy()
-                    if np.any(ra < 0):
-                        r.future.set_exception(TacError(TAC_E_UNSEEN_TOKEN,
-                                                        "a token of this document has no centroid"))
-                        self.stats.failed += 1
-                    else:
-                        r.future.set_result(Result(ra, c[off:off + k].copy(), rho[off:off + k].copy(),
-                                                   now - r.t_arrival))
-                        self.stats.latencies.append(now - r.t_arrival)
-                off += k
+                    o0, o1 = offs[i], offs[i + 1]
+                    r.future.set_result(Result(a[o0:o1], c[o0:o1], rho[o0:o1], now - r.t_arrival))
+                    self.stats.latencies.append(now - r.t_arrival)
+            off = int(offs[-1])
             self.stats.batches += 1
             self.stats.docs += len(batch)
             self.stats.vectors += off

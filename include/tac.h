@@ -254,6 +254,31 @@ tac_status tac_ivf_build(tac_ctx ctx, const int32_t* assign_d, const int32_t* do
 tac_status tac_doc_layout(tac_ctx ctx, const int32_t* assign_d, const uint8_t* codes_d, int32_t M,
                           const int64_t* doc_off_d, int64_t D, int64_t N, uint8_t* layout_d);
 
+/* Gather phase of retrieval (Sect. 2.3, "Gather Phase: Centroid-based
+ * Document Scoring"): for each of the B queries,
+ *  1. every query token q_i takes the kc centroids of largest <q_i, c_j>
+ *     (exactly: the paper's HNSW graph approximates this set; ties go to the
+ *     lower centroid id);
+ *  2. s_i(d) = the largest <q_i, c_j> over those centroids whose inverted list
+ *     holds document d;
+ *  3. S(q, d) = sum_i s_i(d) over the tokens that reach d;
+ * and returns the kd documents of largest S, ties to the lower document id.
+ *  Q_d         [B, nq, d] float32 (1 <= nq <= 1024), C_d [K, d] float32 (d = 128);
+ *  list_off_d  [K + 1] int64, list_docs_d [list_off_d[K]] int32: the inverted
+ *              lists of tac_ivf_build, document ids in [0, D);
+ *  cand_d      [B, kd] int32 and score_d [B, kd] float32 (output): documents by
+ *              S descending; unused slots hold (-1, -inf).
+ * 1 <= kc <= 256, 1 <= kd <= 4096.  Similarities are FP32 products with FP32
+ * accumulation on the matrix cores and S adds them in float64 in token order,
+ * so repeated calls give identical results.  The workspace holds at most 1 GiB
+ * of similarities plus 36 bytes per visited list entry.  Synchronous (the
+ * call returns after its work has completed on the context's stream); not for
+ * graph capture.  TAC_E_INVAL on bad sizes or NULL pointers; list offsets must
+ * be non-decreasing within list_docs_d. */
+tac_status tac_gather(tac_ctx ctx, const float* Q_d, int64_t B, int32_t nq, int32_t d, const float* C_d, int64_t K,
+                      const int64_t* list_off_d, const int32_t* list_docs_d, int64_t D, int32_t kc, int32_t kd,
+                      int32_t* cand_d, float* score_d);
+
 /* Refine phase of retrieval (Sect. 2.3, "Refine Phase: PQ-Optimized MaxSim
  * Computation"): the MaxSim score of each candidate document for its query,
  *   S(q, d) = sum_i max_{t in d} <q_i, c_{a_t} + rho_t * u_t>,

@@ -27,7 +27,7 @@ EXPORTS = ["tac_ctx_create", "tac_ctx_set_stream", "tac_ctx_destroy", "tac_last_
            "tac_budget_from_stats",
            "tac_init_centroids", "tac_assign", "tac_assign_stats", "tac_update", "tac_residuals", "pq_train",
            "pq_encode", "tac_ctx_enable_timing", "tac_kernel_ms", "tac_ctx_set_tuning", "tac_ctx_get_tuning",
-           "tac_ivf_build", "tac_doc_layout", "tac_maxsim"]
+           "tac_ivf_build", "tac_doc_layout", "tac_maxsim", "tac_gather"]
 TAC_SLOT_ASSIGN, TAC_SLOT_UPDATE, TAC_SLOT_ENCODE = 0, 1, 2
 
 
@@ -81,6 +81,7 @@ _SIGS = {
     "tac_doc_layout": (C.c_int, [_P, _P, _P, _I32, _P, _I64, _I64, _P]),
     "tac_maxsim": (C.c_int, [_P, _P, _I64, _I32, _I32, _P, _I64, _P, _I32, _I32, _P, _P, _I64, _I64, _P, _P,
                              _I64, _P]),
+    "tac_gather": (C.c_int, [_P, _P, _I64, _I32, _I32, _P, _I64, _P, _P, _I64, _I32, _I32, _P, _P]),
 }
 
 _lib = None
@@ -335,3 +336,21 @@ def tac_maxsim(ctx: Context, Q, C_cent, codebooks, layout, doc_off, rnorm, cand,
     _check(load().tac_maxsim(ctx.handle, _dptr(Q), B, nq, d, _dptr(C_cent), C_cent.shape[0], _dptr(codebooks), M,
                              ksub, _dptr(layout), _dptr(doc_off), D, N, _dptr(rnorm), _dptr(cand), cand.shape[1],
                              _dptr(scores)))
+
+
+def tac_gather(ctx: Context, Q, C_cent, list_off, list_docs, D: int, kc: int, cand, scores):
+    """Gather phase (Sect. 2.3): the kd = cand.shape[1] documents of largest centroid-level
+    score per query.  Q float32 [B, nq, 128]; C_cent [K, 128]; list_off int64 [K + 1] and
+    list_docs int32 from tac_ivf_build; cand int32 [B, kd] and scores float32 [B, kd] (output).
+    Synchronous."""
+    B, nq, d = Q.shape
+    K = C_cent.shape[0]
+    _check_dtype(Q, torch.float32, "Q")
+    _check_dtype(list_off, torch.int64, "list_off")
+    _check_dtype(list_docs, torch.int32, "list_docs")
+    _check_dtype(cand, torch.int32, "cand")
+    _check_dtype(scores, torch.float32, "scores")
+    if list_off.shape[0] != K + 1 or cand.dim() != 2 or cand.shape[0] != B or tuple(scores.shape) != tuple(cand.shape):
+        raise ValueError("tac_gather: inconsistent shapes")
+    _check(load().tac_gather(ctx.handle, _dptr(Q), B, nq, d, _dptr(C_cent), K, _dptr(list_off), _dptr(list_docs),
+                             D, kc, cand.shape[1], _dptr(cand), _dptr(scores)))

@@ -1,0 +1,511 @@
+// Gather phase of retrieval (Sect. 2.3, "Gather Phase: Centroid-based
+// Document Scoring"): for each query token the kappa_c centroids of largest
+// inner product, the documents of their inverted lists with the largest
+// similarity per (token, document), the sum over the query's tokens, and the
+// kappa_d documents of largest sum.
+//
+// The paper finds the centroids with an HNSW graph over them; on gfx950 the
+// exact set costs one dense product per query token, so it is computed:
+// * sim_kernel: <q, c> for a block of query tokens and every centroid on the
+//   matrix cores (v_mfma_f32_16x16x4f32), written to the workspace;
+// * topk_rows: one work-group per query token selects the kappa_c largest
+//   (ties to the lower centroid id) with a three-digit radix select on the
+//   order-preserving bit pattern of the similarity, then sorts them in LDS;
+// * the lists of the selected centroids expand into (query, document) keys
+//   carrying the token and the similarity (counts, a scan, emission), one
+//   stable radix sort groups them by (query, document) with the tokens in
+//   increasing order, and one thread per group takes the largest similarity
+//   of each token and adds them up in token order;
+// * topk_docs: one work-group per query selects the kappa_d documents of
+//   largest sum (ties to the lower document id) the same way.
+// Queries run in chunks so that the similarity matrix stays within 1 GiB.
+#include <algorithm>
+#include <cmath>
+
+#include "tac_internal.h"
+
+namespace tac {
+
+namespace {
+
+constexpr int kGDim = 128;
+constexpr int kSelThreads = 256;
+constexpr int kMaxKc = 256;
+constexpr int kMaxKd = 4096;
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+unsigned grid_for(int64_t work, int per_block) {
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (unsigned)g;
+}
+
+// Order-preserving key of a float (larger float, larger key); NaN ranks lowest.
+__device__ __forceinline__ uint32_t fkey(float f) {
+    if (f != f) return 0u;
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// ---- similarities: 64 query-token rows x 256 centroids per wave ----------------
+// Lane (g, col) supplies coordinates 16 i + 4 g + k of centroid k0 + col (A) and
+// of query row 16 rb + col (B); D[centroid 4 g + r][row col].
+__global__ void __launch_bounds__(256) sim_kernel(const float* __restrict__ Q, int64_t R,
+                                                  const float* __restrict__ C, int64_t K, float* __restrict__ S,
+                                                  int64_t ldS) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
+    const int64_t r0 = (int64_t)blockIdx.y * 64;
+    const int64_t kbase = ((int64_t)blockIdx.x * 4 + wave) * 256;
+    if (kbase >= K) return;
+    float qf[4][32];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        const int64_t row = r0 + 16 * rb + col;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (row < R) v = reinterpret_cast<const float4*>(Q + row * kGDim)[4 * i + g];
+            qf[rb][4 * i + 0] = v.x;
+            qf[rb][4 * i + 1] = v.y;
+            qf[rb][4 * i + 2] = v.z;
+            qf[rb][4 * i + 3] = v.w;
+        }
+    }
+    for (int t = 0; t < 16; ++t) {
+        const int64_t k0 = kbase + 16 * t;
+        if (k0 >= K) break;
+        const int64_t kr = k0 + col;
+        float cf[32];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (kr < K) v = reinterpret_cast<const float4*>(C + kr * kGDim)[4 * i + g];
+            cf[4 * i + 0] = v.x;
+            cf[4 * i + 1] = v.y;
+            cf[4 * i + 2] = v.z;
+            cf[4 * i + 3] = v.w;
+        }
+        f4 acc[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) acc[rb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 32; ++s)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(cf[s], qf[rb][s], acc[rb], 0, 0, 0);
+        const int64_t kk = k0 + 4 * g;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            const int64_t row = r0 + 16 * rb + col;
+            if (row >= R) continue;
+            float* dst = S + row * ldS + kk;
+            if (kk + 3 < K) {
+                *reinterpret_cast<float4*>(dst) = make_float4(acc[rb][0], acc[rb][1], acc[rb][2], acc[rb][3]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (kk + r < K) dst[r] = acc[rb][r];
+            }
+        }
+    }
+}
+
+// ---- exact top-k of one list in one work-group ---------------------------------
+struct SelShared {
+    unsigned hist[2048];
+    unsigned cnt_gt[kSelThreads];
+    unsigned cnt_eq[kSelThreads];
+    unsigned long long sortbuf[kMaxKd];
+    unsigned sel_digit, sel_above;
+};
+
+// The k largest (key, index) of n elements, larger key first and, among equal
+// keys, lower index first; GET(t) returns the key of element t.  Results (key,
+// index) land sorted in sh.sortbuf[0 .. min(k, n)) as ((~key) << 32) | index.
+// Returns min(k, n).  k <= kMaxKd.
+template <class GET>
+__device__ int select_topk(GET get, int64_t n, int k, SelShared& sh) {
+    const int tid = threadIdx.x;
+    const int kk = (int)std::min<int64_t>(k, n);
+    uint32_t prefix = 0u, pmask = 0u;
+    unsigned remaining = (unsigned)kk;  // elements still to take among those matching the prefix
+    if (kk > 0 && kk < n) {
+        const int shifts[3] = {21, 10, 0};
+        const int widths[3] = {11, 11, 10};
+        for (int dgt = 0; dgt < 3; ++dgt) {
+            const int sh_ = shifts[dgt];
+            const uint32_t dmask = (1u << widths[dgt]) - 1u;
+            for (int b = tid; b < 2048; b += kSelThreads) sh.hist[b] = 0u;
+            __syncthreads();
+            for (int64_t t = tid; t < n; t += kSelThreads) {
+                const uint32_t key = get(t);
+                if ((key & pmask) == prefix) atomicAdd(&sh.hist[(key >> sh_) & dmask], 1u);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                unsigned above = 0u;
+                int v = (int)dmask;
+                for (; v > 0; --v) {
+                    if (above + sh.hist[v] >= remaining) break;
+                    above += sh.hist[v];
+                }
+                sh.sel_digit = (unsigned)v;
+                sh.sel_above = above;
+            }
+            __syncthreads();
+            prefix |= sh.sel_digit << sh_;
+            pmask |= dmask << sh_;
+            remaining -= sh.sel_above;
+            __syncthreads();
+        }
+    }
+    // collect: every key above the threshold, then the lowest-index keys equal to it
+    const bool all = kk >= n;
+    const int64_t chunk = (n + kSelThreads - 1) / kSelThreads;
+    const int64_t t0 = std::min<int64_t>(n, tid * chunk), t1 = std::min<int64_t>(n, t0 + chunk);
+    unsigned ngt = 0u, neq = 0u;
+    for (int64_t t = t0; t < t1; ++t) {
+        const uint32_t key = get(t);
+        if (all || key > prefix) ++ngt;
+        else if (key == prefix) ++neq;
+    }
+    sh.cnt_gt[tid] = ngt;
+    sh.cnt_eq[tid] = neq;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned a = 0u, e = 0u;
+        for (int i = 0; i < kSelThreads; ++i) {
+            const unsigned x = sh.cnt_gt[i], y = sh.cnt_eq[i];
+            sh.cnt_gt[i] = a;
+            sh.cnt_eq[i] = e;
+            a += x;
+            e += y;
+        }
+        sh.sel_above = a;  // number of keys above the threshold
+    }
+    __syncthreads();
+    const unsigned nabove = sh.sel_above;
+    unsigned pg = sh.cnt_gt[tid], pe = sh.cnt_eq[tid];
+    for (int64_t t = t0; t < t1; ++t) {
+        const uint32_t key = get(t);
+        const unsigned long long packed = ((unsigned long long)(~key) << 32) | (unsigned long long)(uint32_t)t;
+        if (all || key > prefix) {
+            sh.sortbuf[pg++] = packed;
+        } else if (key == prefix) {
+            if (pe < remaining) sh.sortbuf[nabove + pe] = packed;
+            ++pe;
+        }
+    }
+    // pad to a power of two and sort ascending (bitonic)
+    int np2 = 1;
+    while (np2 < kk) np2 <<= 1;
+    for (int i = kk + tid; i < np2; i += kSelThreads) sh.sortbuf[i] = ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= np2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < np2; i += kSelThreads) {
+                const int p = i ^ stride;
+                if (p > i) {
+                    const bool up = (i & size) == 0;
+                    const unsigned long long a = sh.sortbuf[i], b = sh.sortbuf[p];
+                    if ((a > b) == up) {
+                        sh.sortbuf[i] = b;
+                        sh.sortbuf[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    return kk;
+}
+
+__device__ __forceinline__ float key_float(uint32_t key) {
+    const uint32_t u = (key & 0x80000000u) ? (key & 0x7FFFFFFFu) : ~key;
+    return __uint_as_float(u);
+}
+
+// kappa_c largest similarities of every query-token row
+__global__ void __launch_bounds__(kSelThreads) topk_rows(const float* __restrict__ S, int64_t ldS, int64_t K, int kc,
+                                                         int32_t* __restrict__ top_id, float* __restrict__ top_sim) {
+    __shared__ SelShared sh;
+    const int64_t row = blockIdx.x;
+    const float* s = S + row * ldS;
+    const int kk = select_topk([&](int64_t t) { return fkey(s[t]); }, K, kc, sh);
+    for (int r = threadIdx.x; r < kc; r += kSelThreads) {
+        const int64_t o = row * kc + r;
+        if (r < kk) {
+            const unsigned long long p = sh.sortbuf[r];
+            top_id[o] = (int32_t)(uint32_t)p;
+            top_sim[o] = key_float(~(uint32_t)(p >> 32));
+        } else {
+            top_id[o] = -1;
+            top_sim[o] = -INFINITY;
+        }
+    }
+}
+
+// entries (row, rank): the length of the selected centroid's list
+__global__ void emit_count(const int32_t* __restrict__ top_id, int64_t n, const int64_t* __restrict__ list_off,
+                           int64_t K, int64_t* __restrict__ cnt) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t j = top_id[e];
+        cnt[e] = (j >= 0 && j < K) ? std::max<int64_t>(0, list_off[j + 1] - list_off[j]) : 0;
+    }
+}
+
+// one wave per entry: its list's documents become keys q * D + d carrying (token, similarity)
+__global__ void emit_kernel(const int32_t* __restrict__ top_id, const float* __restrict__ top_sim, int64_t n, int kc,
+                            int nq, const int64_t* __restrict__ list_off, const int32_t* __restrict__ list_docs,
+                            int64_t K, int64_t D, const int64_t* __restrict__ eoff, uint32_t* __restrict__ keys,
+                            int32_t* __restrict__ tok, float* __restrict__ sim) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+    const uint32_t sentinel = (uint32_t)((n / kc / nq) * D);  // past every valid key of the chunk
+    for (int64_t e = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); e < n; e += waves) {
+        const int32_t j = top_id[e];
+        if (j < 0 || j >= K) continue;
+        const int64_t row = e / kc;
+        const int64_t q = row / nq;
+        const int i = (int)(row - q * nq);
+        const float s = top_sim[e];
+        const int64_t base = list_off[j], len = eoff[e + 1] - eoff[e];
+        for (int64_t t = lane; t < len; t += 64) {
+            const int64_t pos = eoff[e] + t;
+            const int32_t d = list_docs[base + t];
+            keys[pos] = (d >= 0 && d < D) ? (uint32_t)(q * D + d) : sentinel;
+            tok[pos] = i;
+            sim[pos] = s;
+        }
+    }
+}
+
+// group heads of the sorted keys (valid keys only)
+__global__ void seg_flags(const uint32_t* __restrict__ keys, int64_t n, uint32_t limit, int64_t* __restrict__ flag) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+        flag[p] = (keys[p] < limit && (p == 0 || keys[p] != keys[p - 1])) ? 1 : 0;
+}
+
+__global__ void seg_compact(const int64_t* __restrict__ flag, const int64_t* __restrict__ idx, int64_t n,
+                            int64_t* __restrict__ start) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+        if (flag[p]) start[idx[p]] = p;
+}
+
+// One thread per (query, document) group: the largest similarity of each token,
+// summed over the tokens in increasing order (the sort kept emission order).
+__global__ void seg_reduce(const uint32_t* __restrict__ keys, const int32_t* __restrict__ pos, int64_t n,
+                           const int32_t* __restrict__ tok, const float* __restrict__ sim,
+                           const int64_t* __restrict__ start, const int64_t* __restrict__ nseg_p,
+                           uint32_t* __restrict__ seg_key, float* __restrict__ seg_score) {
+    const int64_t nseg = *nseg_p;
+    for (int64_t sg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; sg < nseg;
+         sg += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p0 = start[sg];
+        const uint32_t key = keys[p0];
+        double sum = 0.0;
+        int cur = -1;
+        float mx = -INFINITY;
+        for (int64_t p = p0; p < n && keys[p] == key; ++p) {
+            const int32_t e = pos[p];
+            const int i = tok[e];
+            const float v = sim[e];
+            if (i != cur) {
+                if (cur >= 0) sum += (double)mx;
+                cur = i;
+                mx = v;
+            } else {
+                mx = fmaxf(mx, v);
+            }
+        }
+        if (cur >= 0) sum += (double)mx;
+        seg_key[sg] = key;
+        seg_score[sg] = (float)sum;
+    }
+}
+
+// qoff[q] = first group with key >= q * D, q in [0, QC]
+__global__ void seg_qoff(const uint32_t* __restrict__ seg_key, const int64_t* __restrict__ nseg_p, int64_t QC,
+                         int64_t D, int64_t* __restrict__ qoff) {
+    const int64_t nseg = *nseg_p;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q <= QC; q += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t target = (uint64_t)q * (uint64_t)D;
+        int64_t lo = 0, hi = nseg;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((uint64_t)seg_key[mid] < target) lo = mid + 1;
+            else hi = mid;
+        }
+        qoff[q] = lo;
+    }
+}
+
+// kappa_d documents of largest score per query (ties: lower id, which is the lower group index)
+__global__ void __launch_bounds__(kSelThreads) topk_docs(const uint32_t* __restrict__ seg_key,
+                                                         const float* __restrict__ seg_score,
+                                                         const int64_t* __restrict__ qoff, int64_t D, int kd,
+                                                         int32_t* __restrict__ out_doc, float* __restrict__ out_score) {
+    __shared__ SelShared sh;
+    const int64_t q = blockIdx.x;
+    const int64_t s0 = qoff[q], n = qoff[q + 1] - s0;
+    const int kk = select_topk([&](int64_t t) { return fkey(seg_score[s0 + t]); }, n, kd, sh);
+    for (int r = threadIdx.x; r < kd; r += kSelThreads) {
+        const int64_t o = q * kd + r;
+        if (r < kk) {
+            const unsigned long long p = sh.sortbuf[r];
+            const int64_t t = (int64_t)(uint32_t)p;
+            out_doc[o] = (int32_t)((int64_t)seg_key[s0 + t] - q * D);
+            out_score[o] = seg_score[s0 + t];
+        } else {
+            out_doc[o] = -1;
+            out_score[o] = -INFINITY;
+        }
+    }
+}
+
+int bits_for(uint64_t maxkey) {
+    int b = 1;
+    while (b < 32 && (uint64_t(1) << b) <= maxkey) ++b;
+    return b;
+}
+
+}  // namespace
+
+}  // namespace tac
+
+using namespace tac;
+
+extern "C" tac_status tac_gather(tac_ctx ctx, const float* Q_d, int64_t B, int32_t nq, int32_t d, const float* C_d,
+                                 int64_t K, const int64_t* list_off_d, const int32_t* list_docs_d, int64_t D,
+                                 int32_t kc, int32_t kd, int32_t* cand_d, float* score_d) {
+    if (!ctx) return set_error(TAC_E_INVAL, "tac_gather: ctx is NULL");
+    if (d != kGDim) return set_error(TAC_E_INVAL, "tac_gather: d must be 128");
+    if (B < 0 || nq < 1 || nq > 1024 || K < 1 || K > INT32_MAX || D < 1 || D > INT32_MAX)
+        return set_error(TAC_E_INVAL, "tac_gather: bad sizes");
+    if (kc < 1 || kc > kMaxKc) return set_error(TAC_E_INVAL, "tac_gather: kappa_c must be in [1, 256]");
+    if (kd < 1 || kd > kMaxKd) return set_error(TAC_E_INVAL, "tac_gather: kappa_d must be in [1, 4096]");
+    if (B == 0) return TAC_OK;
+    if (!Q_d || !C_d || !list_off_d || !list_docs_d || !cand_d || !score_d)
+        return set_error(TAC_E_INVAL, "tac_gather: NULL pointer");
+    TAC_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int64_t ldS = (K + 3) / 4 * 4;
+    // queries per chunk: the similarity matrix within 1 GiB, the keys q * D + d within 32 bits
+    int64_t QC = std::max<int64_t>(1, ((int64_t)1 << 30) / ((int64_t)nq * ldS * 4));
+    QC = std::min<int64_t>(QC, ((int64_t)UINT32_MAX - 1) / D);
+    QC = std::min<int64_t>(QC, B);
+    if (QC < 1) return set_error(TAC_E_INVAL, "tac_gather: too many documents for 32-bit keys");
+    size_t need_b = 0;  // size of the expansion stage seen so far
+    for (int64_t q0 = 0; q0 < B; q0 += QC) {
+        const int64_t qc = std::min<int64_t>(QC, B - q0);
+        const int64_t R = qc * nq;
+        const int64_t nent = R * kc;
+        // stage A: top lists and list-length scan, then the similarity matrix
+        Carve ca;
+        const size_t o_id = ca.take<int32_t>(nent), o_sim = ca.take<float>(nent);
+        const size_t o_eoff = ca.take<int64_t>(nent + 1);
+        const size_t o_scan = ca.take<char>(scan_scratch_bytes(nent));
+        const size_t base_b = ca.off;
+        const size_t o_S = ca.take<float>(R * ldS);
+        tac_status st = ws_reserve(ctx, std::max(ca.off, need_b));
+        if (st != TAC_OK) return st;
+        int64_t E = 0;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            int32_t* top_id = ws_at<int32_t>(ctx, o_id);
+            float* top_sim = ws_at<float>(ctx, o_sim);
+            int64_t* eoff = ws_at<int64_t>(ctx, o_eoff);
+            float* S = ws_at<float>(ctx, o_S);
+            const dim3 sg((unsigned)((K + 1023) / 1024), (unsigned)((R + 63) / 64));
+            if (sg.y > 65535) return set_error(TAC_E_INVAL, "tac_gather: too many query tokens per chunk");
+            sim_kernel<<<sg, 256, 0, s>>>(Q_d + q0 * nq * kGDim, R, C_d, K, S, ldS);
+            TAC_LAUNCH_CHECK("sim_kernel");
+            topk_rows<<<(unsigned)R, kSelThreads, 0, s>>>(S, ldS, K, kc, top_id, top_sim);
+            TAC_LAUNCH_CHECK("topk_rows");
+            emit_count<<<grid_for(nent, 256), 256, 0, s>>>(top_id, nent, list_off_d, K, eoff);
+            TAC_LAUNCH_CHECK("emit_count");
+            st = exclusive_scan_i64(s, eoff, eoff, nent, ws_at<void>(ctx, o_scan));
+            if (st != TAC_OK) return st;
+            TAC_HIP(hipMemcpyAsync(&E, eoff + nent, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            TAC_HIP(hipStreamSynchronize(s));
+            // stage B sizes (it reuses the similarity matrix's memory)
+            Carve cb;
+            cb.off = base_b;
+            const int64_t En = std::max<int64_t>(E, 1);
+            cb.take<uint32_t>(En);
+            cb.take<uint32_t>(En);
+            cb.take<int32_t>(En);
+            cb.take<int32_t>(En);
+            cb.take<int32_t>(En);
+            cb.take<float>(En);
+            cb.take<char>(radix_sort_scratch_bytes(En));
+            cb.take<int64_t>(En + 1);
+            cb.take<int64_t>(En + 1);
+            cb.take<char>(scan_scratch_bytes(En + 1));
+            cb.take<int64_t>(En + 1);
+            cb.take<uint32_t>(En);
+            cb.take<float>(En);
+            cb.take<int64_t>(qc + 1);
+            need_b = std::max(need_b, cb.off);
+            if (need_b <= ctx->ws_cap) break;
+            // the workspace must grow, which drops its contents: grow, then redo stage A
+            st = ws_reserve(ctx, std::max(ca.off, need_b));
+            if (st != TAC_OK) return st;
+        }
+        int32_t* top_id = ws_at<int32_t>(ctx, o_id);
+        float* top_sim = ws_at<float>(ctx, o_sim);
+        int64_t* eoff = ws_at<int64_t>(ctx, o_eoff);
+        int32_t* cand = cand_d + q0 * kd;
+        float* score = score_d + q0 * kd;
+        if (E == 0) {
+            Carve cq;
+            cq.off = base_b;
+            int64_t* qoff = ws_at<int64_t>(ctx, cq.take<int64_t>(qc + 1));
+            TAC_HIP(hipMemsetAsync(qoff, 0, (qc + 1) * sizeof(int64_t), s));
+            topk_docs<<<(unsigned)qc, kSelThreads, 0, s>>>(nullptr, nullptr, qoff, D, kd, cand, score);
+            TAC_LAUNCH_CHECK("topk_docs");
+            continue;
+        }
+        Carve cb;
+        cb.off = base_b;
+        uint32_t* keys = ws_at<uint32_t>(ctx, cb.take<uint32_t>(E));
+        uint32_t* k1 = ws_at<uint32_t>(ctx, cb.take<uint32_t>(E));
+        int32_t* v0 = ws_at<int32_t>(ctx, cb.take<int32_t>(E));
+        int32_t* v1 = ws_at<int32_t>(ctx, cb.take<int32_t>(E));
+        int32_t* tok = ws_at<int32_t>(ctx, cb.take<int32_t>(E));
+        float* simv = ws_at<float>(ctx, cb.take<float>(E));
+        void* sort_scr = ws_at<void>(ctx, cb.take<char>(radix_sort_scratch_bytes(E)));
+        int64_t* flag = ws_at<int64_t>(ctx, cb.take<int64_t>(E + 1));
+        int64_t* fidx = ws_at<int64_t>(ctx, cb.take<int64_t>(E + 1));
+        void* scan2 = ws_at<void>(ctx, cb.take<char>(scan_scratch_bytes(E + 1)));
+        int64_t* start = ws_at<int64_t>(ctx, cb.take<int64_t>(E + 1));
+        uint32_t* seg_key = ws_at<uint32_t>(ctx, cb.take<uint32_t>(E));
+        float* seg_score = ws_at<float>(ctx, cb.take<float>(E));
+        int64_t* qoff = ws_at<int64_t>(ctx, cb.take<int64_t>(qc + 1));
+        {
+            const int waves_per_block = 4;
+            emit_kernel<<<grid_for(nent, waves_per_block), 64 * waves_per_block, 0, s>>>(
+                top_id, top_sim, nent, kc, nq, list_off_d, list_docs_d, K, D, eoff, keys, tok, simv);
+            TAC_LAUNCH_CHECK("emit_kernel");
+        }
+        const uint32_t limit = (uint32_t)(qc * D);
+        int in1 = 0;
+        st = radix_sort(s, E, bits_for(limit), keys, v0, k1, v1, nullptr, sort_scr, &in1);
+        if (st != TAC_OK) return st;
+        const uint32_t* sk = in1 ? k1 : keys;
+        const int32_t* sv = in1 ? v1 : v0;
+        seg_flags<<<grid_for(E, 256), 256, 0, s>>>(sk, E, limit, flag);
+        TAC_LAUNCH_CHECK("seg_flags");
+        st = exclusive_scan_i64(s, flag, fidx, E, scan2);  // fidx[E] = number of groups
+        if (st != TAC_OK) return st;
+        seg_compact<<<grid_for(E, 256), 256, 0, s>>>(flag, fidx, E, start);
+        TAC_LAUNCH_CHECK("seg_compact");
+        seg_reduce<<<grid_for(E, 256), 256, 0, s>>>(sk, sv, E, tok, simv, start, fidx + E, seg_key, seg_score);
+        TAC_LAUNCH_CHECK("seg_reduce");
+        seg_qoff<<<grid_for(qc + 1, 256), 256, 0, s>>>(seg_key, fidx + E, qc, D, qoff);
+        TAC_LAUNCH_CHECK("seg_qoff");
+        topk_docs<<<(unsigned)qc, kSelThreads, 0, s>>>(seg_key, seg_score, qoff, D, kd, cand, score);
+        TAC_LAUNCH_CHECK("topk_docs");
+    }
+    return TAC_OK;
+}

@@ -13,13 +13,16 @@
  *    context's device); pointers ending in _h are host pointers.  Arrays are
  *    dense and row-major; vectors are float32 rows of d = 128 values.
  *  - The caller owns every input and output buffer.  The context owns only its
- *    workspace, which grows on demand up to max_workspace_bytes and is freed
- *    by tac_ctx_destroy.  No call keeps a caller pointer after it returns.
- *  - Every call except tac_budget, tac_init_centroids and tac_assign_stats only
- *    enqueues work on the context's HIP stream and returns; the caller keeps
- *    buffers alive until that stream has finished the work.  These calls may
- *    be captured into a HIP graph once one eager call of the same sizes has
- *    grown the workspace (growth is refused during capture).
+ *    workspace, which grows on demand.  A workspace that has to grow is
+ *    replaced, and the replaced allocation stays until tac_ctx_destroy, so a
+ *    HIP graph captured earlier keeps addressing valid memory; every
+ *    allocation the context holds counts towards max_workspace_bytes.  No
+ *    call keeps a caller pointer after it returns.
+ *  - Every call except tac_budget, tac_init_centroids, tac_assign_stats and
+ *    tac_gather only enqueues work on the context's HIP stream and returns;
+ *    the caller keeps buffers alive until that stream has finished the work.
+ *    These calls may be captured into a HIP graph once one eager call of the
+ *    same sizes has grown the workspace (growth is refused during capture).
  *  - Arguments are checked on the host before anything is launched; on any
  *    error nothing is enqueued and the call returns a negative status, with a
  *    message in tac_last_error().  No call aborts or throws.
@@ -87,7 +90,8 @@ typedef struct {
 } tac_assign_counters;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
- * (a hipStream_t; NULL = the device's null stream).  The workspace may grow to
+ * (a hipStream_t; NULL = the device's null stream).  The context's device
+ * allocations (current and replaced workspaces) stay within
  * max_workspace_bytes (0 = no limit).  On success *out holds the context. */
 tac_status tac_ctx_create(int device, void* hip_stream, size_t max_workspace_bytes, tac_ctx* out);
 

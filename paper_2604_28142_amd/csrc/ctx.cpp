@@ -25,9 +25,11 @@ tac_status hip_error(hipError_t e, const char* what) {
 
 tac_status ws_reserve(tac_ctx ctx, size_t bytes) {
     if (bytes <= ctx->ws_cap) return TAC_OK;
-    if (ctx->max_ws && bytes > ctx->max_ws)
-        return set_error(TAC_E_NOMEM, "workspace of " + std::to_string(bytes) +
-                                          " bytes exceeds the context limit of " +
+    // the limit bounds every allocation the context holds, replaced workspaces included
+    const size_t held = ctx->ws_retired_bytes + ctx->ws_cap;
+    if (ctx->max_ws && held + bytes > ctx->max_ws)
+        return set_error(TAC_E_NOMEM, "workspace of " + std::to_string(bytes) + " bytes (with " +
+                                          std::to_string(held) + " bytes already held) exceeds the context limit of " +
                                           std::to_string(ctx->max_ws));
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     TAC_HIP(hipStreamIsCapturing(ctx->stream, &cs));
@@ -37,10 +39,12 @@ tac_status ws_reserve(tac_ctx ctx, size_t bytes) {
                                           "run one eager call of the same sizes first");
     // round up to limit regrowth
     size_t cap = bytes + bytes / 8 + (size_t(1) << 20);
-    if (ctx->max_ws && cap > ctx->max_ws) cap = ctx->max_ws;
+    if (ctx->max_ws && held + cap > ctx->max_ws) cap = ctx->max_ws - held;
     TAC_HIP(hipStreamSynchronize(ctx->stream));
     if (ctx->ws) {
-        TAC_HIP(hipFree(ctx->ws));
+        // not freed: a graph captured on this context may still address it
+        ctx->ws_retired.push_back(ctx->ws);
+        ctx->ws_retired_bytes += ctx->ws_cap;
         ctx->ws = nullptr;
         ctx->ws_cap = 0;
     }
@@ -144,6 +148,7 @@ extern "C" void tac_ctx_destroy(tac_ctx ctx) {
         for (int k = 0; k < 2; ++k)
             if (ctx->ev[s][k]) (void)hipEventDestroy(ctx->ev[s][k]);
     if (ctx->ws) (void)hipFree(ctx->ws);
+    for (void* p : ctx->ws_retired) (void)hipFree(p);
     if (ctx->counters) (void)hipFree(ctx->counters);
     delete ctx;
 }

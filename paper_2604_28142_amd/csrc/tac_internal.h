@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "tac.h"
 
@@ -51,6 +52,10 @@ struct tac_ctx_s {
     size_t max_ws = 0;
     void* ws = nullptr;
     size_t ws_cap = 0;
+    // workspaces replaced by a larger one: kept until the context is destroyed,
+    // because HIP graphs captured earlier still address them
+    std::vector<void*> ws_retired;
+    size_t ws_retired_bytes = 0;
     // per-context device counters of the last tac_assign (rows, screened, fallback, unassigned)
     unsigned long long* counters = nullptr;
     int props_cu = 256;

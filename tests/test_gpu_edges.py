@@ -226,6 +226,40 @@ def test_graph_replay_equals_eager(ctx):
         run_assign(ctx, c.xs, c.seg_off, c.C0, c.cent_off, tac.TAC_FP32)
 
 
+def test_graph_survives_workspace_growth():
+    """A Lloyd graph captured on a context stays valid after a later call on the
+    same context (PQ training on a larger sample) grows the workspace: the
+    replaced workspace is kept until the context is destroyed."""
+    from paper_2604_28142_amd import index as IX
+    ctx2 = tac.Context(0)
+    try:
+        c = Case("small")
+        d = c.device()
+        ix = IX.Index(T=c.T, K=c.K, xs=d["xs"], perm=dev(c.perm.astype(np.int32)), seg_off=d["seg_off"],
+                      cent_off=d["cent_off"], C=dev(c.C0))
+        C0 = ix.C.clone()
+        loop = IX.LloydLoop(ctx2, ix, iters=3, precision=tac.TAC_BF16)
+        loop.run()
+        torch.cuda.synchronize()
+        C_eager, a_eager = ix.C.clone(), loop.assign.clone()
+        ix.C.copy_(C0)
+        loop.capture()
+        rng = np.random.default_rng(70)
+        R = dev((0.1 * rng.standard_normal((300_000, 128))).astype(np.float32))
+        init = R[:256].reshape(256, 32, 4).transpose(0, 1).contiguous()
+        cb = torch.empty((32, 256, 4), dtype=torch.float32, device="cuda")
+        tac.pq_train(ctx2, R, init, cb, iters=1)         # needs far more workspace than the graph's calls
+        torch.cuda.synchronize()
+        for rep in range(2):
+            ix.C.copy_(C0)
+            loop.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(ix.C, C_eager), rep
+            assert torch.equal(loop.assign, a_eager), rep
+    finally:
+        ctx2.close()
+
+
 @pytest.mark.parametrize("tuning", [dict(direct_max_kappa=0, heavy_kappa=1, groups_per_cu=1),
                                     dict(direct_max_kappa=16, heavy_kappa=64, groups_per_cu=0)])
 def test_tuning_keeps_results(ctx, tuning):

@@ -21,7 +21,7 @@ how many threads generate it.
 Streams: 0 token uniforms, 1 per-token means, 2 per-token sub-centres,
 3 vector noise, 4 initial-centroid picks, 5 PQ sample, 6 PQ initial rows,
 7 id permutation, 8 serving documents, 9 serving arrivals, 10 sub-centre pick
-and document lengths, 11 queries, 12 refine candidates.
+and document lengths, 11 queries.
 """
 from __future__ import annotations
 
@@ -230,8 +230,3 @@ def queries(w: Workload | str, count: int, nq: int = 32, seed: int = 0) -> np.nd
     x = vectors(tok, cen, w.sigma, seed + 2000, noise_stream=11, pick_stream=11)
     return x.reshape(count, nq, -1)
 
-
-def refine_candidates(D: int, count: int, per_query: int, seed: int = 0) -> np.ndarray:
-    """int32[count, per_query]: distinct document ids per query, uniformly drawn (stream 12)."""
-    rng = np.random.default_rng([seed, 12])
-    return np.stack([rng.choice(D, size=min(per_query, D), replace=False) for _ in range(count)]).astype(np.int32)

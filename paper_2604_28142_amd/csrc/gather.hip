@@ -9,8 +9,10 @@
 // * sim_kernel: <q, c> for a block of query tokens and every centroid on the
 //   matrix cores (v_mfma_f32_16x16x4f32), written to the workspace;
 // * topk_rows: one work-group per query token selects the kappa_c largest
-//   (ties to the lower centroid id) with a three-digit radix select on the
-//   order-preserving bit pattern of the similarity, then sorts them in LDS;
+//   (ties to the lower centroid id): the kappa_c-th largest of 1024 block
+//   maxima bounds the cut from below, the few similarities above that bound
+//   are sorted in LDS (a three-digit radix select on the order-preserving bit
+//   pattern of the similarity when too many reach it);
 // * the lists of the selected centroids expand into (query, document) keys
 //   carrying the token and the similarity (counts, a scan, emission), one
 //   stable radix sort groups them by (query, document) with the tokens in
@@ -221,6 +223,92 @@ __device__ int select_topk(GET get, int64_t n, int k, SelShared& sh) {
     return kk;
 }
 
+// Ascending bitonic sort of np2 (a power of two, <= 2048) 32-bit keys in LDS.
+__device__ void bitonic_u32(unsigned* a, int np2) {
+    const int tid = threadIdx.x;
+    for (int size = 2; size <= np2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < np2; i += kSelThreads) {
+                const int p = i ^ stride;
+                if (p > i) {
+                    const bool up = (i & size) == 0;
+                    const unsigned x = a[i], y = a[p];
+                    if ((x > y) == up) {
+                        a[i] = y;
+                        a[p] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// The same selection for small k out of many elements.  The maxima of 1024
+// blocks of the list (block b holds the elements t with t mod 1024 = b, so
+// that every pass reads the list coalesced) give a lower bound for the k-th
+// largest key (the k-th largest block maximum: at least k elements reach it),
+// every element at or above that bound is collected, and the candidates are
+// sorted like select_topk's.  When more candidates than the sort buffer holds
+// reach the bound, select_topk runs instead.  The candidate set, and so the
+// result, does not depend on the order of the collection.  n >= 1024.
+template <class GET>
+__device__ int select_topk_blocks(GET get, int64_t n, int k, SelShared& sh) {
+    constexpr int kBlocks = 1024;
+    static_assert(kBlocks % kSelThreads == 0, "each thread owns whole blocks");
+    constexpr int kPer = kBlocks / kSelThreads;  // blocks per thread: tid + kSelThreads * q
+    const int tid = threadIdx.x;
+    uint32_t mx[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) mx[q] = 0u;
+    for (int64_t j = 0; tid + j * kSelThreads < n; ++j) {
+        const uint32_t key = get(tid + j * kSelThreads);
+        const int q = (int)(j % kPer);
+#pragma unroll
+        for (int r = 0; r < kPer; ++r)
+            if (r == q) mx[r] = max(mx[r], key);
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) sh.hist[tid + kSelThreads * q] = mx[q];
+    if (tid == 0) sh.sel_above = 0u;
+    __syncthreads();
+    bitonic_u32(sh.hist, kBlocks);
+    const uint32_t bound = sh.hist[kBlocks - k];  // k-th largest block maximum
+    for (int64_t t = tid; t < n; t += kSelThreads) {
+        const uint32_t key = get(t);
+        if (key >= bound) {
+            const unsigned slot = atomicAdd(&sh.sel_above, 1u);
+            if (slot < (unsigned)kMaxKd)
+                sh.sortbuf[slot] = ((unsigned long long)(~key) << 32) | (unsigned long long)(uint32_t)t;
+        }
+    }
+    __syncthreads();
+    const unsigned nc = sh.sel_above;
+    __syncthreads();
+    if (nc > (unsigned)kMaxKd) return select_topk(get, n, k, sh);
+    int np2 = 1;
+    while (np2 < (int)nc) np2 <<= 1;
+    for (int i = (int)nc + tid; i < np2; i += kSelThreads) sh.sortbuf[i] = ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= np2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < np2; i += kSelThreads) {
+                const int p = i ^ stride;
+                if (p > i) {
+                    const bool up = (i & size) == 0;
+                    const unsigned long long a = sh.sortbuf[i], b = sh.sortbuf[p];
+                    if ((a > b) == up) {
+                        sh.sortbuf[i] = b;
+                        sh.sortbuf[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    return k;
+}
+
 __device__ __forceinline__ float key_float(uint32_t key) {
     const uint32_t u = (key & 0x80000000u) ? (key & 0x7FFFFFFFu) : ~key;
     return __uint_as_float(u);
@@ -232,7 +320,9 @@ __global__ void __launch_bounds__(kSelThreads) topk_rows(const float* __restrict
     __shared__ SelShared sh;
     const int64_t row = blockIdx.x;
     const float* s = S + row * ldS;
-    const int kk = select_topk([&](int64_t t) { return fkey(s[t]); }, K, kc, sh);
+    auto get = [&](int64_t t) { return fkey(s[t]); };
+    // the block bound needs at least kc non-empty blocks
+    const int kk = (K >= 4 * 1024 && kc <= 256) ? select_topk_blocks(get, K, kc, sh) : select_topk(get, K, kc, sh);
     for (int r = threadIdx.x; r < kc; r += kSelThreads) {
         const int64_t o = row * kc + r;
         if (r < kk) {

@@ -244,43 +244,52 @@ __device__ void bitonic_u32(unsigned* a, int np2) {
     }
 }
 
-// The same selection for small k out of many elements.  The maxima of 1024
-// blocks of the list (block b holds the elements t with t mod 1024 = b, so
-// that every pass reads the list coalesced) give a lower bound for the k-th
-// largest key (the k-th largest block maximum: at least k elements reach it),
-// every element at or above that bound is collected, and the candidates are
-// sorted like select_topk's.  When more candidates than the sort buffer holds
-// reach the bound, select_topk runs instead.  The candidate set, and so the
-// result, does not depend on the order of the collection.  n >= 1024.
+// The same selection for small k out of a long float row.  The maxima of
+// 1024 blocks of the row (block b holds the elements t with t mod 1024 = b,
+// so that thread i owns blocks 4 i .. 4 i + 3 and both passes read the row
+// coalesced, four elements per load) give a lower bound for the k-th largest
+// key (the k-th largest block maximum: at least k elements reach it), every
+// element at or above that bound is collected, and the candidates are sorted
+// like select_topk's.  When more candidates than the sort buffer holds reach
+// the bound, select_topk runs instead.  The candidate set, and so the result,
+// does not depend on the order of the collection.  n >= 1024, n % 4 == 0, row
+// 16-byte aligned.
 template <class GET>
-__device__ int select_topk_blocks(GET get, int64_t n, int k, SelShared& sh) {
+__device__ int select_topk_blocks(const float* __restrict__ row, GET get, int64_t n, int k, SelShared& sh) {
     constexpr int kBlocks = 1024;
-    static_assert(kBlocks % kSelThreads == 0, "each thread owns whole blocks");
-    constexpr int kPer = kBlocks / kSelThreads;  // blocks per thread: tid + kSelThreads * q
+    static_assert(kBlocks == 4 * kSelThreads, "each thread owns four blocks");
     const int tid = threadIdx.x;
-    uint32_t mx[kPer];
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) mx[q] = 0u;
-    for (int64_t j = 0; tid + j * kSelThreads < n; ++j) {
-        const uint32_t key = get(tid + j * kSelThreads);
-        const int q = (int)(j % kPer);
-#pragma unroll
-        for (int r = 0; r < kPer; ++r)
-            if (r == q) mx[r] = max(mx[r], key);
+    const float4* r4 = reinterpret_cast<const float4*>(row);
+    const int64_t n4 = n / 4;
+    uint32_t m0 = 0u, m1 = 0u, m2 = 0u, m3 = 0u;
+    for (int64_t v = tid; v < n4; v += kSelThreads) {
+        const float4 x = r4[v];
+        m0 = max(m0, fkey(x.x));
+        m1 = max(m1, fkey(x.y));
+        m2 = max(m2, fkey(x.z));
+        m3 = max(m3, fkey(x.w));
     }
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) sh.hist[tid + kSelThreads * q] = mx[q];
+    sh.hist[4 * tid + 0] = m0;
+    sh.hist[4 * tid + 1] = m1;
+    sh.hist[4 * tid + 2] = m2;
+    sh.hist[4 * tid + 3] = m3;
     if (tid == 0) sh.sel_above = 0u;
     __syncthreads();
     bitonic_u32(sh.hist, kBlocks);
     const uint32_t bound = sh.hist[kBlocks - k];  // k-th largest block maximum
-    for (int64_t t = tid; t < n; t += kSelThreads) {
-        const uint32_t key = get(t);
+    auto take = [&](uint32_t key, int64_t t) {
         if (key >= bound) {
             const unsigned slot = atomicAdd(&sh.sel_above, 1u);
             if (slot < (unsigned)kMaxKd)
                 sh.sortbuf[slot] = ((unsigned long long)(~key) << 32) | (unsigned long long)(uint32_t)t;
         }
+    };
+    for (int64_t v = tid; v < n4; v += kSelThreads) {
+        const float4 x = r4[v];
+        take(fkey(x.x), 4 * v + 0);
+        take(fkey(x.y), 4 * v + 1);
+        take(fkey(x.z), 4 * v + 2);
+        take(fkey(x.w), 4 * v + 3);
     }
     __syncthreads();
     const unsigned nc = sh.sel_above;
@@ -322,7 +331,8 @@ __global__ void __launch_bounds__(kSelThreads) topk_rows(const float* __restrict
     const float* s = S + row * ldS;
     auto get = [&](int64_t t) { return fkey(s[t]); };
     // the block bound needs at least kc non-empty blocks
-    const int kk = (K >= 4 * 1024 && kc <= 256) ? select_topk_blocks(get, K, kc, sh) : select_topk(get, K, kc, sh);
+    const int kk = (K >= 4 * 1024 && K % 4 == 0 && ldS % 4 == 0 && kc <= 256) ? select_topk_blocks(s, get, K, kc, sh)
+                                                                             : select_topk(get, K, kc, sh);
     for (int r = threadIdx.x; r < kc; r += kSelThreads) {
         const int64_t o = row * kc + r;
         if (r < kk) {

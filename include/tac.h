@@ -274,7 +274,7 @@ tac_status tac_doc_layout(tac_ctx ctx, const int32_t* assign_d, const uint8_t* c
  *              S descending; unused slots hold (-1, -inf).
  * 1 <= kc <= 256, 1 <= kd <= 4096.  Similarities are FP32 products with FP32
  * accumulation on the matrix cores and S adds them in float64 in token order,
- * so repeated calls give identical results.  The workspace holds at most 1 GiB
+ * so repeated calls give identical results.  The workspace holds at most 4 GiB
  * of similarities plus 36 bytes per visited list entry.  Synchronous (the
  * call returns after its work has completed on the context's stream); not for
  * graph capture.  TAC_E_INVAL on bad sizes or NULL pointers; list offsets must

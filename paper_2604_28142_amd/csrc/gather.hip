@@ -20,7 +20,7 @@
 //   of each token and adds them up in token order;
 // * topk_docs: one work-group per query selects the kappa_d documents of
 //   largest sum (ties to the lower document id) the same way.
-// Queries run in chunks so that the similarity matrix stays within 1 GiB.
+// Queries run in chunks so that the similarity matrix stays within 4 GiB.
 #include <algorithm>
 #include <cmath>
 
@@ -34,6 +34,7 @@ constexpr int kGDim = 128;
 constexpr int kSelThreads = 256;
 constexpr int kMaxKc = 256;
 constexpr int kMaxKd = 4096;
+constexpr int64_t kSimBudget = (int64_t)4 << 30;  // bytes of similarities per chunk of queries
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -491,8 +492,8 @@ extern "C" tac_status tac_gather(tac_ctx ctx, const float* Q_d, int64_t B, int32
     TAC_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     const int64_t ldS = (K + 3) / 4 * 4;
-    // queries per chunk: the similarity matrix within 1 GiB, the keys q * D + d within 32 bits
-    int64_t QC = std::max<int64_t>(1, ((int64_t)1 << 30) / ((int64_t)nq * ldS * 4));
+    // queries per chunk: the similarity matrix within kSimBudget, the keys q * D + d within 32 bits
+    int64_t QC = std::max<int64_t>(1, kSimBudget / ((int64_t)nq * ldS * 4));
     QC = std::min<int64_t>(QC, ((int64_t)UINT32_MAX - 1) / D);
     QC = std::min<int64_t>(QC, B);
     if (QC < 1) return set_error(TAC_E_INVAL, "tac_gather: too many documents for 32-bit keys");

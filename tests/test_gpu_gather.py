@@ -131,3 +131,21 @@ def test_sampled_at_benchmark_shape(ctx):
             S = oracle.document_scores(Q[b], C, off, docs, 40)
             ok = [abs(s - S[d]) <= TOL * 32 for d, s in zip(got_d[b].tolist(), got_s[b].tolist()) if d in S]
             assert sum(ok) >= 0.99 * len(ok)
+
+
+def test_query_chunks(ctx):
+    """130 queries x 32 tokens against 262,144 centroids do not fit one chunk of
+    similarities (128 queries do); queries on both sides of the chunk edge are
+    checked against the oracle."""
+    K, D = 262_144, 2_000
+    C, off, docs = _index(110, K, D, 200_000)
+    Q = _queries(111, 130, 32)
+    got_d, got_s = _gpu(ctx, Q, C, off, docs, D, 8, 50)
+    for b in (0, 127, 128, 129):
+        if _well_posed(Q[b], C, 8):
+            _check(Q[b], C, off, docs, 8, 50, got_d[b], got_s[b])
+        else:   # a near-tie at a token's cut may swap a centroid: nearly all scores still agree
+            S = oracle.document_scores(Q[b], C, off, docs, 8)
+            ok = [d in S and abs(s - S[d]) <= TOL * 32 for d, s in zip(got_d[b].tolist(), got_s[b].tolist())]
+            assert sum(ok) >= 0.95 * len(ok), (b, sum(ok))
+

@@ -16,9 +16,18 @@ Every output row is the canonical argmin for that row alone (assignment and
 PQ codes), so a document's result is bitwise the same alone or in any batch.
 A document with a token that has no centroid (or an id outside [0, T)) fails
 on its own with TacError(TAC_E_UNSEEN_TOKEN); the rest of its batch succeeds.
+
+Garbage collection.  Every request allocates a future, a request and a result
+record; with Python's default thresholds the cyclic collector then runs full
+collections over every long-lived object of the process (the caller's data
+included) in the middle of serving, which showed as tail latencies of tens of
+milliseconds.  By default the first running service therefore freezes the
+objects alive at its start (gc.freeze) and raises the collector's first
+threshold; the last one to close restores both.
 """
 from __future__ import annotations
 
+import gc
 import queue
 import threading
 import time
@@ -29,6 +38,32 @@ from dataclasses import dataclass, field
 import numpy as np
 
 ROW_BYTES = 128 * 4 + 4 + 4 + 32 + 4   # staged per vector: x, token, assignment, codes, norm
+
+GC_THRESHOLD0 = 50_000                 # first-generation threshold while a service runs
+
+_gc_lock = threading.Lock()
+_gc_users = 0
+_gc_saved = None
+
+
+def _gc_acquire():
+    global _gc_users, _gc_saved
+    with _gc_lock:
+        if _gc_users == 0:
+            _gc_saved = gc.get_threshold()
+            gc.collect()
+            gc.freeze()
+            gc.set_threshold(max(GC_THRESHOLD0, _gc_saved[0]), *_gc_saved[1:])
+        _gc_users += 1
+
+
+def _gc_release():
+    global _gc_users
+    with _gc_lock:
+        _gc_users -= 1
+        if _gc_users == 0:
+            gc.set_threshold(*_gc_saved)
+            gc.unfreeze()
 
 
 @dataclass
@@ -146,8 +181,12 @@ class EncodeService:
     """Continuous-batching encode service over an executor (GpuExecutor, or a
     stand-in with the same launch / wait interface)."""
 
-    def __init__(self, executor, max_docs: int = 512, ledger_bytes: int | None = None, idle_wait: float = 0.0005):
+    def __init__(self, executor, max_docs: int = 512, ledger_bytes: int | None = None, idle_wait: float = 0.0005,
+                 tune_gc: bool = True):
         self.ex = executor
+        self._tune_gc = tune_gc
+        if tune_gc:
+            _gc_acquire()
         self.n_slots = executor.n_slots
         self.max_docs = max_docs
         self.max_rows = executor.max_rows
@@ -191,6 +230,9 @@ class EncodeService:
         self._sched.join()
         self._inflight.put(None)
         self._done.join()
+        if self._tune_gc:
+            self._tune_gc = False
+            _gc_release()
 
     # ---- scheduler ----------------------------------------------------------
     def _take_arrivals(self, block: bool):

@@ -126,3 +126,22 @@ def test_rejects_malformed_documents():
     with pytest.raises(ValueError):
         svc.submit(np.zeros((0, 128), np.float32), np.zeros(0, np.int32))
     svc.close()
+
+
+def test_gc_tuning_lasts_while_any_service_runs():
+    import gc
+    before = gc.get_threshold()
+    a = EncodeService(FakeExecutor())
+    b = EncodeService(FakeExecutor())
+    try:
+        assert gc.get_threshold()[0] >= 50_000 and gc.get_freeze_count() > 0
+        res, _ = run_load(a, docs(20, seed=5), None)
+        assert all(not isinstance(r, Exception) for r in res)
+    finally:
+        a.close()
+    assert gc.get_threshold()[0] >= 50_000          # b still serves
+    b.close()
+    assert gc.get_threshold() == before and gc.get_freeze_count() == 0
+    c = EncodeService(FakeExecutor(), tune_gc=False)
+    assert gc.get_threshold() == before
+    c.close()

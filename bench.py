@@ -15,6 +15,7 @@ must give identical final assignments.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -28,6 +29,11 @@ sys.path.insert(0, ROOT)
 PEAK = {"bf16": 2500.0, "f16": 2500.0, "fp32": 157.3}   # dense MFMA TFLOP/s of an MI355X
 PRODUCTS = {"bf16": 3, "f16": 1, "fp32": 1}              # matrix-core products per coordinate of x.c
 HBM_PEAK = 8000.0                         # GB/s
+# Matrix-core ceilings measured with a microbenchmark on an MI355X: the
+# instruction each screen issues, at the kernel's occupancy (one wave per SIMD
+# for the 16-bit screens, two for FP32), in TFLOP/s
+MEASURED_MFMA = {"bf16": 1950.0, "f16": 1970.0, "fp32": 156.0}
+STAGED_BYTES = {"bf16": 4, "f16": 2, "fp32": 4}          # bytes per centroid coordinate the screen streams
 
 WORKLOAD_TEXT = {
     "c1": "10M token vectors x 128 fp32 (L2-normalised), Zipf(1.0) token ids over 30,522, 4 sub-centres per "
@@ -72,12 +78,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(x, tok, w, sample_rows: int, seed: int = 0):
+def cpu_baseline(x, tok, w, sample_rows: int, one_core_rows: int = 0, seed: int = 0):
     """Time the oracle's float64 assignment of a uniform row sample (a row's
-    assignment depends only on its token's centroids) on the host cores."""
+    assignment depends only on its token's centroids) on the host cores: with
+    every BLAS thread, then (when one_core_rows > 0) a smaller sample on one.
+    Returns (all-cores record, one-core record or None)."""
     import datagen
     import oracle
     from oracle.budget import BudgetParams
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     t0 = time.time()
     perm, seg_off, counts = oracle.group_by_token(tok, w.vocab)
@@ -88,14 +97,66 @@ def cpu_baseline(x, tok, w, sample_rows: int, seed: int = 0):
     picks = datagen.init_picks(counts, kappa, w.seed)
     C0 = oracle.init_centroids(xs, seg_off, cent_off, picks)
     log(f"cpu_baseline: oracle preparation {time.time() - t0:.1f}s")
-    rows = np.sort(np.random.default_rng([seed, 11]).choice(xs.shape[0], sample_rows, replace=False))
-    t0 = time.perf_counter()
-    oracle.assign_rows(xs, rows, seg_off, C0, cent_off, decide="fp64")
-    dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": sample_rows / dt, "unit": "vectors/s", "cores": threads, "kind": "oracle",
-            "sample": f"{sample_rows} uniformly sampled rows of the same workload assigned by the float64 oracle "
-                      f"against their tokens' initial centroids ({dt:.1f}s on {threads} threads)"}
+
+    def timed(n, threads_label):
+        rows = np.sort(np.random.default_rng([seed, 11]).choice(xs.shape[0], n, replace=False))
+        t0 = time.perf_counter()
+        oracle.assign_rows(xs, rows, seg_off, C0, cent_off, decide="fp64")
+        dt = time.perf_counter() - t0
+        threads = threads_label()
+        return {"value": n / dt, "unit": "vectors/s", "cores": threads, "kind": "oracle",
+                "sample": f"{n} uniformly sampled rows of the same workload assigned by the float64 oracle "
+                          f"against their tokens' initial centroids ({dt:.1f}s on {threads} threads)"}
+
+    def blas_threads():
+        return max([i["num_threads"] for i in threadpool_info()] or [1])
+
+    full = timed(sample_rows, blas_threads)
+    one = None
+    if one_core_rows > 0:
+        with threadpool_limits(limits=1):
+            one = timed(one_core_rows, blas_threads)
+    return full, one
+
+
+def segment_roofline(counts, kappa, kernel_ms: float, prec: str, hbm_gbs: float | None):
+    """Per-token roofline of one assignment launch: T_roof = sum over tokens of
+    max(F_j / P, B_j / BW) with F_j = 2 d n_j kappa_j for the screened tokens
+    (kappa_j > 4) and B_j = 4 d n_j (x) + b_c d kappa_j (the staged centroid
+    copy) + 8 n_j (assignment and distance); the fraction is T_roof over the
+    measured kernel time, against the spec-sheet peaks and against the measured
+    ceilings (the kernel's own matrix instruction at its occupancy, and a
+    device-to-device copy)."""
+    d = 128
+    n = counts.astype(np.float64)
+    k = kappa.astype(np.float64)
+    f = np.where(k > 4, 2.0 * d * n * k, 0.0)
+    b = 4.0 * d * n + STAGED_BYTES[prec] * d * k + 8.0 * n
+    t_spec = float(np.maximum(f / (PEAK[prec] * 1e12), b / (HBM_PEAK * 1e9)).sum()) * 1e3
+    out = {"t_roof_ms": t_spec, "t_measured_ms": kernel_ms, "frac": t_spec / kernel_ms,
+           "mfma_peak_tflops": PEAK[prec], "hbm_peak_gbs": HBM_PEAK}
+    if hbm_gbs:
+        t_meas = float(np.maximum(f / (MEASURED_MFMA[prec] * 1e12), b / (hbm_gbs * 1e9)).sum()) * 1e3
+        out.update({"t_roof_measured_ceilings_ms": t_meas, "frac_vs_measured_ceilings": t_meas / kernel_ms,
+                    "measured_mfma_tflops": MEASURED_MFMA[prec], "measured_copy_gbs": hbm_gbs})
+    return out
+
+
+def copy_bandwidth(torch, dev, nbytes: int = 1 << 31) -> float:
+    """Device-to-device copy rate (read + write bytes per second, GB/s), best of three."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    best = float("inf")
+    for _ in range(3):
+        ev[0].record()
+        dst.copy_(src)
+        ev[1].record()
+        ev[1].synchronize()
+        best = min(best, ev[0].elapsed_time(ev[1]))
+    del src, dst
+    return 2.0 * nbytes / (best / 1e3) / 1e9
 
 
 def global_baseline(ctx, idx, w, tac_iter_ms: float, rows: int, seed: int = 0):
@@ -278,8 +339,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c1", choices=["c0", "c1", "c3"])
     ap.add_argument("--iters", type=int, default=10)
+    ap.add_argument("--seed", type=int, default=0, help="data seed of the workload (0: the headline data)")
     ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-one-core-sample", type=int, default=20_000,
+                    help="rows of the single-thread oracle timing (0: skip it)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-f16", action="store_true", help="skip the FP16-screen comparison leg")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-screen comparison leg")
@@ -305,7 +369,7 @@ def main():
     from paper_2604_28142_amd import autotune
     from paper_2604_28142_amd import index as IX
 
-    w = datagen.WORKLOADS[args.config]
+    w = dataclasses.replace(datagen.WORKLOADS[args.config], seed=args.seed)
     t0 = time.time()
     x_h, tok_h = datagen.make(w)
     N = x_h.shape[0]
@@ -455,6 +519,9 @@ def main():
     extra["mfma_executed_tflops"] = {nm: PRODUCTS[nm] * F / (kms[nm] / 1e3) / 1e12 for nm in legs}
     if "fp32" in kms:
         extra["fp32_roofline_frac"] = F / (kms["fp32"] / 1e3) / 1e12 / PEAK["fp32"]
+    copy_gbs = copy_bandwidth(torch, dev)
+    extra["segment_roofline"] = {nm: segment_roofline(counts, kappa, kms[nm], nm, copy_gbs) for nm in legs}
+    log(f"per-token roofline: {extra['segment_roofline']}")
 
     extra["index_structures"], index = index_structures(ctx, idx, w, N)
     log(f"inverted lists + document layout: {extra['index_structures']}")
@@ -471,8 +538,10 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         n_cpu = min(args.cpu_sample, N)
-        cpu = cpu_baseline(x_h, tok_h, w, n_cpu)
+        cpu, cpu1 = cpu_baseline(x_h, tok_h, w, n_cpu, min(args.cpu_one_core_sample, N))
         cpu["value"] = float(cpu["value"])
+        if cpu1:
+            extra["cpu_baseline_one_core"] = cpu1
 
     line = {
         "metric": "vectors assigned/sec per Lloyd iter, bf16 vs fp32 at equal argmin; encode p99",
@@ -489,9 +558,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOAD_TEXT[args.config]}", "vectors": N, "tokens": w.vocab,
                    "centroids": w.k, "lloyd_iters": args.iters, "budget": "mu=128 tau=256 eps=4 theta=39",
-                   "timed_region_ms": wall},
+                   "seed": args.seed, "timed_region_ms": wall},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[hl], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK[hl], "traffic": measured_traffic(args.config, hl),
+                     "frac": achieved / PEAK[hl],
+                     "traffic": measured_traffic(args.config, hl) if args.seed == 0 else None,
                      "kernel": f"assign_main<{hl}> (persistent screen + per-lane top-3 + certificate)"},
         "cpu_baseline": cpu,
         **extra,

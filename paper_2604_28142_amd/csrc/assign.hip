@@ -107,18 +107,43 @@ __global__ void reset_call(unsigned long long* __restrict__ work, unsigned long 
 }
 
 // ---- plan: item counts per (class, token) ----
+// Split route (16-bit screens): a token of at most kSplitMaxRows rows and at
+// least kSplitMinKappa centroids -- the shape of a serving batch's frequent
+// tokens; no token of a clustering run qualifies, as kappa <= n / theta there --
+// is cut into (row tile, chunk of kSplitChunk centroids) work items of a second
+// launch spread over the device, where the persistent kernel would screen all
+// of the token's centroids for a row tile on one CU.  Each item's exact per-row
+// minimum over its chunk (with its own certificate) meets the other chunks' in
+// a 64-bit (distance bits, index) atomicMin slot per row; a row whose
+// certificate fails in any chunk goes, once, to the token's fallback queue,
+// which rescores every centroid of the token.
+constexpr int kSplitMaxRows = 8192;
+constexpr int kSplitMinKappa = 2048;
+constexpr int kSplitChunk = 1024;
+
+// work items per (class, token): class 0 heavy screen, 1 screen, 2 direct,
+// 3 split (row tiles x centroid chunks); after them, at 4T + j, the split
+// token's row count (its scan gives the token's first row slot)
 __global__ void plan_count(const int64_t* __restrict__ seg_off, const int64_t* __restrict__ cent_off, int32_t T,
-                           int direct_max, int heavy, int screen_rows, int direct_rows, int64_t* __restrict__ cnt,
-                           unsigned* __restrict__ kmax) {
+                           int direct_max, int heavy, int split_min, int screen_rows, int direct_rows,
+                           int64_t* __restrict__ cnt, unsigned* __restrict__ kmax) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= T) return;
     const int64_t n = seg_off[j + 1] - seg_off[j];
     const int64_t k = cent_off[j + 1] - cent_off[j];
     if (n > 0 && k > 0) atomicMax(kmax, (unsigned)k);
-    const int cls = (k == 0 || k <= direct_max) ? 2 : (k >= heavy ? 0 : 1);
+    int cls;
+    if (k == 0 || k <= direct_max)
+        cls = 2;
+    else if (split_min > 0 && n > 0 && n <= kSplitMaxRows && k >= split_min)
+        cls = 3;
+    else
+        cls = k >= heavy ? 0 : 1;
     const int64_t rows = cls == 2 ? direct_rows : screen_rows;
     const int64_t tiles = (n + rows - 1) / rows;
-    for (int c = 0; c < 3; ++c) cnt[(int64_t)c * T + j] = c == cls ? tiles : 0;
+    const int64_t items = cls == 3 ? tiles * ((k + kSplitChunk - 1) / kSplitChunk) : tiles;
+    for (int c = 0; c < 4; ++c) cnt[(int64_t)c * T + j] = c == cls ? items : 0;
+    cnt[4 * (int64_t)T + j] = cls == 3 ? n : 0;
 }
 
 // Everything a work item needs, in one 32-byte record, so that an item's first
@@ -134,11 +159,14 @@ struct ItemDesc {
 static_assert(sizeof(ItemDesc) == 32, "one 32-byte record per item");
 
 // item descriptors from the scanned item offsets: items of (class, token) pair
-// idx = class * T + token cut the token's rows into tiles of the class's size
+// idx = class * T + token cut the token's rows into tiles of the class's size,
+// and (class 3) each tile's centroids into chunks; for a split token this also
+// clears its rows' slots (row s0 + q: slot item_off[4T + j] - item_off[4T] + q)
 __global__ void plan_fill(const int64_t* __restrict__ item_off, const int64_t* __restrict__ seg_off,
                           const int64_t* __restrict__ cent_off, int32_t T, int screen_rows, int direct_rows,
-                          ItemDesc* __restrict__ desc) {
-    const int64_t ncls = 3 * (int64_t)T;
+                          ItemDesc* __restrict__ desc, unsigned long long* __restrict__ sslot,
+                          int32_t* __restrict__ sflag) {
+    const int64_t ncls = 4 * (int64_t)T;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < ncls;
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = item_off[idx], e = item_off[idx + 1];
@@ -152,6 +180,23 @@ __global__ void plan_fill(const int64_t* __restrict__ item_off, const int64_t* _
         d.kc = (int32_t)(cent_off[j + 1] - d.k0);
         d.jc = (cls << 24) | j;
         const int64_t s0 = seg_off[j];
+        if (cls == 3) {
+            const int64_t k0 = d.k0, kc = d.kc;
+            const int64_t chunks = (kc + kSplitChunk - 1) / kSplitChunk;
+            for (int64_t t = b; t < e; ++t) {
+                const int64_t tile = (t - b) / chunks, c = (t - b) - tile * chunks;
+                d.row0 = s0 + tile * rows;
+                d.k0 = k0 + c * kSplitChunk;
+                d.kc = (int32_t)min((int64_t)kSplitChunk, kc - c * kSplitChunk);
+                desc[t] = d;
+            }
+            const int64_t sb = item_off[4 * (int64_t)T + j] - item_off[4 * (int64_t)T];
+            for (int64_t q = 0; q < d.s1 - s0; ++q) {
+                sslot[sb + q] = ~0ull;
+                sflag[sb + q] = 0;
+            }
+            continue;
+        }
         for (int64_t t = b; t < e; ++t) {
             d.row0 = s0 + (t - b) * rows;
             desc[t] = d;
@@ -239,7 +284,7 @@ struct Params {
     const void* cstage;          // rows staged into LDS: C (FP32), hi/lo BF16 pairs or FP16 rows
     const float* cn;
     const unsigned* cstat;       // [0] = bits of max ||c||^2, [1] = max kappa, [2] = bits of max ||c - f16(c)||^2
-    const int64_t* item_off;     // [3T + 1]
+    const int64_t* item_off;     // [4T + 1]: items of classes 0-2, then the split items
     const ItemDesc* desc;        // per item
     unsigned long long* work;
     int32_t* assign;
@@ -253,6 +298,13 @@ struct Params {
     unsigned long long* fbslot;
     int32_t* fbcnt;
     unsigned long long* counters;
+};
+
+// Per-row state of the split route's rows (see kSplitMaxRows): the best exact
+// candidate over the chunks so far, and whether the row is already queued.
+struct SplitArgs {
+    unsigned long long* slot;
+    int32_t* flag;
 };
 
 __device__ __forceinline__ unsigned med3u(unsigned a, unsigned b, unsigned c) {
@@ -580,10 +632,10 @@ __device__ __forceinline__ void epoch_flush(Key (&el)[NB][4], unsigned* glist, i
 //   rounds y = -2x and c once, and with dy = y - f16(y), dc = c - f16(c) the
 //   dot error y.c - f16(y).f16(c) = f16(y).dc + dy.f16(c) + dy.dc is bounded by
 //   Cauchy-Schwarz with the measured norms ||dy|| (per row) and max ||dc||.
-template <int PREC, int NB, int LK>
+template <int PREC, int NB, int LK, bool SPLIT = false>
 __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t row0, int64_t s1,
                                             const unsigned* glist, float beta, float cnmax, float cmax, int lane,
-                                            const float* sdx = nullptr) {
+                                            const float* sdx = nullptr, SplitArgs S = {}) {
     const double u = 5.9604644775390625e-8;  // 2^-24
     const double g130 = 130.0 * u / (1.0 - 130.0 * u);
     const double g260 = 260.0 * u / (1.0 - 260.0 * u);
@@ -671,7 +723,22 @@ __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t 
             }
             ok = bounded && ((double)tau >= 1.0e38 || ((double)tau + shift) * (1.0 - g130) > (double)bd);
         }
-        if (ok) {
+        if constexpr (SPLIT) {
+            // this chunk's exact minimum joins the row's slot; a failed
+            // certificate queues the row once, with this chunk's best as its
+            // starting bound
+            const int64_t si = P.item_off[4 * (int64_t)P.T + j] - P.item_off[4 * (int64_t)P.T] + (v - P.seg_off[j]);
+            if (ok) {
+                atomicMin(&S.slot[si], ((unsigned long long)__float_as_uint(bd) << 32) | (unsigned)bi);
+            } else if (atomicExch(&S.flag[si], 1) == 0) {
+                const int64_t qi = P.seg_off[j] + atomicAdd(&P.fbcnt[j], 1);
+                P.fbq[qi] = (int32_t)r;
+                P.fbxx[qi] = xxq;
+                P.fbslot[qi] =
+                    bi < INT32_MAX ? ((unsigned long long)__float_as_uint(bd) << 32) | (unsigned)bi : ~0ull;
+                atomicAdd(&P.counters[kCntFallback], 1ull);
+            }
+        } else if (ok) {
             P.assign[r] = bi;
             P.dist[r] = bd;
         } else {
@@ -682,6 +749,7 @@ __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t 
             atomicAdd(&P.counters[kCntFallback], 1ull);
         }
     }
+    if constexpr (SPLIT) return;  // the split route's rows are counted once, when their slots are read
     for (int m = 32; m > 0; m >>= 1) nscreen += __shfl_xor(nscreen, m);
     if (lane == 0 && nscreen) {
         atomicAdd(&P.counters[kCntRows], (unsigned long long)nscreen);
@@ -905,8 +973,8 @@ struct BBlock<TAC_F16> {
     f4 cb;
 };
 
-template <int PREC>
-__device__ __forceinline__ void screen_item_mx(const Params& P, const ItemDesc& D, unsigned* lds) {
+template <int PREC, bool SPLIT = false>
+__device__ __forceinline__ void screen_item_mx(const Params& P, const ItemDesc& D, unsigned* lds, SplitArgs S = {}) {
     constexpr int NB = kBNB;
     constexpr int SC = StageGeom<PREC>::kCents;
     constexpr int BPS = StageGeom<PREC>::kBlocks;
@@ -1105,7 +1173,7 @@ __device__ __forceinline__ void screen_item_mx(const Params& P, const ItemDesc& 
             flush_if(blk - 1);
         }
     }
-    finish_item<PREC, NB, kBLK<PREC>>(P, j, row0, s1, glist, beta, cnmax, cmax, lane, sdx);
+    finish_item<PREC, NB, kBLK<PREC>, SPLIT>(P, j, row0, s1, glist, beta, cnmax, cmax, lane, sdx, S);
 }
 
 template <int PREC>
@@ -1160,6 +1228,52 @@ __global__ void __launch_bounds__(PREC == TAC_FP32 ? kThreads : kBThreads) assig
             s_idx[1] = nn;
         }
         __syncthreads();
+    }
+}
+
+// The split route's work items (items item_off[3T] .. item_off[4T]), one per
+// work-group at a time in a grid-stride loop: the same 16-bit screen and
+// finish as the persistent kernel, on one row tile and one centroid chunk.
+template <int PREC>
+__global__ void __launch_bounds__(kBThreads) assign_split(Params P, SplitArgs S) {
+    extern __shared__ __attribute__((aligned(16))) unsigned lds[];
+    const int64_t b = P.item_off[3 * (int64_t)P.T], e = P.item_off[4 * (int64_t)P.T];
+    for (int64_t t = b + blockIdx.x; t < e; t += gridDim.x) {
+        const ItemDesc D = P.desc[t];
+        screen_item_mx<PREC, true>(P, D, lds, S);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();  // every wave is done with this item's LDS
+    }
+}
+
+// The split route's results: each split token's first item writes the slots
+// of all of the token's rows to assign / dist, except rows queued for
+// exhaustive rescoring (the fallback writes those), and counts the rows.
+__global__ void split_resolve(const int64_t* __restrict__ item_off, const ItemDesc* __restrict__ desc, int32_t T,
+                              const int32_t* __restrict__ rowmap, const unsigned long long* __restrict__ slot,
+                              const int32_t* __restrict__ flag, int32_t* __restrict__ assign,
+                              float* __restrict__ dist, unsigned long long* __restrict__ counters) {
+    const int64_t b = item_off[3 * (int64_t)T], e = item_off[4 * (int64_t)T];
+    for (int64_t t = b + blockIdx.x; t < e; t += gridDim.x) {
+        const ItemDesc D = desc[t];
+        const int32_t j = D.jc & 0xFFFFFF;
+        if (t != item_off[3 * (int64_t)T + j]) continue;  // not the token's first chunk
+        const int n = (int)(D.s1 - D.row0);  // the first item's tile starts at the token's first row
+        const int64_t sb = item_off[4 * (int64_t)T + j] - item_off[4 * (int64_t)T];
+        for (int q = threadIdx.x; q < n; q += blockDim.x) {
+            const int64_t si = sb + q;
+            const int64_t v = D.row0 + q;
+            const int64_t r = rowmap ? (int64_t)rowmap[v] : v;
+            if (!flag[si]) {
+                const unsigned long long sv = slot[si];
+                assign[r] = (int32_t)(unsigned)sv;
+                dist[r] = __uint_as_float((unsigned)(sv >> 32));
+            }
+        }
+        if (threadIdx.x == 0) {
+            atomicAdd(&counters[kCntRows], (unsigned long long)n);
+            atomicAdd(&counters[kCntScreened], (unsigned long long)n);
+        }
     }
 }
 
@@ -1411,11 +1525,14 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     hipStream_t s = ctx->stream;
 
     const bool serve = tok_d != nullptr;
-    const int64_t ncls = 3 * (int64_t)T;
+    const int64_t ncls = 4 * (int64_t)T;  // item counts of the four classes; the split rows follow
     Carve cv;
-    const size_t o_cnt = cv.take<int64_t>(ncls + 1);
-    const size_t o_scan = cv.take<char>(scan_scratch_bytes(ncls));
-    const size_t o_table = cv.take<ItemDesc>(N / 256 + (int64_t)T + 1);  // items: at most one partial per token
+    const size_t o_cnt = cv.take<int64_t>(ncls + T + 1);
+    const size_t o_scan = cv.take<char>(scan_scratch_bytes(ncls + T));
+    // items: at most one partial tile per token, plus the split route's (tile, chunk) items
+    constexpr int64_t kSplitTiles = (kSplitMaxRows + kBTileRows - 1) / kBTileRows;
+    const size_t o_table =
+        cv.take<ItemDesc>(N / 256 + (int64_t)T + kSplitTiles * (K / kSplitChunk + K / kSplitMinKappa) + 1);
     const size_t o_work = cv.take<unsigned long long>(1);
     const size_t o_cstat = cv.take<unsigned>(4);
     const size_t o_cn = cv.take<float>(K + 1);
@@ -1425,6 +1542,10 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     const size_t o_fbxx = cv.take<float>(N + 1);
     const size_t o_slot = cv.take<unsigned long long>(N + 1);
     const size_t o_fbcnt = cv.take<int32_t>((int64_t)T + 1);
+    // split-route row slots: each split token has at most kSplitMaxRows rows and kSplitMinKappa centroids
+    const int64_t nsplit_rows = mx16 ? std::min<int64_t>(N, (K / kSplitMinKappa) * kSplitMaxRows) : 0;
+    const size_t o_sslot = cv.take<unsigned long long>(nsplit_rows + 1);
+    const size_t o_sflag = cv.take<int32_t>(nsplit_rows + 1);
     const size_t o_dist = dist_d ? 0 : cv.take<float>(N + 1);
     const int64_t nred = (N + kRedThreads * kRedItems - 1) / (kRedThreads * kRedItems);
     const size_t o_red = cv.take<double>(nred + 1);
@@ -1474,15 +1595,17 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     // dynamic LDS: the kernel's tiles plus the work-item slots
     const size_t lds_bytes = (mx16 ? kBLdsBytes : kLdsBytes) + kSlotBytes;
     plan_count<<<grid_for(T, 256), 256, 0, s>>>(seg, cent_off_d, T, ctx->tuning.direct_max_kappa,
-                                                  ctx->tuning.heavy_kappa,
-                                                  mx16 ? kBTileRows : kTileRows, threads, cnt,
-                                                  cstat + 1);
+                                                  ctx->tuning.heavy_kappa, mx16 ? kSplitMinKappa : 0,
+                                                  mx16 ? kBTileRows : kTileRows, threads, cnt, cstat + 1);
     TAC_LAUNCH_CHECK("plan_count");
-    st = exclusive_scan_i64(s, cnt, cnt, ncls, ws_at<void>(ctx, o_scan));
+    st = exclusive_scan_i64(s, cnt, cnt, ncls + T, ws_at<void>(ctx, o_scan));
     if (st != TAC_OK) return st;
     ItemDesc* table = ws_at<ItemDesc>(ctx, o_table);
+    SplitArgs S;
+    S.slot = ws_at<unsigned long long>(ctx, o_sslot);
+    S.flag = ws_at<int32_t>(ctx, o_sflag);
     plan_fill<<<grid_for(ncls, 256), 256, 0, s>>>(cnt, seg, cent_off_d, T, mx16 ? kBTileRows : kTileRows, threads,
-                                                    table);
+                                                    table, S.slot, S.flag);
     TAC_LAUNCH_CHECK("plan_fill");
     if (K > 0) {
         // a grid-stride launch of a few blocks per CU keeps the per-block atomicMax on the norm bound cheap
@@ -1521,6 +1644,10 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
                                     (int)(kBLdsBytes + kSlotBytes)));
         TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_F16>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)(kBLdsBytes + kSlotBytes)));
+        TAC_HIP(hipFuncSetAttribute((const void*)assign_split<TAC_BF16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kBLdsBytes));
+        TAC_HIP(hipFuncSetAttribute((const void*)assign_split<TAC_F16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kBLdsBytes));
         TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], assign_main<TAC_BF16>, kBThreads,
                                                              kBLdsBytes + kSlotBytes));
         TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], assign_main<TAC_F16>, kBThreads,
@@ -1544,6 +1671,18 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
         TAC_LAUNCH_CHECK("assign_main<f16>");
     }
     time_stop(ctx, TAC_SLOT_ASSIGN);
+    if (mx16) {
+        // the split route (no work items outside serving-sized batches: then the
+        // launches find an empty item range and return)
+        const unsigned sgrid = (unsigned)ctx->props_cu;
+        if (precision == TAC_BF16)
+            assign_split<TAC_BF16><<<sgrid, kBThreads, kBLdsBytes, s>>>(P, S);
+        else
+            assign_split<TAC_F16><<<sgrid, kBThreads, kBLdsBytes, s>>>(P, S);
+        TAC_LAUNCH_CHECK("assign_split");
+        split_resolve<<<sgrid, 128, 0, s>>>(cnt, table, T, rowmap, S.slot, S.flag, assign_d, dist, ctx->counters);
+        TAC_LAUNCH_CHECK("split_resolve");
+    }
     // rows whose certificate failed: per-token work plan (the item plan's
     // buffers are free again), matrix-core rescoring, write-back
     int64_t* woff = cnt;

@@ -189,11 +189,11 @@ tac_status tac_init_centroids(tac_ctx ctx, const float* xs_d, const int64_t* seg
  *  inertia_d device float64 scalar or NULL: sum of dist over assigned rows,
  *           summed in float64 in a fixed order (within-cluster sum of squares).
  * With TAC_BF16 and TAC_F16, a token of at most 8,192 rows and at least 2,048
- * centroids (a serving batch's frequent token; none in a clustering run, where
- * kappa_j <= n_j / theta) is screened as (row tile, 1,024-centroid chunk) work
- * items of a second launch across the device, each chunk's exact minimum
- * merged per row; the results are the same as on every other route.  The
- * workspace holds one 12-byte slot per such row. */
+ * centroids (a serving batch's frequent token; a clustering budget gives such
+ * a kappa_j only to tokens with far more rows) is screened as (row tile,
+ * 1,024-centroid chunk) work items of a second launch across the device, each
+ * chunk's exact minimum merged per row; the results are the same as on every
+ * other route.  The workspace holds one 12-byte slot per such row. */
 tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* seg_off_d, const int32_t* tok_d,
                       int64_t N, int32_t d, int32_t T, const float* C_d, const int64_t* cent_off_d,
                       int64_t K, int32_t precision, int32_t* assign_d, float* dist_d,

@@ -109,8 +109,8 @@ __global__ void reset_call(unsigned long long* __restrict__ work, unsigned long 
 // ---- plan: item counts per (class, token) ----
 // Split route (16-bit screens): a token of at most kSplitMaxRows rows and at
 // least kSplitMinKappa centroids -- the shape of a serving batch's frequent
-// tokens; no token of a clustering run qualifies, as kappa <= n / theta there --
-// is cut into (row tile, chunk of kSplitChunk centroids) work items of a second
+// tokens; a clustering budget gives such a kappa only to tokens with far more
+// rows -- is cut into (row tile, chunk of kSplitChunk centroids) work items of a second
 // launch spread over the device, where the persistent kernel would screen all
 // of the token's centroids for a row tile on one CU.  Each item's exact per-row
 // minimum over its chunk (with its own certificate) meets the other chunks' in

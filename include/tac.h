@@ -129,6 +129,19 @@ typedef struct {
 tac_status tac_ctx_set_tuning(tac_ctx ctx, const tac_tuning* tuning);
 tac_status tac_ctx_get_tuning(tac_ctx ctx, tac_tuning* tuning);
 
+/* Declare centroids unchanging (a resident index, as in the encode service):
+ * their squared norms, norm bounds and 16-bit staging rows, which tac_assign
+ * otherwise recomputes from all K centroids on every call, are prepared once
+ * here for this precision.  Later tac_assign calls on this context with
+ * exactly this (C_d, K, precision) use them; any other call prepares its own
+ * as before.  The caller must not change C_d's contents while the
+ * declaration stands.  C_d = NULL clears it.  The prepared buffer (about
+ * 516 bytes per centroid for TAC_BF16, 260 for TAC_F16, 4 for TAC_FP32) is
+ * held until the context is destroyed, also after clearing, because a graph
+ * captured on the context may address it.  Not allowed during stream
+ * capture.  Asynchronous. */
+tac_status tac_ctx_set_static_centroids(tac_ctx ctx, const float* C_d, int64_t K, int32_t precision);
+
 /* Wait for the context's stream, then free the workspace and the context. */
 void tac_ctx_destroy(tac_ctx ctx);
 

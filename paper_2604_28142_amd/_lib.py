@@ -27,7 +27,7 @@ EXPORTS = ["tac_ctx_create", "tac_ctx_set_stream", "tac_ctx_destroy", "tac_last_
            "tac_budget_from_stats",
            "tac_init_centroids", "tac_assign", "tac_assign_stats", "tac_update", "tac_residuals", "pq_train",
            "pq_encode", "tac_ctx_enable_timing", "tac_kernel_ms", "tac_ctx_set_tuning", "tac_ctx_get_tuning",
-           "tac_ivf_build", "tac_doc_layout", "tac_maxsim", "tac_gather"]
+           "tac_ivf_build", "tac_doc_layout", "tac_maxsim", "tac_gather", "tac_ctx_set_static_centroids"]
 TAC_SLOT_ASSIGN, TAC_SLOT_UPDATE, TAC_SLOT_ENCODE = 0, 1, 2
 
 
@@ -65,6 +65,7 @@ _SIGS = {
     "tac_ctx_enable_timing": (C.c_int, [_P, C.c_int]),
     "tac_kernel_ms": (C.c_int, [_P, C.c_int, C.POINTER(C.c_float)]),
     "tac_ctx_set_tuning": (C.c_int, [_P, C.POINTER(Tuning)]),
+    "tac_ctx_set_static_centroids": (C.c_int, [_P, _P, C.c_int64, C.c_int32]),
     "tac_ctx_get_tuning": (C.c_int, [_P, C.POINTER(Tuning)]),
     "tac_last_error": (C.c_char_p, []),
     "tac_budget": (C.c_int, [_P, _P, _P, _I64, _I32, _I32, _I64, C.POINTER(BudgetParams), _P, _P, _P, _P, _P, _P,
@@ -171,6 +172,17 @@ class Context:
             t.groups_per_cu = groups_per_cu
         _check(load().tac_ctx_set_tuning(self.handle, C.byref(t)))
         return t.as_dict()
+
+    def set_static_centroids(self, C_cent, precision: int):
+        """Declare C_cent [K, d] float32 unchanging for tac_assign at this precision
+        (prepared once; None clears).  C_cent must stay alive and unchanged meanwhile."""
+        if C_cent is None:
+            _check(load().tac_ctx_set_static_centroids(self.handle, None, 0, 0))
+            self._static = None
+            return
+        _check_dtype(C_cent, torch.float32, "C_cent")
+        _check(load().tac_ctx_set_static_centroids(self.handle, _dptr(C_cent), C_cent.shape[0], precision))
+        self._static = C_cent          # keeps the tensor alive while declared
 
     def get_tuning(self) -> dict:
         t = Tuning()

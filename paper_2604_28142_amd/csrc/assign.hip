@@ -98,12 +98,13 @@ __device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_
 
 // ---- per-call reset of the work counter, statistics and max centroid norm ----
 __global__ void reset_call(unsigned long long* __restrict__ work, unsigned long long* __restrict__ counters,
-                           unsigned* __restrict__ cstat) {
+                           unsigned* __restrict__ cstat, const unsigned* __restrict__ cstat_static) {
     work[0] = 0;
     for (int i = 0; i < 4; ++i) counters[i] = 0;
-    cstat[0] = 0;
+    // the centroid bounds come from prep_centroids, or from the prepared static centroids
+    cstat[0] = cstat_static ? cstat_static[0] : 0;
     cstat[1] = 0;
-    cstat[2] = 0;
+    cstat[2] = cstat_static ? cstat_static[2] : 0;
 }
 
 // ---- plan: item counts per (class, token) ----
@@ -1507,6 +1508,62 @@ unsigned grid_for(int64_t work, int per_block) {
 
 using namespace tac;
 
+namespace {
+// Layout of a prepared-centroid buffer: the bounds (4 words), the norms (K + 1
+// floats), then the 16-bit staging rows, each part 256-byte aligned.
+struct StaticLayout {
+    size_t cn, chl, bytes;
+    StaticLayout(int64_t K, int32_t precision) {
+        cn = 256;
+        chl = cn + (((size_t)(K + 1) * sizeof(float) + 255) / 256) * 256;
+        const size_t rows = precision == TAC_FP32 ? 0 : (size_t)(K + 1) * (precision == TAC_BF16 ? 2 : 1) * kDim;
+        bytes = chl + rows * sizeof(unsigned short);
+    }
+};
+}  // namespace
+
+extern "C" tac_status tac_ctx_set_static_centroids(tac_ctx ctx, const float* C_d, int64_t K, int32_t precision) {
+    if (!ctx) return set_error(TAC_E_INVAL, "tac_ctx_set_static_centroids: ctx is NULL");
+    if (C_d && (K < 1 || K > INT32_MAX))
+        return set_error(TAC_E_INVAL, "tac_ctx_set_static_centroids: K out of range");
+    if (C_d && precision != TAC_FP32 && precision != TAC_BF16 && precision != TAC_F16)
+        return set_error(TAC_E_INVAL, "tac_ctx_set_static_centroids: bad precision");
+    TAC_HIP(hipSetDevice(ctx->device));
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    TAC_HIP(hipStreamIsCapturing(ctx->stream, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+        return set_error(TAC_E_INVAL, "tac_ctx_set_static_centroids: not allowed during stream capture");
+    if (ctx->sc_buf) {
+        // retired, not freed: a graph captured on this context may still address it
+        ctx->ws_retired.push_back(ctx->sc_buf);
+        ctx->sc_buf = nullptr;
+    }
+    ctx->sc_C = nullptr;
+    ctx->sc_K = 0;
+    ctx->sc_prec = -1;
+    if (!C_d) return TAC_OK;
+    const StaticLayout L(K, precision);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, L.bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(TAC_E_NOMEM, "hipMalloc of " + std::to_string(L.bytes) + " prepared-centroid bytes failed");
+    }
+    char* base = static_cast<char*>(p);
+    unsigned* cstat = reinterpret_cast<unsigned*>(base);
+    TAC_HIP(hipMemsetAsync(cstat, 0, 4 * sizeof(unsigned), ctx->stream));
+    const unsigned pgrid = std::min<unsigned>(grid_for(K * 32, 256), (unsigned)ctx->props_cu * 16);
+    prep_centroids<<<pgrid, 256, 0, ctx->stream>>>(
+        C_d, K, reinterpret_cast<float*>(base + L.cn), cstat,
+        precision == TAC_FP32 ? nullptr : reinterpret_cast<unsigned short*>(base + L.chl), precision);
+    TAC_LAUNCH_CHECK("prep_centroids");
+    ctx->sc_buf = p;
+    ctx->sc_C = C_d;
+    ctx->sc_K = K;
+    ctx->sc_prec = precision;
+    return TAC_OK;
+}
+
 extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* seg_off_d, const int32_t* tok_d,
                                  int64_t N, int32_t d, int32_t T, const float* C_d, const int64_t* cent_off_d,
                                  int64_t K, int32_t precision, int32_t* assign_d, float* dist_d, double* inertia_d) {
@@ -1535,9 +1592,12 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
         cv.take<ItemDesc>(N / 256 + (int64_t)T + kSplitTiles * (K / kSplitChunk + K / kSplitMinKappa) + 1);
     const size_t o_work = cv.take<unsigned long long>(1);
     const size_t o_cstat = cv.take<unsigned>(4);
-    const size_t o_cn = cv.take<float>(K + 1);
     const bool mx16 = precision != TAC_FP32;
-    const size_t o_chl = mx16 ? cv.take<unsigned short>((K + 1) * (precision == TAC_BF16 ? 2 : 1) * kDim) : 0;
+    // centroids declared unchanging for exactly this call's (C, K, precision): prepared once
+    const bool prepared = ctx->sc_buf && ctx->sc_C == C_d && ctx->sc_K == K && ctx->sc_prec == precision;
+    const size_t o_cn = prepared ? 0 : cv.take<float>(K + 1);
+    const size_t o_chl =
+        mx16 && !prepared ? cv.take<unsigned short>((K + 1) * (precision == TAC_BF16 ? 2 : 1) * kDim) : 0;
     const size_t o_fbq = cv.take<int32_t>(N + 1);
     const size_t o_fbxx = cv.take<float>(N + 1);
     const size_t o_slot = cv.take<unsigned long long>(N + 1);
@@ -1564,12 +1624,20 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     unsigned* cstat = ws_at<unsigned>(ctx, o_cstat);
     float* cn = ws_at<float>(ctx, o_cn);
     unsigned short* chl = mx16 ? ws_at<unsigned short>(ctx, o_chl) : nullptr;
+    const unsigned* cstat_static = nullptr;
+    if (prepared) {
+        const StaticLayout L(K, precision);
+        char* base = static_cast<char*>(ctx->sc_buf);
+        cstat_static = reinterpret_cast<const unsigned*>(base);
+        cn = reinterpret_cast<float*>(base + L.cn);
+        chl = mx16 ? reinterpret_cast<unsigned short*>(base + L.chl) : nullptr;
+    }
     int64_t* cnt = ws_at<int64_t>(ctx, o_cnt);
     unsigned long long* work = ws_at<unsigned long long>(ctx, o_work);
 
     const int64_t* seg = seg_off_d;
     const int32_t* rowmap = nullptr;
-    reset_call<<<1, 1, 0, s>>>(work, ctx->counters, cstat);
+    reset_call<<<1, 1, 0, s>>>(work, ctx->counters, cstat, cstat_static);
     TAC_LAUNCH_CHECK("reset_call");
     if (serve) {
         int64_t* sseg = ws_at<int64_t>(ctx, o_seg);
@@ -1607,7 +1675,7 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     plan_fill<<<grid_for(ncls, 256), 256, 0, s>>>(cnt, seg, cent_off_d, T, mx16 ? kBTileRows : kTileRows, threads,
                                                     table, S.slot, S.flag);
     TAC_LAUNCH_CHECK("plan_fill");
-    if (K > 0) {
+    if (K > 0 && !prepared) {
         // a grid-stride launch of a few blocks per CU keeps the per-block atomicMax on the norm bound cheap
         const unsigned pgrid = std::min<unsigned>(grid_for(K * 32, 256), (unsigned)ctx->props_cu * 16);
         prep_centroids<<<pgrid, 256, 0, s>>>(C_d, K, cn, cstat, chl, precision);

@@ -148,6 +148,7 @@ extern "C" void tac_ctx_destroy(tac_ctx ctx) {
         for (int k = 0; k < 2; ++k)
             if (ctx->ev[s][k]) (void)hipEventDestroy(ctx->ev[s][k]);
     if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->sc_buf) (void)hipFree(ctx->sc_buf);
     for (void* p : ctx->ws_retired) (void)hipFree(p);
     if (ctx->counters) (void)hipFree(ctx->counters);
     delete ctx;

@@ -60,6 +60,13 @@ struct tac_ctx_s {
     unsigned long long* counters = nullptr;
     int props_cu = 256;
     tac_tuning tuning = {4, 1024, 0};
+    // centroids declared unchanging (tac_ctx_set_static_centroids): the
+    // assignment's per-call preparation (norms, bounds, 16-bit staging rows),
+    // done once into sc_buf; replaced buffers are retired like workspaces
+    const float* sc_C = nullptr;
+    int64_t sc_K = 0;
+    int32_t sc_prec = -1;
+    void* sc_buf = nullptr;
     // optional HIP-event timing of each entry point's dominant kernel
     bool timing = false;
     hipEvent_t ev[TAC_KERNEL_SLOTS][2] = {};

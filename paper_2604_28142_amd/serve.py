@@ -110,7 +110,9 @@ class ServiceStats:
 
 class GpuExecutor:
     """Runs batches on the GPU through libtac; one context, stream and set of
-    staging buffers per slot."""
+    staging buffers per slot.  Each context holds the resident index's
+    centroids prepared once (tac_ctx_set_static_centroids), so a batch's
+    assignment does not re-derive norms and 16-bit rows from all K centroids."""
 
     def __init__(self, index, n_slots: int = 3, max_rows: int = 512 * 180, device: int = 0,
                  precision: int | None = None):
@@ -129,6 +131,7 @@ class GpuExecutor:
         for _ in range(n_slots):
             s = torch.cuda.Stream(device=dev)
             ctx = L.Context(device, stream=s)
+            ctx.set_static_centroids(index.C, self.precision)
             self.slots.append(dict(
                 stream=s, ctx=ctx, event=torch.cuda.Event(),
                 x_h=torch.empty((max_rows, 128), dtype=torch.float32, pin_memory=True),

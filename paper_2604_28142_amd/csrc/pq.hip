@@ -249,7 +249,9 @@ __global__ void __launch_bounds__(512) train_encode(const float* __restrict__ R,
 // Codes are bitwise those of the scalar screen.
 // Work split: the 32 subspaces are encoded by two work-groups per block of
 // 512 rows (16 subspaces each, 80 KiB of codebooks and norms in LDS), so two
-// work-groups share a CU and hide each other's load and shuffle latency.
+// work-groups share a CU and hide each other's load and shuffle latency.  An
+// input of few row blocks (a serving batch) is split into eight work-groups of
+// 4 subspaces per block instead, so that it spreads over more CUs.
 constexpr int kEThreads = 512;
 constexpr int kENB = 4;
 constexpr int kERows = (kEThreads / 64) * kENB * 16;
@@ -291,7 +293,7 @@ __device__ __forceinline__ unsigned screen_key(float v, unsigned codes) {
     return __builtin_amdgcn_perm(__float_as_uint(v), codes, 0x07060500u + r);
 }
 
-template <bool RESID>
+template <bool RESID, int SUB = kEHalf>
 __global__ void __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(4))) encode_screen(const float* __restrict__ x,
                                                               const int32_t* __restrict__ assign,
                                                               const float* __restrict__ C, int64_t K, int64_t n,
@@ -300,13 +302,14 @@ __global__ void __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(
                                                               uint32_t* __restrict__ codes_sub,
                                                               float* __restrict__ rnorm) {
     constexpr int M = kDim / kDsub;
-    static_assert(M == 2 * kEHalf, "two halves of the subspaces");
+    static_assert(M % SUB == 0 && SUB % 4 == 0, "whole 4-code words per work-group");
+    constexpr int G = M / SUB;  // work-groups per row block
     constexpr unsigned kNoKey = 0x7F7FFFFFu;  // FLT_MAX: an empty list entry
     extern __shared__ float4 lds4[];
-    const int m0 = (int)(blockIdx.x & 1) * kEHalf;
+    const int m0 = (int)(blockIdx.x % G) * SUB;
     float4* lcb = lds4;
-    float* lcn = reinterpret_cast<float*>(lds4 + kEHalf * ksub);
-    const float cnmax = load_codebooks_norms(cbg + (size_t)m0 * ksub * kDsub, kEHalf, ksub, lcb, lcn);
+    float* lcn = reinterpret_cast<float*>(lds4 + SUB * ksub);
+    const float cnmax = load_codebooks_norms(cbg + (size_t)m0 * ksub * kDsub, SUB, ksub, lcb, lcn);
     const float* lcbf = reinterpret_cast<const float*>(lcb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
     const double uc = 5.9604644775390625e-8;  // 2^-24
@@ -315,8 +318,8 @@ __global__ void __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(
     const double cm2 = (double)cnmax * (1.0 + 1e-5);
     const double scm = sqrt(cm2);
     const int nt = ksub / 16;
-    const int64_t nblk = gridDim.x >> 1;
-    for (int64_t base = (int64_t)(blockIdx.x >> 1) * kERows; base < n; base += nblk * kERows) {
+    const int64_t nblk = gridDim.x / G;
+    for (int64_t base = (int64_t)(blockIdx.x / G) * kERows; base < n; base += nblk * kERows) {
         const int64_t wbase = base + wave * (kENB * 16);
         // lane-per-row prologue: validity, centroid and canonical residual norm
         const int64_t myrow = wbase + lane;
@@ -356,7 +359,7 @@ __global__ void __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(
             }
         };
         fetch(m0);
-        for (int mi = 0; mi < kEHalf; ++mi) {
+        for (int mi = 0; mi < SUB; ++mi) {
             const int m = m0 + mi;
             float u[kENB], sq[kENB], um = 0.f;
 #pragma unroll
@@ -377,7 +380,7 @@ __global__ void __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(
                 sq[nb] = s;  // the row's ||u||^2, within a relative 3 u of the exact value
                 um = fmaxf(um, s);
             }
-            if (mi + 1 < kEHalf) fetch(m + 1);
+            if (mi + 1 < SUB) fetch(m + 1);
             um = row16_max(um);
             // one shift per wave and subspace: beta >= ||u||^2 + (screen error) for each of its rows
             const float beta = um * (1.0f + 0.00390625f) + 0.00390625f * cnmax + 1e-30f;
@@ -479,7 +482,8 @@ __global__ void __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(
 bool g_attr_screen[2] = {false, false};
 
 // LDS of one encode_screen work-group: codebooks and norms of its 16 subspaces.
-size_t screen_lds(int ksub) { return (size_t)kEHalf * ksub * (kDsub + 1) * sizeof(float); }
+size_t screen_lds(int ksub, int sub = kEHalf) { return (size_t)sub * ksub * (kDsub + 1) * sizeof(float); }
+bool g_attr_screen4 = false;
 
 // off[t] = first sorted position with key >= t, t in [0, nkeys]
 __global__ void code_offsets(const uint32_t* __restrict__ keys, int64_t n, int nkeys, int64_t* __restrict__ off) {
@@ -600,10 +604,20 @@ extern "C" tac_status pq_encode(tac_ctx ctx, const float* x_d, const int32_t* as
                                         (int)kMaxCodebookLds));
             g_attr_screen[0] = true;
         }
-        const unsigned grid = 2u * (unsigned)std::max<int64_t>(
-                                       1, std::min<int64_t>((n + kERows - 1) / kERows, (int64_t)ctx->props_cu));
-        encode_screen<true><<<grid, kEThreads, screen_lds(ksub), ctx->stream>>>(
-            x_d, assign_d, C_d, K, n, normalize, codebooks_d, ksub, codes_d, nullptr, rnorm_d);
+        const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + kERows - 1) / kERows, (int64_t)ctx->props_cu));
+        if (4 * blocks <= (int64_t)ctx->props_cu) {
+            // few row blocks: eight work-groups of 4 subspaces per block
+            if (!g_attr_screen4) {
+                TAC_HIP(hipFuncSetAttribute((const void*)encode_screen<true, 4>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxCodebookLds));
+                g_attr_screen4 = true;
+            }
+            encode_screen<true, 4><<<(unsigned)(8 * blocks), kEThreads, screen_lds(ksub, 4), ctx->stream>>>(
+                x_d, assign_d, C_d, K, n, normalize, codebooks_d, ksub, codes_d, nullptr, rnorm_d);
+        } else {
+            encode_screen<true><<<(unsigned)(2 * blocks), kEThreads, screen_lds(ksub), ctx->stream>>>(
+                x_d, assign_d, C_d, K, n, normalize, codebooks_d, ksub, codes_d, nullptr, rnorm_d);
+        }
         TAC_LAUNCH_CHECK("encode_screen");
     } else {
         const unsigned grid =

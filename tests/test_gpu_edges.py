@@ -331,6 +331,26 @@ def test_pq_encode_shapes_and_invalid_rows(ctx, ksub, normalize):
     assert np.array_equal(host(rho)[ok], rho32)
 
 
+@pytest.mark.parametrize("n", [700, 32_768, 32_769])
+def test_pq_encode_work_splits(ctx, n):
+    """The encode's work split follows the input size (8 work-groups of 4
+    subspaces per 512-row block up to 64 blocks, 2 of 16 beyond, on this
+    device's 256 CUs); both splits, at their boundary, give the oracle's codes
+    and norms."""
+    rng = np.random.default_rng(120)
+    K = 50
+    x = clustered(rng, n, 9)
+    C = x[rng.choice(n, K, replace=False)].copy()
+    a = rng.integers(0, K, n).astype(np.int32)
+    cb = (0.25 * rng.standard_normal((32, 256, 4))).astype(np.float32)
+    codes = torch.empty((n, 32), dtype=torch.uint8, device="cuda")
+    rho = torch.empty(n, dtype=torch.float32, device="cuda")
+    tac.pq_encode(ctx, dev(x), dev(a), dev(C), dev(cb), codes, normalize=True, rnorm=rho)
+    u32, rho32 = oracle.residuals(x, C[a], normalize=True, mode="fp32")
+    assert np.array_equal(host(codes), oracle.pq_encode(u32, cb, decide="fp32"))
+    assert np.array_equal(host(rho), rho32)
+
+
 def test_pq_encode_ties_and_fallback(ctx):
     """Duplicate codes tie exactly (the lowest code wins); a codebook of nearly
     equal codes defeats the screen's certificate and is scanned exhaustively."""

@@ -139,7 +139,7 @@ tac_status tac_ctx_get_tuning(tac_ctx ctx, tac_tuning* tuning);
  * 516 bytes per centroid for TAC_BF16, 260 for TAC_F16, 4 for TAC_FP32) is
  * held until the context is destroyed, also after clearing, because a graph
  * captured on the context may address it.  Not allowed during stream
- * capture.  Asynchronous. */
+ * capture.  Synchronous (later calls may use another stream). */
 tac_status tac_ctx_set_static_centroids(tac_ctx ctx, const float* C_d, int64_t K, int32_t precision);
 
 /* Wait for the context's stream, then free the workspace and the context. */

@@ -1557,6 +1557,8 @@ extern "C" tac_status tac_ctx_set_static_centroids(tac_ctx ctx, const float* C_d
         C_d, K, reinterpret_cast<float*>(base + L.cn), cstat,
         precision == TAC_FP32 ? nullptr : reinterpret_cast<unsigned short*>(base + L.chl), precision);
     TAC_LAUNCH_CHECK("prep_centroids");
+    // synchronous: later calls may run on another stream of the context
+    TAC_HIP(hipStreamSynchronize(ctx->stream));
     ctx->sc_buf = p;
     ctx->sc_C = C_d;
     ctx->sc_K = K;

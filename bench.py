@@ -277,7 +277,7 @@ def index_structures(ctx, idx, w, N):
 
 
 def query_path(ctx, idx, w, index, nqueries=64, nq=32, kc=40, ncand=1000):
-    """Both phases of retrieval (Sect. 2.3) for synthetic queries against the
+    """Both phases of retrieval (Sect. 2.2) for synthetic queries against the
     built index: the gather phase (kappa_c = `kc` centroids per query token,
     kappa_d = `ncand` candidates per query) and the refine phase (MaxSim over
     the PQ-coded candidates).  Timed with HIP events on the context's stream

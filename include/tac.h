@@ -277,7 +277,7 @@ tac_status tac_ivf_build(tac_ctx ctx, const int32_t* assign_d, const int32_t* do
 tac_status tac_doc_layout(tac_ctx ctx, const int32_t* assign_d, const uint8_t* codes_d, int32_t M,
                           const int64_t* doc_off_d, int64_t D, int64_t N, uint8_t* layout_d);
 
-/* Gather phase of retrieval (Sect. 2.3, "Gather Phase: Centroid-based
+/* Gather phase of retrieval (Sect. 2.2, "Gather Phase: Centroid-based
  * Document Scoring"): for each of the B queries,
  *  1. every query token q_i takes the kc centroids of largest <q_i, c_j>
  *     (exactly: the paper's HNSW graph approximates this set; ties go to the
@@ -302,7 +302,7 @@ tac_status tac_gather(tac_ctx ctx, const float* Q_d, int64_t B, int32_t nq, int3
                       const int64_t* list_off_d, const int32_t* list_docs_d, int64_t D, int32_t kc, int32_t kd,
                       int32_t* cand_d, float* score_d);
 
-/* Refine phase of retrieval (Sect. 2.3, "Refine Phase: PQ-Optimized MaxSim
+/* Refine phase of retrieval (Sect. 2.2, "Refine Phase: PQ-Optimized MaxSim
  * Computation"): the MaxSim score of each candidate document for its query,
  *   S(q, d) = sum_i max_{t in d} <q_i, c_{a_t} + rho_t * u_t>,
  * with u_t the concatenation of the codewords codebooks[m][code_{t,m}] (the

@@ -5,7 +5,7 @@ NumPy implementation of what the GPU library computes, written from the paper
 (Sect. 2.1: tail handling, damped scoring, bounding, budget reconciliation,
 per-token k-means, residual compression with product quantisation), the
 inverted lists and document layout built from it (Sect. 2.2), and the two
-phases of retrieval over that index (Sect. 2.3: gather, refine).  Only the
+phases of retrieval over that index (Sect. 2.2, its Gather and Refine phases).  Only the
 test suite, the smoke check and the CPU-baseline leg of the benchmark may
 import it; the product path never does, and it imports nothing from the
 product package.
@@ -37,4 +37,4 @@ __all__ = [
     "inverted_lists", "doc_layout", "decode_layout",
 ]
 from .refine import distance_tables, doc_block, maxsim_scores
-from .gather import top_centroids, document_scores, gather
+from .gather import top_centroids, document_scores, document_score_bounds, gather

@@ -1,4 +1,4 @@
-"""Oracle for the gather phase of retrieval (Sect. 2.3, "Gather Phase:
+"""Oracle for the gather phase of retrieval (Sect. 2.2, "Gather Phase:
 Centroid-based Document Scoring").
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
@@ -70,3 +70,63 @@ def gather(Q, C, list_off, list_docs, kc, kd):
         docs[r] = d
         scores[r] = s
     return docs, scores
+
+
+def document_score_bounds(Q, C, list_off, list_docs, kc, tol):
+    """Admissible scores when every similarity may carry an error of up to ``tol``.
+
+    An implementation that computes <q_i, c_j> with an error of at most tol and
+    then takes its own top-kc per query token can pick any centroid whose exact
+    similarity lies within 2 tol of the kc-th largest one (``v_i``): a centroid
+    above v_i + 2 tol is always taken, one below v_i - 2 tol never (at least kc
+    centroids stay above it).  Over every such choice, s_i(d) (the largest
+    similarity among the chosen centroids that reach d, absent when none does)
+    lies between the bounds below, so S(q, d) lies in [lo(d), hi(d)], with each
+    similarity itself exact here and the rounding allowance left to the caller.
+
+    Returns (sure, lo, hi): ``sure`` the set of documents every choice reaches,
+    ``lo`` / ``hi`` dicts over every document some choice reaches (absent
+    tokens count 0).  With tol = 0 and no equal similarities across any cut,
+    lo = hi = document_scores.
+    """
+    Q = np.asarray(Q, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    K = C.shape[0]
+    kc = min(int(kc), K)
+    sims = Q @ C.T
+    lo, hi = {}, {}
+    sure = None
+    for i in range(Q.shape[0]):
+        v = np.sort(sims[i])[::-1][kc - 1]
+        if kc >= K:
+            must = np.arange(K)
+            maybe = np.zeros(0, dtype=np.int64)
+        else:
+            must = np.nonzero(sims[i] > v + 2 * tol)[0]
+            maybe = np.nonzero((sims[i] >= v - 2 * tol) & (sims[i] <= v + 2 * tol))[0]
+            if must.size + maybe.size == kc:         # no choice left: every optional centroid is taken
+                must = np.concatenate([must, maybe])
+                maybe = maybe[:0]
+        sure_i = {}                                  # d -> max similarity over the centroids always taken
+        for j in must.tolist():
+            s = sims[i, j]
+            for d in np.asarray(list_docs[int(list_off[j]):int(list_off[j + 1])]).tolist():
+                if d not in sure_i or s > sure_i[d]:
+                    sure_i[d] = s
+        amb_min, amb_max = {}, {}                    # d -> min / max similarity over the optional centroids
+        for j in maybe.tolist():
+            s = sims[i, j]
+            for d in np.asarray(list_docs[int(list_off[j]):int(list_off[j + 1])]).tolist():
+                amb_min[d] = min(amb_min.get(d, s), s)
+                amb_max[d] = max(amb_max.get(d, s), s)
+        for d in set(sure_i) | set(amb_max):
+            if d in sure_i:
+                l_i = sure_i[d]
+                h_i = max(sure_i[d], amb_max.get(d, -np.inf))
+            else:                                    # reached or not, depending on the choice
+                l_i = min(0.0, amb_min[d])
+                h_i = max(0.0, amb_max[d])
+            lo[d] = lo.get(d, 0.0) + l_i
+            hi[d] = hi.get(d, 0.0) + h_i
+        sure = set(sure_i) if sure is None else sure | set(sure_i)
+    return (sure or set()), lo, hi

@@ -45,6 +45,23 @@ def _d64_matrix(X: np.ndarray, C: np.ndarray) -> np.ndarray:
     return xx[:, None] - 2.0 * (X @ C.T) + cc[None, :]
 
 
+def _smallest_k(D: np.ndarray, kk: int) -> np.ndarray:
+    """int64[n, kk]: per row the column indices of the kk smallest entries in
+    ascending order, equal values by lower index -- the first kk entries of a
+    stable argsort of the row, found without sorting the whole row."""
+    n, k = D.shape
+    if kk >= k or k <= 64:
+        return np.argsort(D, axis=1, kind="stable")[:, :kk]
+    # every entry not above the row's kk-th smallest value is a candidate
+    kth = np.partition(D, kk - 1, axis=1)[:, kk - 1]
+    out = np.empty((n, kk), dtype=np.int64)
+    for i in range(n):
+        cand = np.nonzero(D[i] <= kth[i])[0]
+        order = np.lexsort((cand, D[i, cand]))
+        out[i] = cand[order[:kk]]
+    return out
+
+
 def _assign_block(X32, C32, decide, topk, full_fp32=False):
     """Assign rows X32 to centroids C32 (both float32 arrays of one token).
 
@@ -79,7 +96,7 @@ def _assign_block(X32, C32, decide, topk, full_fp32=False):
     d32_chosen = _d32.rowwise(X32, C32[a])
     if topk:
         kk = min(topk, k)
-        idx = np.argsort(D, axis=1, kind="stable")[:, :kk]
+        idx = _smallest_k(D, kk)
         tD = np.take_along_axis(D, idx, axis=1)
         if kk < topk:
             idx = np.pad(idx, ((0, 0), (0, topk - kk)), constant_values=-1)

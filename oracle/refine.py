@@ -1,5 +1,5 @@
 """Oracle for the refine phase of retrieval: MaxSim over candidate documents
-from their centroid ids, PQ codes and residual norms (Sect. 2.3, "Refine
+from their centroid ids, PQ codes and residual norms (Sect. 2.2, "Refine
 Phase: PQ-Optimized MaxSim Computation", with the document layout of the same
 section and the distance-table layout of Figure 1).
 

@@ -327,7 +327,7 @@ def tac_doc_layout(ctx: Context, assign, codes, doc_off, layout):
 
 
 def tac_maxsim(ctx: Context, Q, C_cent, codebooks, layout, doc_off, rnorm, cand, scores):
-    """Refine phase (Sect. 2.3): MaxSim of every candidate document for its query.
+    """Refine phase (Sect. 2.2): MaxSim of every candidate document for its query.
     Q float32 [B, nq, 128]; C_cent [K, 128]; codebooks [32, ksub, 4]; layout uint8 and
     doc_off int64 [D + 1] from tac_doc_layout; rnorm float32 [N] in layout token order;
     cand int32 [B, nc]; scores float32 [B, nc] (output)."""
@@ -351,7 +351,7 @@ def tac_maxsim(ctx: Context, Q, C_cent, codebooks, layout, doc_off, rnorm, cand,
 
 
 def tac_gather(ctx: Context, Q, C_cent, list_off, list_docs, D: int, kc: int, cand, scores):
-    """Gather phase (Sect. 2.3): the kd = cand.shape[1] documents of largest centroid-level
+    """Gather phase (Sect. 2.2): the kd = cand.shape[1] documents of largest centroid-level
     score per query.  Q float32 [B, nq, 128]; C_cent [K, 128]; list_off int64 [K + 1] and
     list_docs int32 from tac_ivf_build; cand int32 [B, kd] and scores float32 [B, kd] (output).
     Synchronous."""

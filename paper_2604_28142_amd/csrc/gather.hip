@@ -1,4 +1,4 @@
-// Gather phase of retrieval (Sect. 2.3, "Gather Phase: Centroid-based
+// Gather phase of retrieval (Sect. 2.2, "Gather Phase: Centroid-based
 // Document Scoring"): for each query token the kappa_c centroids of largest
 // inner product, the documents of their inverted lists with the largest
 // similarity per (token, document), the sum over the query's tokens, and the

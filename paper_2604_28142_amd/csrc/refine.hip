@@ -1,4 +1,4 @@
-// Refine phase of retrieval (Sect. 2.3, "Refine Phase: PQ-Optimized MaxSim
+// Refine phase of retrieval (Sect. 2.2, "Refine Phase: PQ-Optimized MaxSim
 // Computation"): the MaxSim score of candidate documents for a query,
 //   S(q, d) = sum_i max_{t in d} <q_i, x_t>,  x_t = c_{a_t} + rho_t * u_t,
 // read from the document layout (centroid ids, then PQ codes) with the

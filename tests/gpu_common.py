@@ -15,6 +15,7 @@ PARAMS = {
     "tiny": dict(mu=20, tau=60, eps=2, theta=10.0),
     "small": dict(mu=128, tau=256, eps=4, theta=39.0),
     "c0": dict(mu=128, tau=256, eps=4, theta=39.0),
+    "c1": dict(mu=128, tau=256, eps=4, theta=39.0),
 }
 
 

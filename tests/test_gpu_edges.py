@@ -66,15 +66,20 @@ def test_class_boundaries_and_ragged_tiles(ctx, kappa, prec):
     assert abs(J - r64["J"]) <= 1e-5 * max(r64["J"], 1e-30)
 
 
-def test_heavy_token_epoch_flush(ctx):
-    """A token with 2,500 centroids spans three packed-index epochs."""
+@pytest.mark.parametrize("n,route", [(9000, "persistent"), (6000, "split")])
+def test_heavy_token_epoch_flush(ctx, n, route):
+    """A token with 2,500 centroids spans three packed-index epochs (the last
+    one ragged).  With 9,000 rows the 16-bit screens keep it on the persistent
+    kernel; with 6,000 rows (at most 8,192) they cut it into the split route's
+    1,024-centroid chunks.  FP32 runs the persistent kernel either way."""
     rng = np.random.default_rng(11)
-    xs = clustered(rng, 6000, 400, spread=0.3)
-    C = xs[rng.choice(6000, 2500, replace=False)].copy()
-    seg_off = np.array([0, 6000], np.int64)
+    xs = clustered(rng, n, 400, spread=0.3)
+    C = xs[rng.choice(n, 2500, replace=False)].copy()
+    seg_off = np.array([0, n], np.int64)
     cent_off = np.array([0, 2500], np.int64)
     for prec in (0, 1, 2):
         a, d, J = run_assign(ctx, xs, seg_off, C, cent_off, prec)
+        assert tac.tac_assign_stats(ctx)["rows"] == n
         check_assign(xs, seg_off, C, cent_off, a, d)
 
 

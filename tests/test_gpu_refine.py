@@ -1,4 +1,4 @@
-"""Refine-phase MaxSim on the GPU (Sect. 2.3) against the oracle: ragged and
+"""Refine-phase MaxSim on the GPU (Sect. 2.2) against the oracle: ragged and
 empty documents, tokens without a centroid, out-of-range candidates, query
 lengths 1, 17 and 32, repeated candidates, determinism, and sampled scores at
 the launch shape the benchmark times (64 queries x 1,000 candidates, documents

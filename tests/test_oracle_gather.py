@@ -1,4 +1,4 @@
-"""Pins of the gather-phase oracle (Sect. 2.3): a hand-worked example with a
+"""Pins of the gather-phase oracle (Sect. 2.2): a hand-worked example with a
 tie at the centroid cut, a brute force over a document x centroid incidence
 matrix, and invariants of the definition."""
 import json
@@ -88,3 +88,67 @@ def test_scaling_list_order_and_padding():
     n = len(oracle.document_scores(Q, C, off, docs, 1))
     assert np.all(dn[n:] == -1) and np.all(np.isneginf(sn[n:])) and np.all(dn[:n] >= 0)
     assert np.all(np.diff(sn[:n]) <= 0)
+
+
+def test_score_bounds_exact_without_tolerance():
+    """With no rounding allowance and distinct similarities the admissible
+    interval collapses to the oracle's score, and every document is sure."""
+    for seed, kc in ((0, 3), (1, 10), (5, 1)):
+        Q, C, off, docs, D = _index(seed)
+        S = oracle.document_scores(Q, C, off, docs, kc)
+        sure, lo, hi = oracle.document_score_bounds(Q, C, off, docs, kc, 0.0)
+        assert sure == set(S) and set(lo) == set(S) and set(hi) == set(S)
+        for d, s in S.items():
+            assert lo[d] == hi[d] and abs(lo[d] - s) <= 1e-12 * (1 + abs(s))
+
+
+def _near_tie_index(seed, nq=2, dim=6, K=14, D=12):
+    """Centroid pairs whose similarities to every query token differ by about
+    1e-4, so that a tolerance of 1e-3 makes the centroids at the cut optional."""
+    rng = np.random.default_rng(seed)
+    base = rng.standard_normal((K // 2, dim))
+    C = np.concatenate([base, base * (1 + 1e-4 * rng.standard_normal((K // 2, 1)))])
+    Q = rng.standard_normal((nq, dim))
+    assign = rng.integers(0, K, D * 3)
+    doc = np.repeat(np.arange(D), 3)
+    off, docs = oracle.inverted_lists(assign, doc, K)
+    return Q, C, off, docs, D
+
+
+@pytest.mark.parametrize("seed,kc", [(10, 3), (11, 4), (12, 2)])
+def test_score_bounds_cover_every_admissible_choice(seed, kc):
+    """Brute force over every centroid choice an implementation with similarity
+    error up to tol may make: each choice takes the kc centroids of largest
+    perturbed similarity, so it keeps every centroid above v + 2 tol, none below
+    v - 2 tol, and exactly kc in all.  Every document score of every choice lies
+    in [lo, hi], every sure document is reached by every choice, and every
+    document some choice reaches has bounds."""
+    import itertools
+    tol = 1e-3
+    Q, C, off, docs, D = _near_tie_index(seed)
+    sure, lo, hi = oracle.document_score_bounds(Q, C, off, docs, kc, tol)
+    sims = Q @ C.T
+    K = C.shape[0]
+    per_token = []
+    for i in range(Q.shape[0]):
+        v = np.sort(sims[i])[::-1][kc - 1]
+        must = [j for j in range(K) if sims[i, j] > v + 2 * tol]
+        maybe = [j for j in range(K) if v - 2 * tol <= sims[i, j] <= v + 2 * tol]
+        assert len(maybe) >= 2, "the fixture must leave a choice at the cut"
+        choices = [set(must) | set(a) for a in itertools.combinations(maybe, kc - len(must))]
+        per_token.append(choices)
+    seen = set()
+    for combo in itertools.product(*per_token):
+        S = {}
+        for i, chosen in enumerate(combo):
+            best = {}
+            for j in chosen:
+                for d in docs[off[j]:off[j + 1]].tolist():
+                    best[d] = max(best.get(d, -np.inf), sims[i, j])
+            for d, s in best.items():
+                S[d] = S.get(d, 0.0) + s
+        assert sure <= set(S)
+        for d, s in S.items():
+            seen.add(d)
+            assert lo[d] - 1e-12 <= s <= hi[d] + 1e-12, (d, s, lo[d], hi[d])
+    assert seen == set(lo) == set(hi)

@@ -138,3 +138,44 @@ def test_empty_cluster_keeps_previous_centroid():
     C1, cnt = oracle.update(x, r["a"], C)
     assert cnt.tolist() == [3, 0]
     assert C1[1, 0] == 100.0 and C1[0, 0] == np.float32((0.0 + 0.125 + 10.0) / 3)
+
+
+def test_inertia_closed_forms():
+    """oracle.inertia (the within-cluster sum of squares of Sect. 2.1) against
+    values fixed independently of it: at the token means it equals sum_j n_j s_j
+    built from the two-pass spreads, on dyadic 1-D points it equals the
+    hand-computed sum, and a row that is its own centroid adds nothing."""
+    x, tok = datagen.make("tiny")
+    perm, seg_off, counts = oracle.group_by_token(tok, 40)
+    xs = x[perm]
+    s = oracle.spreads(xs, seg_off)
+    present = np.nonzero(counts)[0]
+    means = np.stack([xs[seg_off[j]:seg_off[j + 1]].astype(np.float64).mean(axis=0) for j in present])
+    a = np.repeat(np.arange(present.size), counts[present])
+    # the means kept in float64 (inertia promotes, so no rounding enters the comparison)
+    J = oracle.inertia(xs, a, means)
+    expect = float((counts * s).sum())
+    assert abs(J - expect) <= 1e-10 * expect
+    # 1-D dyadic points 0, 1/2, 3 against centroids 1/4 and 3: (1/4)^2 + (1/4)^2 + 0 = 1/8 exactly
+    X = np.zeros((3, 128), np.float32)
+    X[:, 0] = [0.0, 0.5, 3.0]
+    Cd = np.zeros((2, 128), np.float32)
+    Cd[:, 0] = [0.25, 3.0]
+    assert oracle.inertia(X, np.array([0, 0, 1]), Cd) == 0.125
+    # a wrong assignment costs the squared gap: point 3 to centroid 1/4 adds (11/4)^2
+    assert oracle.inertia(X, np.array([0, 0, 0]), Cd) == 0.125 + (2.75 ** 2)
+    rng = np.random.default_rng(6)
+    R = rng.standard_normal((20, 128)).astype(np.float32)
+    assert oracle.inertia(R, np.arange(20), R) == 0.0
+
+
+def test_smallest_k_is_stable_argsort_prefix():
+    """The top-k selection used for the float64 tie report equals the first k
+    entries of a stable argsort, including ties across the k-th position."""
+    from oracle.lloyd import _smallest_k
+    rng = np.random.default_rng(7)
+    D = rng.integers(0, 40, (300, 500)).astype(np.float64)   # many equal values
+    for kk in (1, 8, 37):
+        assert np.array_equal(_smallest_k(D, kk), np.argsort(D, axis=1, kind="stable")[:, :kk])
+    D2 = rng.standard_normal((50, 70))
+    assert np.array_equal(_smallest_k(D2, 8), np.argsort(D2, axis=1, kind="stable")[:, :8])

@@ -1,4 +1,4 @@
-"""Pins of the refine (MaxSim over PQ-coded documents) oracle (Sect. 2.3): a
+"""Pins of the refine (MaxSim over PQ-coded documents) oracle (Sect. 2.2): a
 hand-worked example, a brute-force decode of every token vector, and
 invariants that hold for the definition."""
 import json

@@ -1534,32 +1534,50 @@ extern "C" tac_status tac_ctx_set_static_centroids(tac_ctx ctx, const float* C_d
     if (cs != hipStreamCaptureStatusNone)
         return set_error(TAC_E_INVAL, "tac_ctx_set_static_centroids: not allowed during stream capture");
     if (ctx->sc_buf) {
-        // retired, not freed: a graph captured on this context may still address it
+        // retired, not freed: a graph captured on this context may still address
+        // it; it keeps counting against the context's limit
         ctx->ws_retired.push_back(ctx->sc_buf);
+        ctx->ws_retired_bytes += ctx->sc_bytes;
         ctx->sc_buf = nullptr;
+        ctx->sc_bytes = 0;
     }
     ctx->sc_C = nullptr;
     ctx->sc_K = 0;
     ctx->sc_prec = -1;
     if (!C_d) return TAC_OK;
     const StaticLayout L(K, precision);
+    const size_t held = ctx->ws_retired_bytes + ctx->ws_cap;
+    if (ctx->max_ws && held + L.bytes > ctx->max_ws)
+        return set_error(TAC_E_NOMEM, "prepared centroids of " + std::to_string(L.bytes) + " bytes (with " +
+                                          std::to_string(held) + " bytes already held) exceed the context limit of " +
+                                          std::to_string(ctx->max_ws));
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, L.bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return set_error(TAC_E_NOMEM, "hipMalloc of " + std::to_string(L.bytes) + " prepared-centroid bytes failed");
     }
+    // from here on every failure frees the new buffer before returning
+    auto fail = [&](hipError_t err, const char* what) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(p);
+        return hip_error(err, what);
+    };
     char* base = static_cast<char*>(p);
     unsigned* cstat = reinterpret_cast<unsigned*>(base);
-    TAC_HIP(hipMemsetAsync(cstat, 0, 4 * sizeof(unsigned), ctx->stream));
+    e = hipMemsetAsync(cstat, 0, 4 * sizeof(unsigned), ctx->stream);
+    if (e != hipSuccess) return fail(e, "hipMemsetAsync(prepared bounds)");
     const unsigned pgrid = std::min<unsigned>(grid_for(K * 32, 256), (unsigned)ctx->props_cu * 16);
     prep_centroids<<<pgrid, 256, 0, ctx->stream>>>(
         C_d, K, reinterpret_cast<float*>(base + L.cn), cstat,
         precision == TAC_FP32 ? nullptr : reinterpret_cast<unsigned short*>(base + L.chl), precision);
-    TAC_LAUNCH_CHECK("prep_centroids");
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(e, "prep_centroids");
     // synchronous: later calls may run on another stream of the context
-    TAC_HIP(hipStreamSynchronize(ctx->stream));
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail(e, "hipStreamSynchronize(prepared centroids)");
     ctx->sc_buf = p;
+    ctx->sc_bytes = L.bytes;
     ctx->sc_C = C_d;
     ctx->sc_K = K;
     ctx->sc_prec = precision;

@@ -26,7 +26,7 @@ tac_status hip_error(hipError_t e, const char* what) {
 tac_status ws_reserve(tac_ctx ctx, size_t bytes) {
     if (bytes <= ctx->ws_cap) return TAC_OK;
     // the limit bounds every allocation the context holds, replaced workspaces included
-    const size_t held = ctx->ws_retired_bytes + ctx->ws_cap;
+    const size_t held = ctx->ws_retired_bytes + ctx->ws_cap + ctx->sc_bytes;
     if (ctx->max_ws && held + bytes > ctx->max_ws)
         return set_error(TAC_E_NOMEM, "workspace of " + std::to_string(bytes) + " bytes (with " +
                                           std::to_string(held) + " bytes already held) exceeds the context limit of " +

@@ -67,6 +67,7 @@ struct tac_ctx_s {
     int64_t sc_K = 0;
     int32_t sc_prec = -1;
     void* sc_buf = nullptr;
+    size_t sc_bytes = 0;
     // optional HIP-event timing of each entry point's dominant kernel
     bool timing = false;
     hipEvent_t ev[TAC_KERNEL_SLOTS][2] = {};

@@ -212,6 +212,27 @@ tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* seg_off_d, c
                       int64_t K, int32_t precision, int32_t* assign_d, float* dist_d,
                       double* inertia_d);
 
+/* tac_assign without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops that must not call
+ * hipMalloc).  Same arguments, results and errors as tac_assign; the results
+ * are bitwise those of tac_assign.  Its workspace is one fixed 64 MiB scratch
+ * array per device inside the library (held by every device the library runs
+ * on until the process ends) instead of the context's arena, so a call whose
+ * workspace would exceed 64 MiB returns TAC_E_NOMEM without launching
+ * anything.  The need grows with N (about 60 bytes per row on the serving
+ * path), T (about 50 bytes per token) and, unless the centroids were prepared
+ * with tac_ctx_set_static_centroids for this (C_d, K, precision), with K
+ * (4 bytes per centroid in FP32, 516 in BF16, 260 in FP16): a serving batch
+ * of 100k rows over 30,522 tokens against prepared centroids needs about
+ * 10 MB.  Every call on a device shares that device's scratch: calls that
+ * overlap on one device (other streams, other contexts, other threads) race
+ * and must be serialised by the caller.  The scratch keeps the last call's
+ * contents; every part a kernel reads is written earlier in the same call. */
+tac_status tac_assign_noalloc(tac_ctx ctx, const float* x_d, const int64_t* seg_off_d, const int32_t* tok_d,
+                              int64_t N, int32_t d, int32_t T, const float* C_d, const int64_t* cent_off_d,
+                              int64_t K, int32_t precision, int32_t* assign_d, float* dist_d,
+                              double* inertia_d);
+
 /* Counters of the last tac_assign on this context.  Synchronises the stream. */
 tac_status tac_assign_stats(tac_ctx ctx, tac_assign_counters* out);
 

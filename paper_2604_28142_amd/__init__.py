@@ -5,11 +5,11 @@ this package holds the ctypes binding (``_lib``), the in-tree build script
 (``build``) and the drivers that chain the calls (``index``, ``serve``).
 """
 from ._lib import (TAC_BF16, TAC_F16, TAC_FP32, TAC_THETA_FILL_THEN_RELAX, TAC_THETA_SOFT, BudgetParams, Context,
-                   TacError, Tuning, load, pq_encode, pq_train, tac_assign, tac_assign_stats, tac_budget,
+                   TacError, Tuning, load, pq_encode, pq_train, tac_assign, tac_assign_noalloc, tac_assign_stats, tac_budget,
                    tac_budget_from_stats, tac_doc_layout, tac_gather, tac_init_centroids, tac_ivf_build, tac_maxsim, tac_residuals,
                    tac_update)
 
 __all__ = ["TAC_BF16", "TAC_F16", "TAC_FP32", "TAC_THETA_FILL_THEN_RELAX", "TAC_THETA_SOFT", "BudgetParams", "Context",
-           "TacError", "Tuning", "load", "pq_encode", "pq_train", "tac_assign", "tac_assign_stats", "tac_budget",
+           "TacError", "Tuning", "load", "pq_encode", "pq_train", "tac_assign", "tac_assign_noalloc", "tac_assign_stats", "tac_budget",
            "tac_budget_from_stats", "tac_doc_layout", "tac_gather", "tac_init_centroids", "tac_ivf_build", "tac_maxsim", "tac_residuals",
            "tac_update"]

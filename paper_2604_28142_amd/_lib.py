@@ -23,7 +23,7 @@ TAC_THETA_FILL_THEN_RELAX, TAC_THETA_SOFT = 0, 1
 _STATUS = {TAC_E_INVAL: "TAC_E_INVAL", TAC_E_INFEASIBLE: "TAC_E_INFEASIBLE", TAC_E_NOMEM: "TAC_E_NOMEM",
            TAC_E_HIP: "TAC_E_HIP", TAC_E_UNSEEN_TOKEN: "TAC_E_UNSEEN_TOKEN"}
 
-EXPORTS = ["tac_ctx_create", "tac_ctx_set_stream", "tac_ctx_destroy", "tac_last_error", "tac_budget",
+EXPORTS = ["tac_ctx_create", "tac_ctx_set_stream", "tac_ctx_destroy", "tac_last_error", "tac_budget", "tac_assign_noalloc",
            "tac_budget_from_stats",
            "tac_init_centroids", "tac_assign", "tac_assign_stats", "tac_update", "tac_residuals", "pq_train",
            "pq_encode", "tac_ctx_enable_timing", "tac_kernel_ms", "tac_ctx_set_tuning", "tac_ctx_get_tuning",
@@ -73,6 +73,7 @@ _SIGS = {
     "tac_budget_from_stats": (C.c_int, [_P, _P, _I32, _I64, C.POINTER(BudgetParams), _P, _P]),
     "tac_init_centroids": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _P, _I64, _P]),
     "tac_assign": (C.c_int, [_P, _P, _P, _P, _I64, _I32, _I32, _P, _P, _I64, _I32, _P, _P, _P]),
+    "tac_assign_noalloc": (C.c_int, [_P, _P, _P, _P, _I64, _I32, _I32, _P, _P, _I64, _I32, _P, _P, _P]),
     "tac_assign_stats": (C.c_int, [_P, C.POINTER(AssignCounters)]),
     "tac_update": (C.c_int, [_P, _P, _P, _I32, _I64, _I32, _P, _P, _I64, _P, _P]),
     "tac_residuals": (C.c_int, [_P, _P, _P, _P, _I64, _P, _I64, _I32, C.c_int, _P, _P]),
@@ -261,6 +262,22 @@ def tac_assign(ctx: Context, x, C_cent, cent_off, assign, seg_off=None, tok=None
     _check(load().tac_assign(ctx.handle, _dptr(x), _dptr(seg_off), _dptr(tok), N, d, T, _dptr(C_cent),
                              _dptr(cent_off), C_cent.shape[0], precision, _dptr(assign), _dptr(dist),
                              _dptr(inertia)))
+
+
+def tac_assign_noalloc(ctx: Context, x, C_cent, cent_off, assign, seg_off=None, tok=None,
+                       precision: int = TAC_FP32, dist=None, inertia=None):
+    """tac_assign with the library's fixed per-device scratch instead of the
+    context's workspace: allocates nothing (TacError TAC_E_NOMEM when the call
+    needs more than the scratch holds)."""
+    N, d = x.shape
+    T = cent_off.shape[0] - 1
+    _check_dtype(assign, torch.int32, "assign")
+    _check_dtype(dist, torch.float32, "dist")
+    _check_dtype(inertia, torch.float64, "inertia")
+    _check_dtype(tok, torch.int32, "tok")
+    _check(load().tac_assign_noalloc(ctx.handle, _dptr(x), _dptr(seg_off), _dptr(tok), N, d, T, _dptr(C_cent),
+                                     _dptr(cent_off), C_cent.shape[0], precision, _dptr(assign), _dptr(dist),
+                                     _dptr(inertia)))
 
 
 def tac_assign_stats(ctx: Context) -> dict:

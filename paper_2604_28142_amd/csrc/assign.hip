@@ -24,6 +24,7 @@
 // for the FP32 and BF16 screens and independent of tile shapes.
 #include <algorithm>
 #include <cfloat>
+#include <mutex>
 
 #include "tac_internal.h"
 
@@ -1584,66 +1585,98 @@ extern "C" tac_status tac_ctx_set_static_centroids(tac_ctx ctx, const float* C_d
     return TAC_OK;
 }
 
-extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* seg_off_d, const int32_t* tok_d,
-                                 int64_t N, int32_t d, int32_t T, const float* C_d, const int64_t* cent_off_d,
-                                 int64_t K, int32_t precision, int32_t* assign_d, float* dist_d, double* inertia_d) {
-    if (!ctx) return set_error(TAC_E_INVAL, "tac_assign: ctx is NULL");
-    if (d != kDim) return set_error(TAC_E_INVAL, "tac_assign: d must be 128");
-    if (N < 0 || N > INT32_MAX) return set_error(TAC_E_INVAL, "tac_assign: N out of range");
-    if (T < 1 || T > (1 << 24)) return set_error(TAC_E_INVAL, "tac_assign: T must be in [1, 2^24]");
-    if (K < 0 || K > INT32_MAX) return set_error(TAC_E_INVAL, "tac_assign: K out of range");
-    if ((seg_off_d == nullptr) == (tok_d == nullptr))
-        return set_error(TAC_E_INVAL, "tac_assign: pass exactly one of seg_off_d and tok_d");
-    if (precision != TAC_FP32 && precision != TAC_BF16 && precision != TAC_F16)
-        return set_error(TAC_E_INVAL, "tac_assign: bad precision");
-    if (!cent_off_d || (N > 0 && (!x_d || !assign_d)) || (K > 0 && !C_d))
-        return set_error(TAC_E_INVAL, "tac_assign: NULL pointer");
-    TAC_HIP(hipSetDevice(ctx->device));
-    hipStream_t s = ctx->stream;
+namespace {
 
-    const bool serve = tok_d != nullptr;
-    const int64_t ncls = 4 * (int64_t)T;  // item counts of the four classes; the split rows follow
+// Where each part of tac_assign's workspace sits (byte offsets from its base),
+// and the bytes it needs; the same plan serves the context's arena and the
+// no-allocation entry point's static scratch.
+struct AssignPlan {
+    bool serve = false, mx16 = false, prepared = false;
+    int64_t ncls = 0, nsplit_rows = 0, nred = 0;
+    size_t o_cnt = 0, o_scan = 0, o_table = 0, o_work = 0, o_cstat = 0, o_cn = 0, o_chl = 0;
+    size_t o_fbq = 0, o_fbxx = 0, o_slot = 0, o_fbcnt = 0, o_sslot = 0, o_sflag = 0, o_dist = 0, o_red = 0;
+    size_t o_k0 = 0, o_v0 = 0, o_k1 = 0, o_v1 = 0, o_sort = 0, o_seg = 0;
+    size_t bytes = 0;
+};
+
+tac_status assign_check(tac_ctx ctx, const char* fn, const float* x_d, const int64_t* seg_off_d,
+                        const int32_t* tok_d, int64_t N, int32_t d, int32_t T, const float* C_d,
+                        const int64_t* cent_off_d, int64_t K, int32_t precision, const int32_t* assign_d) {
+    const std::string f = fn;
+    if (!ctx) return set_error(TAC_E_INVAL, f + ": ctx is NULL");
+    if (d != kDim) return set_error(TAC_E_INVAL, f + ": d must be 128");
+    if (N < 0 || N > INT32_MAX) return set_error(TAC_E_INVAL, f + ": N out of range");
+    if (T < 1 || T > (1 << 24)) return set_error(TAC_E_INVAL, f + ": T must be in [1, 2^24]");
+    if (K < 0 || K > INT32_MAX) return set_error(TAC_E_INVAL, f + ": K out of range");
+    if ((seg_off_d == nullptr) == (tok_d == nullptr))
+        return set_error(TAC_E_INVAL, f + ": pass exactly one of seg_off_d and tok_d");
+    if (precision != TAC_FP32 && precision != TAC_BF16 && precision != TAC_F16)
+        return set_error(TAC_E_INVAL, f + ": bad precision");
+    if (!cent_off_d || (N > 0 && (!x_d || !assign_d)) || (K > 0 && !C_d))
+        return set_error(TAC_E_INVAL, f + ": NULL pointer");
+    return TAC_OK;
+}
+
+AssignPlan assign_plan(tac_ctx ctx, const int32_t* tok_d, int64_t N, int32_t T, const float* C_d, int64_t K,
+                       int32_t precision, const float* dist_d) {
+    AssignPlan p;
+    p.serve = tok_d != nullptr;
+    p.ncls = 4 * (int64_t)T;  // item counts of the four classes; the split rows follow
+    p.mx16 = precision != TAC_FP32;
+    // centroids declared unchanging for exactly this call's (C, K, precision): prepared once
+    p.prepared = ctx->sc_buf && ctx->sc_C == C_d && ctx->sc_K == K && ctx->sc_prec == precision;
     Carve cv;
-    const size_t o_cnt = cv.take<int64_t>(ncls + T + 1);
-    const size_t o_scan = cv.take<char>(scan_scratch_bytes(ncls + T));
+    p.o_cnt = cv.take<int64_t>(p.ncls + T + 1);
+    p.o_scan = cv.take<char>(scan_scratch_bytes(p.ncls + T));
     // items: at most one partial tile per token, plus the split route's (tile, chunk) items
     constexpr int64_t kSplitTiles = (kSplitMaxRows + kBTileRows - 1) / kBTileRows;
-    const size_t o_table =
-        cv.take<ItemDesc>(N / 256 + (int64_t)T + kSplitTiles * (K / kSplitChunk + K / kSplitMinKappa) + 1);
-    const size_t o_work = cv.take<unsigned long long>(1);
-    const size_t o_cstat = cv.take<unsigned>(4);
-    const bool mx16 = precision != TAC_FP32;
-    // centroids declared unchanging for exactly this call's (C, K, precision): prepared once
-    const bool prepared = ctx->sc_buf && ctx->sc_C == C_d && ctx->sc_K == K && ctx->sc_prec == precision;
-    const size_t o_cn = prepared ? 0 : cv.take<float>(K + 1);
-    const size_t o_chl =
-        mx16 && !prepared ? cv.take<unsigned short>((K + 1) * (precision == TAC_BF16 ? 2 : 1) * kDim) : 0;
-    const size_t o_fbq = cv.take<int32_t>(N + 1);
-    const size_t o_fbxx = cv.take<float>(N + 1);
-    const size_t o_slot = cv.take<unsigned long long>(N + 1);
-    const size_t o_fbcnt = cv.take<int32_t>((int64_t)T + 1);
+    p.o_table = cv.take<ItemDesc>(N / 256 + (int64_t)T + kSplitTiles * (K / kSplitChunk + K / kSplitMinKappa) + 1);
+    p.o_work = cv.take<unsigned long long>(1);
+    p.o_cstat = cv.take<unsigned>(4);
+    p.o_cn = p.prepared ? 0 : cv.take<float>(K + 1);
+    p.o_chl = p.mx16 && !p.prepared ? cv.take<unsigned short>((K + 1) * (precision == TAC_BF16 ? 2 : 1) * kDim) : 0;
+    p.o_fbq = cv.take<int32_t>(N + 1);
+    p.o_fbxx = cv.take<float>(N + 1);
+    p.o_slot = cv.take<unsigned long long>(N + 1);
+    p.o_fbcnt = cv.take<int32_t>((int64_t)T + 1);
     // split-route row slots: each split token has at most kSplitMaxRows rows and kSplitMinKappa centroids
-    const int64_t nsplit_rows = mx16 ? std::min<int64_t>(N, (K / kSplitMinKappa) * kSplitMaxRows) : 0;
-    const size_t o_sslot = cv.take<unsigned long long>(nsplit_rows + 1);
-    const size_t o_sflag = cv.take<int32_t>(nsplit_rows + 1);
-    const size_t o_dist = dist_d ? 0 : cv.take<float>(N + 1);
-    const int64_t nred = (N + kRedThreads * kRedItems - 1) / (kRedThreads * kRedItems);
-    const size_t o_red = cv.take<double>(nred + 1);
-    size_t o_k0 = 0, o_v0 = 0, o_k1 = 0, o_v1 = 0, o_sort = 0, o_seg = 0;
-    if (serve) {
-        o_k0 = cv.take<uint32_t>(N + 1);
-        o_v0 = cv.take<int32_t>(N + 1);
-        o_k1 = cv.take<uint32_t>(N + 1);
-        o_v1 = cv.take<int32_t>(N + 1);
-        o_sort = cv.take<char>(radix_sort_scratch_bytes(N));
-        o_seg = cv.take<int64_t>((int64_t)T + 2);
+    p.nsplit_rows = p.mx16 ? std::min<int64_t>(N, (K / kSplitMinKappa) * kSplitMaxRows) : 0;
+    p.o_sslot = cv.take<unsigned long long>(p.nsplit_rows + 1);
+    p.o_sflag = cv.take<int32_t>(p.nsplit_rows + 1);
+    p.o_dist = dist_d ? 0 : cv.take<float>(N + 1);
+    p.nred = (N + kRedThreads * kRedItems - 1) / (kRedThreads * kRedItems);
+    p.o_red = cv.take<double>(p.nred + 1);
+    if (p.serve) {
+        p.o_k0 = cv.take<uint32_t>(N + 1);
+        p.o_v0 = cv.take<int32_t>(N + 1);
+        p.o_k1 = cv.take<uint32_t>(N + 1);
+        p.o_v1 = cv.take<int32_t>(N + 1);
+        p.o_sort = cv.take<char>(radix_sort_scratch_bytes(N));
+        p.o_seg = cv.take<int64_t>((int64_t)T + 2);
     }
-    tac_status st = ws_reserve(ctx, cv.off);
-    if (st != TAC_OK) return st;
-    float* dist = dist_d ? dist_d : ws_at<float>(ctx, o_dist);
-    unsigned* cstat = ws_at<unsigned>(ctx, o_cstat);
-    float* cn = ws_at<float>(ctx, o_cn);
-    unsigned short* chl = mx16 ? ws_at<unsigned short>(ctx, o_chl) : nullptr;
+    p.bytes = cv.off;
+    return p;
+}
+
+template <class T>
+T* at(char* base, size_t off) {
+    return reinterpret_cast<T*>(base + off);
+}
+
+// Everything tac_assign enqueues, with its workspace at `ws` (laid out by `pl`).
+// Every part of the workspace that a kernel reads is written earlier in the
+// same call, so the workspace may hold anything on entry.
+tac_status assign_run(tac_ctx ctx, char* ws, const AssignPlan& pl, const float* x_d, const int64_t* seg_off_d,
+                      const int32_t* tok_d, int64_t N, int32_t T, const float* C_d, const int64_t* cent_off_d,
+                      int64_t K, int32_t precision, int32_t* assign_d, float* dist_d, double* inertia_d) {
+    hipStream_t s = ctx->stream;
+    const bool serve = pl.serve, mx16 = pl.mx16, prepared = pl.prepared;
+    const int64_t ncls = pl.ncls;
+    tac_status st = TAC_OK;
+    float* dist = dist_d ? dist_d : at<float>(ws, pl.o_dist);
+    unsigned* cstat = at<unsigned>(ws, pl.o_cstat);
+    float* cn = at<float>(ws, pl.o_cn);
+    unsigned short* chl = mx16 ? at<unsigned short>(ws, pl.o_chl) : nullptr;
     const unsigned* cstat_static = nullptr;
     if (prepared) {
         const StaticLayout L(K, precision);
@@ -1652,19 +1685,19 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
         cn = reinterpret_cast<float*>(base + L.cn);
         chl = mx16 ? reinterpret_cast<unsigned short*>(base + L.chl) : nullptr;
     }
-    int64_t* cnt = ws_at<int64_t>(ctx, o_cnt);
-    unsigned long long* work = ws_at<unsigned long long>(ctx, o_work);
+    int64_t* cnt = at<int64_t>(ws, pl.o_cnt);
+    unsigned long long* work = at<unsigned long long>(ws, pl.o_work);
 
     const int64_t* seg = seg_off_d;
     const int32_t* rowmap = nullptr;
     reset_call<<<1, 1, 0, s>>>(work, ctx->counters, cstat, cstat_static);
     TAC_LAUNCH_CHECK("reset_call");
     if (serve) {
-        int64_t* sseg = ws_at<int64_t>(ctx, o_seg);
-        uint32_t* k0 = ws_at<uint32_t>(ctx, o_k0);
-        int32_t* v0 = ws_at<int32_t>(ctx, o_v0);
-        uint32_t* k1 = ws_at<uint32_t>(ctx, o_k1);
-        int32_t* v1 = ws_at<int32_t>(ctx, o_v1);
+        int64_t* sseg = at<int64_t>(ws, pl.o_seg);
+        uint32_t* k0 = at<uint32_t>(ws, pl.o_k0);
+        int32_t* v0 = at<int32_t>(ws, pl.o_v0);
+        uint32_t* k1 = at<uint32_t>(ws, pl.o_k1);
+        int32_t* v1 = at<int32_t>(ws, pl.o_v1);
         if (N > 0) {
             serve_keys<<<grid_for(N, 256), 256, 0, s>>>(tok_d, N, T, k0, assign_d, dist, ctx->counters);
             TAC_LAUNCH_CHECK("serve_keys");
@@ -1672,7 +1705,7 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
         int bits = 1;
         while (bits < 31 && (int64_t(1) << bits) < (int64_t)T + 1) ++bits;
         int in1 = 0;
-        st = radix_sort(s, N, bits, k0, v0, k1, v1, nullptr, ws_at<void>(ctx, o_sort), &in1);
+        st = radix_sort(s, N, bits, k0, v0, k1, v1, nullptr, at<void>(ws, pl.o_sort), &in1);
         if (st != TAC_OK) return st;
         serve_offsets<<<grid_for(N + 1, 256), 256, 0, s>>>(in1 ? k1 : k0, N, T, sseg);
         TAC_LAUNCH_CHECK("serve_offsets");
@@ -1686,12 +1719,12 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
                                                   ctx->tuning.heavy_kappa, mx16 ? kSplitMinKappa : 0,
                                                   mx16 ? kBTileRows : kTileRows, threads, cnt, cstat + 1);
     TAC_LAUNCH_CHECK("plan_count");
-    st = exclusive_scan_i64(s, cnt, cnt, ncls + T, ws_at<void>(ctx, o_scan));
+    st = exclusive_scan_i64(s, cnt, cnt, ncls + T, at<void>(ws, pl.o_scan));
     if (st != TAC_OK) return st;
-    ItemDesc* table = ws_at<ItemDesc>(ctx, o_table);
+    ItemDesc* table = at<ItemDesc>(ws, pl.o_table);
     SplitArgs S;
-    S.slot = ws_at<unsigned long long>(ctx, o_sslot);
-    S.flag = ws_at<int32_t>(ctx, o_sflag);
+    S.slot = at<unsigned long long>(ws, pl.o_sslot);
+    S.flag = at<int32_t>(ws, pl.o_sflag);
     plan_fill<<<grid_for(ncls, 256), 256, 0, s>>>(cnt, seg, cent_off_d, T, mx16 ? kBTileRows : kTileRows, threads,
                                                     table, S.slot, S.flag);
     TAC_LAUNCH_CHECK("plan_fill");
@@ -1716,10 +1749,10 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     P.work = work;
     P.assign = assign_d;
     P.dist = dist;
-    P.fbq = ws_at<int32_t>(ctx, o_fbq);
-    P.fbxx = ws_at<float>(ctx, o_fbxx);
-    P.fbslot = ws_at<unsigned long long>(ctx, o_slot);
-    P.fbcnt = ws_at<int32_t>(ctx, o_fbcnt);
+    P.fbq = at<int32_t>(ws, pl.o_fbq);
+    P.fbxx = at<float>(ws, pl.o_fbxx);
+    P.fbslot = at<unsigned long long>(ws, pl.o_slot);
+    P.fbcnt = at<int32_t>(ws, pl.o_fbcnt);
     fb_zero<<<grid_for(T, 256), 256, 0, s>>>(P.fbcnt, T);
     TAC_LAUNCH_CHECK("fb_zero");
     P.counters = ctx->counters;
@@ -1776,7 +1809,7 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
     int64_t* woff = cnt;
     fb_plan<<<grid_for(T, 256), 256, 0, s>>>(P.fbcnt, cent_off_d, T, woff);
     TAC_LAUNCH_CHECK("fb_plan");
-    st = exclusive_scan_i64(s, woff, woff, T, ws_at<void>(ctx, o_scan));
+    st = exclusive_scan_i64(s, woff, woff, T, at<void>(ws, pl.o_scan));
     if (st != TAC_OK) return st;
     fb_screen<<<(unsigned)ctx->props_cu * 2, 256, 0, s>>>(x_d, seg, cent_off_d, T, C_d, cn, cstat, woff, P.fbcnt, P.fbq,
                                                         P.fbxx, P.fbslot);
@@ -1785,15 +1818,77 @@ extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* s
                                                                                         P.fbslot, assign_d, dist);
     TAC_LAUNCH_CHECK("fb_final");
     if (inertia_d) {
-        double* part = ws_at<double>(ctx, o_red);
-        if (nred > 0) {
-            inertia_partial<<<(unsigned)nred, kRedThreads, 0, s>>>(dist, N, part);
+        double* part = at<double>(ws, pl.o_red);
+        if (pl.nred > 0) {
+            inertia_partial<<<(unsigned)pl.nred, kRedThreads, 0, s>>>(dist, N, part);
             TAC_LAUNCH_CHECK("inertia_partial");
         }
-        inertia_final<<<1, kRedThreads, 0, s>>>(part, nred, inertia_d);
+        inertia_final<<<1, kRedThreads, 0, s>>>(part, pl.nred, inertia_d);
         TAC_LAUNCH_CHECK("inertia_final");
     }
     return TAC_OK;
+}
+
+// ---- the no-allocation entry point's scratch --------------------------------
+// One fixed array per device (each device that loads the library holds its own
+// copy until the process ends).  Host code never passes the array's name to a
+// kernel or a copy: it is a host-side stand-in there, and the device address
+// comes from hipGetSymbolAddress, once per device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+__device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+tac_status scratch_ptr(int device, char** out) {
+    if (device < 0 || device >= kMaxDevices) return set_error(TAC_E_INVAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        TAC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));  // the caller made `device` current
+        if (!p) return set_error(TAC_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[device] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return TAC_OK;
+}
+
+}  // namespace
+
+extern "C" tac_status tac_assign(tac_ctx ctx, const float* x_d, const int64_t* seg_off_d, const int32_t* tok_d,
+                                 int64_t N, int32_t d, int32_t T, const float* C_d, const int64_t* cent_off_d,
+                                 int64_t K, int32_t precision, int32_t* assign_d, float* dist_d, double* inertia_d) {
+    tac_status st = assign_check(ctx, "tac_assign", x_d, seg_off_d, tok_d, N, d, T, C_d, cent_off_d, K, precision,
+                                 assign_d);
+    if (st != TAC_OK) return st;
+    TAC_HIP(hipSetDevice(ctx->device));
+    const AssignPlan pl = assign_plan(ctx, tok_d, N, T, C_d, K, precision, dist_d);
+    st = ws_reserve(ctx, pl.bytes);
+    if (st != TAC_OK) return st;
+    return assign_run(ctx, static_cast<char*>(ctx->ws), pl, x_d, seg_off_d, tok_d, N, T, C_d, cent_off_d, K,
+                      precision, assign_d, dist_d, inertia_d);
+}
+
+extern "C" tac_status tac_assign_noalloc(tac_ctx ctx, const float* x_d, const int64_t* seg_off_d,
+                                         const int32_t* tok_d, int64_t N, int32_t d, int32_t T, const float* C_d,
+                                         const int64_t* cent_off_d, int64_t K, int32_t precision, int32_t* assign_d,
+                                         float* dist_d, double* inertia_d) {
+    tac_status st = assign_check(ctx, "tac_assign_noalloc", x_d, seg_off_d, tok_d, N, d, T, C_d, cent_off_d, K,
+                                 precision, assign_d);
+    if (st != TAC_OK) return st;
+    TAC_HIP(hipSetDevice(ctx->device));
+    const AssignPlan pl = assign_plan(ctx, tok_d, N, T, C_d, K, precision, dist_d);
+    if (pl.bytes > kScratchBytes)
+        return set_error(TAC_E_NOMEM, "tac_assign_noalloc: this call needs " + std::to_string(pl.bytes) +
+                                          " bytes of scratch, more than the fixed " + std::to_string(kScratchBytes) +
+                                          " (fewer rows, fewer tokens, or centroids prepared with "
+                                          "tac_ctx_set_static_centroids lower the need)");
+    char* base = nullptr;
+    st = scratch_ptr(ctx->device, &base);
+    if (st != TAC_OK) return st;
+    return assign_run(ctx, base, pl, x_d, seg_off_d, tok_d, N, T, C_d, cent_off_d, K, precision, assign_d, dist_d,
+                      inertia_d);
 }
 
 extern "C" tac_status tac_assign_stats(tac_ctx ctx, tac_assign_counters* out) {

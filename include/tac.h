@@ -120,11 +120,16 @@ tac_status tac_kernel_ms(tac_ctx ctx, int slot, float* ms);
  *  heavy_kappa       tokens with at least this many centroids are scheduled
  *                    first in the persistent work queue (default 1024)
  *  groups_per_cu     persistent work-groups per compute unit; 0 = as many as
- *                    fit (default 0) */
+ *                    fit (default 0)
+ *  tile_blocks       the 16-bit screens' tile shape: column blocks of 16 rows
+ *                    per wave, so a work item is 64 * tile_blocks rows of one
+ *                    token; 3, 4 or 5 (each is compiled), 0 = 5 (default 0).
+ *                    The FP32 screen keeps its 512-row items. */
 typedef struct {
     int32_t direct_max_kappa;
     int32_t heavy_kappa;
     int32_t groups_per_cu;
+    int32_t tile_blocks;
 } tac_tuning;
 tac_status tac_ctx_set_tuning(tac_ctx ctx, const tac_tuning* tuning);
 tac_status tac_ctx_get_tuning(tac_ctx ctx, tac_tuning* tuning);

@@ -1,11 +1,15 @@
 """Measured launch tuning of tac_assign, cached per workload.
 
-The assignment kernel's launch has three knobs (``tac_tuning`` in the C ABI):
-which tokens skip the matrix-core screen (``direct_max_kappa``), which tokens
-the persistent work queue hands out first (``heavy_kappa``), and how many
-persistent work-groups share a compute unit (``groups_per_cu``).  None of them
-changes a result, only the time, and the best values depend on the segment
-structure (how rows and centroids spread over tokens) and on the device.
+The assignment kernel's launch has four knobs (``tac_tuning`` in the C ABI):
+the 16-bit screens' tile shape (``tile_blocks``: column blocks of 16 rows per
+wave, i.e. 192-, 256- or 320-row work items, each a separately compiled
+kernel), which tokens skip the matrix-core screen (``direct_max_kappa``),
+which tokens the persistent work queue hands out first (``heavy_kappa``), and
+how many persistent work-groups share a compute unit (``groups_per_cu``).
+None of them changes a result, only the time, and the best values depend on
+the segment structure (how rows and centroids spread over tokens) and on the
+device.  A larger tile restages each centroid for more rows; a smaller one
+holds fewer registers and spreads a token's rows over more compute units.
 
 ``tune_assign`` measures candidate settings on the caller's resident buffers by
 coordinate search (one knob at a time, the others held at their best so far),
@@ -27,8 +31,9 @@ import torch
 
 from . import _lib as L
 
-DEFAULT = {"direct_max_kappa": 4, "heavy_kappa": 1024, "groups_per_cu": 0}
+DEFAULT = {"tile_blocks": 5, "direct_max_kappa": 4, "heavy_kappa": 1024, "groups_per_cu": 0}
 SPACE = {
+    "tile_blocks": [5, 4, 3],
     "direct_max_kappa": [0, 2, 4, 8, 16],
     "heavy_kappa": [128, 512, 1024, 4096],
     "groups_per_cu": [0, 1],
@@ -96,7 +101,9 @@ def tune_assign(ctx: L.Context, xs: torch.Tensor, C: torch.Tensor, cent_off: tor
     The chosen tuning is set on `ctx` when `apply` is true.  Candidates whose
     assignments differ from the first candidate's raise RuntimeError (the
     tuning must never change a result)."""
-    space = space or SPACE
+    space = dict(space or SPACE)
+    if precision == L.TAC_FP32:
+        space.pop("tile_blocks", None)  # the FP32 screen has one tile shape
     cache_path = cache_path or default_cache_path()
     so = np.asarray(host_seg_off if host_seg_off is not None else seg_off.cpu().numpy())
     co = np.asarray(host_cent_off if host_cent_off is not None else cent_off.cpu().numpy())

@@ -635,9 +635,9 @@ __device__ __forceinline__ void epoch_flush(Key (&el)[NB][4], unsigned* glist, i
 //   dot error y.c - f16(y).f16(c) = f16(y).dc + dy.f16(c) + dy.dc is bounded by
 //   Cauchy-Schwarz with the measured norms ||dy|| (per row) and max ||dc||.
 template <int PREC, int NB, int LK, bool SPLIT = false>
-__device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t row0, int64_t s1,
-                                            const unsigned* glist, float beta, float cnmax, float cmax, int lane,
-                                            const float* sdx = nullptr, SplitArgs S = {}) {
+__device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t row0, int64_t s1, int64_t klo,
+                                            int64_t khi, const unsigned* glist, float beta, float cnmax, float cmax,
+                                            int lane, const float* sdx = nullptr, SplitArgs S = {}) {
     const double u = 5.9604644775390625e-8;  // 2^-24
     const double g130 = 130.0 * u / (1.0 - 130.0 * u);
     const double g260 = 260.0 * u / (1.0 - 260.0 * u);
@@ -661,7 +661,8 @@ __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t 
             const unsigned* sl = wlist + nb * 8 * 64 + 16 * g + c;
             const float G0 = __uint_as_float(sl[0]);
             const int I0 = (int)sl[4 * 64];
-            if (I0 >= 0 && (G0 < g0 || (G0 == g0 && I0 < i0))) {
+            // a candidate outside the item's centroids (an empty slot) is no candidate
+            if (I0 >= klo && I0 < khi && (G0 < g0 || (G0 == g0 && I0 < i0))) {
                 g0 = G0;
                 i0 = I0;
             }
@@ -715,7 +716,7 @@ __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t 
                 for (int e = 0; e < LK; ++e) {
                     const int I = (int)sl[(4 + e) * 64];
                     const double G = (double)__uint_as_float(sl[e * 64]);
-                    if (I < 0 || I == i0 || (G + shift) * (1.0 - g130) > (double)bd) continue;
+                    if (I < klo || I >= khi || I == i0 || (G + shift) * (1.0 - g130) > (double)bd) continue;
                     const float d = dist((int64_t)I, nullptr);
                     if (d < bd || (d == bd && I < bi)) {
                         bd = d;
@@ -865,7 +866,7 @@ __device__ __forceinline__ void screen_item_fp32(const Params& P, const ItemDesc
         if (st + 1 < nst) store_stage(buf ^ 1, pf, pcn);
         __syncthreads();
     }
-    finish_item<TAC_FP32, NB, 4>(P, j, row0, s1, glist, beta, cnmax, cmax, lane);
+    finish_item<TAC_FP32, NB, 4>(P, j, row0, s1, k0, k0 + kc, glist, beta, cnmax, cmax, lane);
 }
 
 // ---- 16-bit screens: 4 waves (one per SIMD) x 5 column blocks of 16 rows = 320 rows per item ----
@@ -882,7 +883,11 @@ __device__ __forceinline__ void screen_item_fp32(const Params& P, const ItemDesc
 // LDS, vector) overlap.
 constexpr int kBThreads = 256;
 constexpr int kBWaves = kBThreads / 64;
+// column blocks (16 rows each) per wave: the item's row tile is 64 * NB rows.
+// Each NB in [kBNBMin, kBNB] is compiled; the launch takes the context's
+// tuning (tile_blocks), which the autotuner chooses by measurement.
 constexpr int kBNB = 5;
+constexpr int kBNBMin = 3;
 // Per-lane list length of the 16-bit screens.  For BF16 a top-3 costs one med3
 // less per screen value than a top-4 and its certificate rarely fails either
 // way; the FP16 screen's wider error bound makes a top-3 fail about five times
@@ -975,9 +980,9 @@ struct BBlock<TAC_F16> {
     f4 cb;
 };
 
-template <int PREC, bool SPLIT = false>
+template <int PREC, int NB, bool SPLIT = false>
 __device__ __forceinline__ void screen_item_mx(const Params& P, const ItemDesc& D, unsigned* lds, SplitArgs S = {}) {
-    constexpr int NB = kBNB;
+    static_assert(NB >= kBNBMin && NB <= kBNB, "a compiled tile");
     constexpr int SC = StageGeom<PREC>::kCents;
     constexpr int BPS = StageGeom<PREC>::kBlocks;
     constexpr int RW = StageGeom<PREC>::kRowBytes / 4;  // words per staged row
@@ -985,11 +990,17 @@ __device__ __forceinline__ void screen_item_mx(const Params& P, const ItemDesc& 
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4;
     const int col = lane & 15;
-    const int32_t j = D.jc & 0xFFFFFF;
-    const int64_t s1 = D.s1;
-    const int64_t k0 = D.k0;
-    const int kc = D.kc;
-    const int64_t row0 = D.row0 + wave * (NB * 16);
+    // the item's fields are the same on every lane: held as scalars
+    auto uni64 = [](int64_t v) {
+        const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(uint64_t)v);
+        const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((uint64_t)v >> 32));
+        return (int64_t)(((uint64_t)hi << 32) | lo);
+    };
+    const int32_t j = __builtin_amdgcn_readfirstlane(D.jc & 0xFFFFFF);
+    const int64_t s1 = uni64(D.s1);
+    const int64_t k0 = uni64(D.k0);
+    const int kc = __builtin_amdgcn_readfirstlane(D.kc);
+    const int64_t row0 = uni64(D.row0) + wave * (NB * 16);
     const float cnmax = __uint_as_float(P.cstat[0]) * (1.0f + 1e-5f);
     const float cmax = sqrtf(cnmax) * (1.0f + 1e-6f);
 
@@ -1175,10 +1186,10 @@ __device__ __forceinline__ void screen_item_mx(const Params& P, const ItemDesc& 
             flush_if(blk - 1);
         }
     }
-    finish_item<PREC, NB, kBLK<PREC>, SPLIT>(P, j, row0, s1, glist, beta, cnmax, cmax, lane, sdx, S);
+    finish_item<PREC, NB, kBLK<PREC>, SPLIT>(P, j, row0, s1, k0, k0 + kc, glist, beta, cnmax, cmax, lane, sdx, S);
 }
 
-template <int PREC>
+template <int PREC, int NB = kBNB>
 __global__ void __launch_bounds__(PREC == TAC_FP32 ? kThreads : kBThreads) assign_main(Params P) {
     // All shared memory is dynamic so that it starts 16-byte aligned (a static
     // variable in front of it would shift every 16-byte LDS access off alignment).
@@ -1216,7 +1227,7 @@ __global__ void __launch_bounds__(PREC == TAC_FP32 ? kThreads : kBThreads) assig
             if (cls == 2)
                 direct_item<kBThreads>(P, D);
             else
-                screen_item_mx<PREC>(P, D, lds);
+                screen_item_mx<PREC, NB>(P, D, lds);
         } else {
             if (cls == 2)
                 direct_item<kThreads>(P, D);
@@ -1236,13 +1247,13 @@ __global__ void __launch_bounds__(PREC == TAC_FP32 ? kThreads : kBThreads) assig
 // The split route's work items (items item_off[3T] .. item_off[4T]), one per
 // work-group at a time in a grid-stride loop: the same 16-bit screen and
 // finish as the persistent kernel, on one row tile and one centroid chunk.
-template <int PREC>
+template <int PREC, int NB>
 __global__ void __launch_bounds__(kBThreads) assign_split(Params P, SplitArgs S) {
     extern __shared__ __attribute__((aligned(16))) unsigned lds[];
     const int64_t b = P.item_off[3 * (int64_t)P.T], e = P.item_off[4 * (int64_t)P.T];
     for (int64_t t = b + blockIdx.x; t < e; t += gridDim.x) {
         const ItemDesc D = P.desc[t];
-        screen_item_mx<PREC, true>(P, D, lds, S);
+        screen_item_mx<PREC, NB, true>(P, D, lds, S);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();  // every wave is done with this item's LDS
     }
@@ -1503,6 +1514,24 @@ unsigned grid_for(int64_t work, int per_block) {
 }
 
 
+// The compiled 16-bit screen kernels of one precision and row tile.
+struct Kernels16 {
+    void (*main)(Params);
+    void (*split)(Params, SplitArgs);
+};
+template <int PREC>
+Kernels16 kernels16_of(int nb) {
+    static_assert(kBNBMin == 3 && kBNB == 5, "one case per compiled tile");
+    switch (nb) {
+        case 3: return {assign_main<PREC, 3>, assign_split<PREC, 3>};
+        case 4: return {assign_main<PREC, 4>, assign_split<PREC, 4>};
+        default: return {assign_main<PREC, 5>, assign_split<PREC, 5>};
+    }
+}
+Kernels16 kernels16(int precision, int nb) {
+    return precision == TAC_BF16 ? kernels16_of<TAC_BF16>(nb) : kernels16_of<TAC_F16>(nb);
+}
+
 }  // namespace
 
 }  // namespace tac
@@ -1629,7 +1658,8 @@ AssignPlan assign_plan(tac_ctx ctx, const int32_t* tok_d, int64_t N, int32_t T, 
     p.o_cnt = cv.take<int64_t>(p.ncls + T + 1);
     p.o_scan = cv.take<char>(scan_scratch_bytes(p.ncls + T));
     // items: at most one partial tile per token, plus the split route's (tile, chunk) items
-    constexpr int64_t kSplitTiles = (kSplitMaxRows + kBTileRows - 1) / kBTileRows;
+    constexpr int64_t kMinTileRows = kBWaves * kBNBMin * 16;
+    constexpr int64_t kSplitTiles = (kSplitMaxRows + kMinTileRows - 1) / kMinTileRows;
     p.o_table = cv.take<ItemDesc>(N / 256 + (int64_t)T + kSplitTiles * (K / kSplitChunk + K / kSplitMinKappa) + 1);
     p.o_work = cv.take<unsigned long long>(1);
     p.o_cstat = cv.take<unsigned>(4);
@@ -1713,11 +1743,14 @@ tac_status assign_run(tac_ctx ctx, char* ws, const AssignPlan& pl, const float* 
         rowmap = in1 ? v1 : v0;
     }
     const int threads = mx16 ? kBThreads : kThreads;
+    // the 16-bit screens' row tile: tile_blocks column blocks of 16 rows per wave
+    const int nb16 = ctx->tuning.tile_blocks >= kBNBMin && ctx->tuning.tile_blocks <= kBNB ? ctx->tuning.tile_blocks : kBNB;
+    const int screen_rows = mx16 ? kBWaves * nb16 * 16 : kTileRows;
     // dynamic LDS: the kernel's tiles plus the work-item slots
     const size_t lds_bytes = (mx16 ? kBLdsBytes : kLdsBytes) + kSlotBytes;
     plan_count<<<grid_for(T, 256), 256, 0, s>>>(seg, cent_off_d, T, ctx->tuning.direct_max_kappa,
                                                   ctx->tuning.heavy_kappa, mx16 ? kSplitMinKappa : 0,
-                                                  mx16 ? kBTileRows : kTileRows, threads, cnt, cstat + 1);
+                                                  screen_rows, threads, cnt, cstat + 1);
     TAC_LAUNCH_CHECK("plan_count");
     st = exclusive_scan_i64(s, cnt, cnt, ncls + T, at<void>(ws, pl.o_scan));
     if (st != TAC_OK) return st;
@@ -1725,7 +1758,7 @@ tac_status assign_run(tac_ctx ctx, char* ws, const AssignPlan& pl, const float* 
     SplitArgs S;
     S.slot = at<unsigned long long>(ws, pl.o_sslot);
     S.flag = at<int32_t>(ws, pl.o_sflag);
-    plan_fill<<<grid_for(ncls, 256), 256, 0, s>>>(cnt, seg, cent_off_d, T, mx16 ? kBTileRows : kTileRows, threads,
+    plan_fill<<<grid_for(ncls, 256), 256, 0, s>>>(cnt, seg, cent_off_d, T, screen_rows, threads,
                                                     table, S.slot, S.flag);
     TAC_LAUNCH_CHECK("plan_fill");
     if (K > 0 && !prepared) {
@@ -1761,14 +1794,14 @@ tac_status assign_run(tac_ctx ctx, char* ws, const AssignPlan& pl, const float* 
     if (!occ[0]) {
         TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_FP32>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)(kLdsBytes + kSlotBytes)));
-        TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_BF16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(kBLdsBytes + kSlotBytes)));
-        TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_F16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(kBLdsBytes + kSlotBytes)));
-        TAC_HIP(hipFuncSetAttribute((const void*)assign_split<TAC_BF16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)kBLdsBytes));
-        TAC_HIP(hipFuncSetAttribute((const void*)assign_split<TAC_F16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)kBLdsBytes));
+        for (int pr = TAC_BF16; pr <= TAC_F16; ++pr)
+            for (int nb = kBNBMin; nb <= kBNB; ++nb) {
+                const Kernels16 k = kernels16(pr, nb);
+                TAC_HIP(hipFuncSetAttribute((const void*)k.main, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)(kBLdsBytes + kSlotBytes)));
+                TAC_HIP(hipFuncSetAttribute((const void*)k.split, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)kBLdsBytes));
+            }
         TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], assign_main<TAC_BF16>, kBThreads,
                                                              kBLdsBytes + kSlotBytes));
         TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], assign_main<TAC_F16>, kBThreads,
@@ -1784,22 +1817,16 @@ tac_status assign_run(tac_ctx ctx, char* ws, const AssignPlan& pl, const float* 
     if (precision == TAC_FP32) {
         assign_main<TAC_FP32><<<grid, threads, lds_bytes, s>>>(P);
         TAC_LAUNCH_CHECK("assign_main<fp32>");
-    } else if (precision == TAC_BF16) {
-        assign_main<TAC_BF16><<<grid, threads, lds_bytes, s>>>(P);
-        TAC_LAUNCH_CHECK("assign_main<bf16>");
     } else {
-        assign_main<TAC_F16><<<grid, threads, lds_bytes, s>>>(P);
-        TAC_LAUNCH_CHECK("assign_main<f16>");
+        kernels16(precision, nb16).main<<<grid, threads, lds_bytes, s>>>(P);
+        TAC_LAUNCH_CHECK(precision == TAC_BF16 ? "assign_main<bf16>" : "assign_main<f16>");
     }
     time_stop(ctx, TAC_SLOT_ASSIGN);
     if (mx16) {
         // the split route (no work items outside serving-sized batches: then the
         // launches find an empty item range and return)
         const unsigned sgrid = (unsigned)ctx->props_cu;
-        if (precision == TAC_BF16)
-            assign_split<TAC_BF16><<<sgrid, kBThreads, kBLdsBytes, s>>>(P, S);
-        else
-            assign_split<TAC_F16><<<sgrid, kBThreads, kBLdsBytes, s>>>(P, S);
+        kernels16(precision, nb16).split<<<sgrid, kBThreads, kBLdsBytes, s>>>(P, S);
         TAC_LAUNCH_CHECK("assign_split");
         split_resolve<<<sgrid, 128, 0, s>>>(cnt, table, T, rowmap, S.slot, S.flag, assign_d, dist, ctx->counters);
         TAC_LAUNCH_CHECK("split_resolve");

@@ -38,8 +38,13 @@ class TacError(RuntimeError):
 
 
 class BudgetParams(C.Structure):
+    """tac_budget_params; fields left out take the defaults of Sect. 2.1's
+    settings (mu 128, tau 256, eps 4, theta 39, fill-then-relax)."""
     _fields_ = [("mu", C.c_int64), ("tau", C.c_int64), ("eps", C.c_int64), ("theta", C.c_double),
                 ("theta_policy", C.c_int32)]
+
+    def __init__(self, mu: int = 128, tau: int = 256, eps: int = 4, theta: float = 39.0, theta_policy: int = 0):
+        super().__init__(mu, tau, eps, theta, theta_policy)
 
 
 class Tuning(C.Structure):

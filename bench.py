@@ -8,9 +8,18 @@ residual + PQ encoding of every vector.
 
 Metric (vectors assigned per second per Lloyd iteration) = N * iters / Lloyd
 time, Lloyd time measured with HIP events around the graph replay inside each
-step.  The headline runs the BF16 screen (``--headline f16`` times the FP16
-screen instead); the other precisions run the same graph for comparison and
-must give identical final assignments.
+step.  The headline is the 10M-row workload with the BF16 screen
+(``--headline f16`` times the FP16 screen instead); the other precisions run
+the same graph for comparison and must give identical final assignments.
+
+After the headline the same run measures, unless switched off:
+* global k-means on the same kernels (a row sample against all K centroids),
+  beside the work ratio and the speed-up bounds of Sect. 2.1;
+* the encode service against the resident index, at 0.3, 0.6 and 0.9 of its
+  measured saturated rate;
+* the 50M-row, 2,097,152-centroid workload (``c3`` block): one warm-up and one
+  timed BF16 step, the FP16 and FP32 Lloyd legs, the per-token roofline, the
+  final-assignment check, and the encode service against that index.
 """
 from __future__ import annotations
 
@@ -46,6 +55,7 @@ WORKLOAD_TEXT = {
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assign_main_{prec}_{config}_traffic.md")
+PMC_FILE = os.path.join(ROOT, "profiles", "assign_main_{prec}_{config}_mfma_busy.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_28142_amd", "csrc", f) for f in ("assign.hip", "tac_internal.h")]
 
 
@@ -72,6 +82,42 @@ def measured_traffic(config: str, prec: str):
     if vals.get("workload", "").strip() != config:
         return None
     return float(vals["traffic_bytes_per_launch"])
+
+
+def measured_mfma_busy(config: str, prec: str):
+    """Fraction of the matrix cores' cycles busy during the 16-bit assignment
+    kernel, from the committed counter summary (SQ_VALU_MFMA_BUSY_CYCLES over
+    SQ_BUSY_CYCLES times the SIMDs per counter), or None when there is none for
+    this workload or it predates the kernel source."""
+    try:
+        text = open(PMC_FILE.format(prec=prec, config=config)).read()
+    except OSError:
+        return None
+    vals = dict(ln.split(":", 1) for ln in text.splitlines() if ln.startswith(("mfma_busy_frac:",
+                                                                              "kernel_source_sha1:", "workload:")))
+    if vals.get("kernel_source_sha1", "").strip() != kernel_source_hash():
+        return None
+    if vals.get("workload", "").strip() != config:
+        return None
+    return float(vals["mfma_busy_frac"])
+
+
+def host_info() -> dict:
+    """Host cores visible to this process and the CPU model."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
 def log(*a):
@@ -106,7 +152,8 @@ def cpu_baseline(x, tok, w, sample_rows: int, one_core_rows: int = 0, seed: int 
         threads = threads_label()
         return {"value": n / dt, "unit": "vectors/s", "cores": threads, "kind": "oracle",
                 "sample": f"{n} uniformly sampled rows of the same workload assigned by the float64 oracle "
-                          f"against their tokens' initial centroids ({dt:.1f}s on {threads} threads)"}
+                          f"against their tokens' initial centroids ({dt:.1f}s on {threads} threads)",
+                "host": host_info()}
 
     def blas_threads():
         return max([i["num_threads"] for i in threadpool_info()] or [1])
@@ -159,11 +206,25 @@ def copy_bandwidth(torch, dev, nbytes: int = 1 << 31) -> float:
     return 2.0 * nbytes / (best / 1e3) / 1e9
 
 
+def speedup_bounds(counts, spread, kappa, K: int, tau: int = 256) -> dict:
+    """Work ratio of one token-aware Lloyd iteration against global k-means
+    (N K distances over sum_j n_j kappa_j) and the two lower bounds of Sect. 2.1's
+    derivation: W / max w for the proportional allocation kappa_j = w_j / W * K,
+    and K / max kappa_j for the allocation actually used."""
+    n = counts.astype(np.float64)
+    act = counts >= tau
+    wj = np.sqrt(n[act]) * spread[act]
+    return {"work_ratio": float(n.sum() * K / (n * kappa).sum()),
+            "bound_sum_w_over_max_w": float(wj.sum() / wj.max()),
+            "bound_K_over_max_kappa": float(K / kappa.max())}
+
+
 def global_baseline(ctx, idx, w, tac_iter_ms: float, rows: int, seed: int = 0):
     """Plain (global) Lloyd on the same kernels: one segment holding a uniform
     sample of `rows` vectors and all K centroids of the build, one BF16
-    assignment + update timed with HIP events; compared per vector with the
-    token-aware iteration on the full input."""
+    assignment + update timed with HIP events (median of three, after one
+    untimed); compared per vector with the token-aware iteration on the full
+    input, beside the work ratio and the bounds of Sect. 2.1."""
     import torch
     import paper_2604_28142_amd as tac
     dev = idx.xs.device
@@ -178,25 +239,34 @@ def global_baseline(ctx, idx, w, tac_iter_ms: float, rows: int, seed: int = 0):
     stream = ctx.stream
     tac.tac_assign(ctx, xg, idx.C, coff, a, seg_off=seg, precision=tac.TAC_BF16)   # sizes the workspace
     tac.tac_update(ctx, xg, seg, a, idx.C, Cn)
-    ev[0].record(stream)
-    tac.tac_assign(ctx, xg, idx.C, coff, a, seg_off=seg, precision=tac.TAC_BF16)
-    tac.tac_update(ctx, xg, seg, a, idx.C, Cn)
-    ev[1].record(stream)
-    ev[1].synchronize()
-    ms = ev[0].elapsed_time(ev[1])
+    times = []
+    for _ in range(3):
+        ev[0].record(stream)
+        tac.tac_assign(ctx, xg, idx.C, coff, a, seg_off=seg, precision=tac.TAC_BF16)
+        tac.tac_update(ctx, xg, seg, a, idx.C, Cn)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        times.append(ev[0].elapsed_time(ev[1]))
+    ms = float(np.median(times))
+    del xg, Cn, a
     per_vec_global = ms / rows
     per_vec_tac = tac_iter_ms / N
-    return {"rows": rows, "centroids": idx.K, "ms_per_iter": ms,
-            "vectors_per_s": rows / (ms / 1e3), "tac_speedup_per_vector": per_vec_global / per_vec_tac,
-            "note": "one segment: a uniform row sample against all K centroids of the build, same BF16 kernels"}
+    h = idx.host
+    out = {"rows": rows, "centroids": idx.K, "ms_per_iter": ms,
+           "vectors_per_s": rows / (ms / 1e3), "tac_speedup_per_vector": per_vec_global / per_vec_tac,
+           **speedup_bounds(h["counts"], h["spread"], h["kappa"], idx.K),
+           "note": "one segment: a uniform row sample against all K centroids of the build, same BF16 kernels; "
+                   "work_ratio = N K / sum n_j kappa_j of the budget used (theta policy fill-then-relax)"}
+    return out
 
 
-SERVE_RATES = (10_000.0, 25_000.0, 40_000.0)   # fixed Poisson arrival rates, documents per second
+SERVE_FRACTIONS = (0.3, 0.6, 0.9)   # Poisson arrival rates as fractions of the measured saturated rate
 
 
-def serve_bench(idx, w, requests: int, seed: int = 0):
-    """Encode service against the resident index: saturated throughput, then
-    Poisson arrivals at three fixed rates (first 5% of requests discarded)."""
+def serve_bench(idx, w, requests: int, seed: int = 0, label: str | None = None):
+    """Encode service against the resident index: saturated throughput (all
+    requests submitted at once), then Poisson arrivals at 0.3, 0.6 and 0.9 of
+    it (first 5% of each run's requests discarded)."""
     import datagen
     from paper_2604_28142_amd.serve import EncodeService, GpuExecutor, ResidentIndex, run_load
 
@@ -210,20 +280,24 @@ def serve_bench(idx, w, requests: int, seed: int = 0):
     nsat = min(len(docs), 10_000)
     _, wall = run_load(svc, docs[:nsat], None)
     r_sat = nsat / wall
-    log(f"serve: saturated {r_sat:.0f} docs/s")
-    out = {"index": f"{w.name}: K={w.k} centroids, PQ 32x256", "requests_per_rate": requests,
+    log(f"serve {label or w.name}: saturated {r_sat:.0f} docs/s")
+    out = {"index": label or f"{w.name}: K={w.k} centroids, PQ 32x256", "requests_per_rate": requests,
            "docs_mean_vectors": float(lens.mean()), "saturated_docs_per_s": r_sat, "rates": []}
-    for i, rate in enumerate(SERVE_RATES):
+    for i, frac in enumerate(SERVE_FRACTIONS):
+        rate = frac * r_sat
         arr = datagen.poisson_arrivals(rate, len(docs), seed=seed + 3 * (i + 1))
+        b0 = svc.stats.batches
         res, wall = run_load(svc, docs, arr)
         skip = len(docs) // 20
         lat = np.array([r.latency for r in res[skip:]])
         vec = float(lens[skip:].sum())
-        out["rates"].append({"docs_per_s": rate, "fraction_of_saturation": rate / r_sat,
+        out["rates"].append({"fraction_of_saturation": frac, "docs_per_s": rate,
                              "p50_ms": 1e3 * float(np.percentile(lat, 50)),
                              "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                             "batches": svc.stats.batches - b0,
                              "vectors_per_s": vec / (wall * (len(docs) - skip) / len(docs))})
-        log(f"serve: rate {rate:.0f}/s p50 {out['rates'][-1]['p50_ms']:.2f} ms p99 {out['rates'][-1]['p99_ms']:.2f} ms")
+        log(f"serve {label or w.name}: {frac:.1f} x R_sat = {rate:.0f}/s p50 {out['rates'][-1]['p50_ms']:.2f} ms "
+            f"p99 {out['rates'][-1]['p99_ms']:.2f} ms")
     svc.close()
     ex.close()
     return out
@@ -332,36 +406,68 @@ def query_path(ctx, idx, w, index, nqueries=64, nq=32, kc=40, ncand=1000):
                        "scores_finite_where_filled": bool(torch.isfinite(scores[cand >= 0]).all().item())}}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c1", choices=["c0", "c1", "c3"])
-    ap.add_argument("--iters", type=int, default=10)
-    ap.add_argument("--seed", type=int, default=0, help="data seed of the workload (0: the headline data)")
-    ap.add_argument("--cpu-sample", type=int, default=300_000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-one-core-sample", type=int, default=20_000,
-                    help="rows of the single-thread oracle timing (0: skip it)")
-    ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--no-f16", action="store_true", help="skip the FP16-screen comparison leg")
-    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-screen comparison leg")
-    ap.add_argument("--headline", default="bf16", choices=["bf16", "f16"],
-                    help="16-bit screen timed in the steps (the other runs as a comparison leg)")
-    ap.add_argument("--serve-requests", type=int, default=20_000)
-    ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--global-baseline", type=int, default=0, metavar="ROWS",
-                    help="also time one plain Lloyd iteration (one segment, all K centroids) on ROWS sampled vectors")
-    ap.add_argument("--calibration-copy", action="store_true",
-                    help="first run one plain 1 GiB device copy (reference dispatch for HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
-              f"described but not built", file=sys.stderr)
-        sys.exit(2)
+def prepare(ctx, w, x, tok):
+    """Group + budget (one eager pass, which also sizes the workspace), the
+    seeded initial centroids and the PQ sample of a workload resident in HBM."""
+    import datagen
+    from paper_2604_28142_amd import index as IX
+    N = x.shape[0]
+    idx = IX.group_and_budget(ctx, x, tok, w.vocab, w.k)
+    counts, kappa = idx.host["counts"], idx.host["kappa"]
+    picks = datagen.init_picks(counts, kappa, w.seed)
+    sample = datagen.pq_sample(N, w.pq_sample, w.seed)
+    init_rows = datagen.pq_init_rows(sample.shape[0], w.pq_ksub, w.seed)
+    IX.init_centroids(ctx, idx, picks)
+    C0 = idx.C.clone()
+    screen = kappa > 4
+    F = 2.0 * 128 * float((counts[screen] * kappa[screen]).sum())   # algorithmic contraction flops per assign
+    log(f"{w.name} budget: K={int(kappa.sum())}, max kappa={int(kappa.max())}, screen flops/assign={F:.3e}")
+    return dict(idx=idx, counts=counts, kappa=kappa, picks=picks, sample=sample, init_rows=init_rows, C0=C0, F=F)
 
+
+def make_step(ctx, w, x, tok, P, stream):
+    """One pass of the whole path on a prepared workload, the Lloyd iterations
+    replayed from `lp`'s graph; returns (step ms, Lloyd ms, final-assign kernel
+    ms, encode kernel ms) -- the kernel times when kernel timing is on."""
+    import torch
+    import paper_2604_28142_amd as tac
+    from paper_2604_28142_amd import index as IX
+    idx = P["idx"]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def step(lp):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = tac.tac_budget(ctx, x, tok, w.vocab, w.k, perm=idx.perm, xs=idx.xs, seg_off=idx.seg_off,
+                             cent_off=idx.cent_off)
+        assert np.array_equal(out["kappa"], P["kappa"])
+        IX.init_centroids(ctx, idx, P["picks"])
+        ev[0].record(stream)
+        lp.replay()
+        ev[1].record(stream)
+        IX.final_assign(ctx, idx, precision=lp.precision)
+        IX.train_pq(ctx, idx, P["sample"], P["init_rows"], M=w.pq_m, ksub=w.pq_ksub, iters=10)
+        IX.encode_all(ctx, idx)
+        torch.cuda.synchronize()
+        timing = ctx.timing_enabled
+        return ((time.perf_counter() - t0) * 1e3, ev[0].elapsed_time(ev[1]),
+                ctx.kernel_ms(tac._lib.TAC_SLOT_ASSIGN) if timing else float("nan"),
+                ctx.kernel_ms(tac._lib.TAC_SLOT_ENCODE) if timing else float("nan"))
+    return step
+
+
+PRECS = ("bf16", "f16", "fp32")
+
+
+def prec_id(tac, name: str) -> int:
+    return {"bf16": tac.TAC_BF16, "f16": tac.TAC_F16, "fp32": tac.TAC_FP32}[name]
+
+
+def run_headline(args, dev):
+    """The headline workload: K timed steps of the headline precision, the
+    comparison legs, kernel times and rooflines, index structures, the query
+    path, global k-means, the encode service and the CPU oracle baseline.
+    Returns the JSON line (without the c3 block); frees its device state."""
     import torch
 
     import datagen
@@ -374,7 +480,6 @@ def main():
     x_h, tok_h = datagen.make(w)
     N = x_h.shape[0]
     log(f"data: {N} x 128 generated in {time.time() - t0:.1f}s")
-    dev = torch.device("cuda:0")
     x = torch.from_numpy(x_h).to(dev)
     tok = torch.from_numpy(tok_h).to(dev)
     ctx = tac.Context(0)
@@ -386,24 +491,14 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # one eager pass sizes the workspace and gives the budget for the plan
-    idx = IX.group_and_budget(ctx, x, tok, w.vocab, w.k)
-    counts, kappa = idx.host["counts"], idx.host["kappa"]
-    picks = datagen.init_picks(counts, kappa, w.seed)
-    sample = datagen.pq_sample(N, w.pq_sample, w.seed)
-    init_rows = datagen.pq_init_rows(sample.shape[0], w.pq_ksub, w.seed)
-    IX.init_centroids(ctx, idx, picks)
-    C0 = idx.C.clone()
-    screen = kappa > 4
-    F = 2.0 * 128 * float((counts[screen] * kappa[screen]).sum())   # algorithmic contraction flops per assign
-    log(f"budget: K={int(kappa.sum())}, max kappa={int(kappa.max())}, screen flops/assign={F:.3e}")
+    P = prepare(ctx, w, x, tok)
+    idx, counts, kappa, C0, F = P["idx"], P["counts"], P["kappa"], P["C0"], P["F"]
 
-    precs = {"bf16": tac.TAC_BF16, "f16": tac.TAC_F16, "fp32": tac.TAC_FP32}
     hl = args.headline
-    legs = [hl] + [nm for nm in ("bf16", "f16", "fp32") if nm != hl and not getattr(args, f"no_{nm}", False)]
+    legs = [hl] + [nm for nm in PRECS if nm != hl and not getattr(args, f"no_{nm}", False)]
     loops, tuned, tuning = {}, {}, {}
     for name in legs:
-        prec = precs[name]
+        prec = prec_id(tac, name)
         if not args.no_autotune:
             # launch tuning for this precision, measured on the initial centroids (cached per workload);
             # it is baked into the captured graph
@@ -429,24 +524,7 @@ def main():
         ev[1].synchronize()
         return ev[0].elapsed_time(ev[1])
 
-    def step(lp):
-        """One pass of the whole path; returns (step ms, Lloyd ms, final-assign kernel ms, encode kernel ms)."""
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        out = tac.tac_budget(ctx, x, tok, w.vocab, w.k, perm=idx.perm, xs=idx.xs, seg_off=idx.seg_off,
-                             cent_off=idx.cent_off)
-        assert np.array_equal(out["kappa"], kappa)
-        IX.init_centroids(ctx, idx, picks)
-        ev[0].record(stream)
-        lp.replay()
-        ev[1].record(stream)
-        IX.final_assign(ctx, idx, precision=lp.precision)
-        IX.train_pq(ctx, idx, sample, init_rows, M=w.pq_m, ksub=w.pq_ksub, iters=10)
-        IX.encode_all(ctx, idx)
-        torch.cuda.synchronize()
-        return ((time.perf_counter() - t0) * 1e3, ev[0].elapsed_time(ev[1]),
-                ctx.kernel_ms(tac._lib.TAC_SLOT_ASSIGN), ctx.kernel_ms(tac._lib.TAC_SLOT_ENCODE))
-
+    step = make_step(ctx, w, x, tok, P, stream)
     head = loops[hl]
     ctx.set_tuning(**tuning[hl])
     # kernel events: each step's final assignment (one launch of the persistent 16-bit assignment
@@ -477,7 +555,7 @@ def main():
         ctx.set_tuning(**tuning[name])
         ms = float(np.median([lloyd_ms(loops[name]) for _ in range(2)]))
         leg_ms[name] = ms
-        IX.final_assign(ctx, idx, precision=precs[name])
+        IX.final_assign(ctx, idx, precision=prec_id(tac, name))
         same = bool(torch.equal(idx.assign, final_head))
         same_all = same_all and same
         extra[name] = {"lloyd_ms_per_iter": ms / args.iters, "value": N * args.iters / (ms / 1e3),
@@ -498,7 +576,8 @@ def main():
         ctx.set_tuning(**tuning[name])
         vals = []
         for _ in range(3):
-            tac.tac_assign(ctx, idx.xs, idx.C, idx.cent_off, idx.assign, seg_off=idx.seg_off, precision=precs[name])
+            tac.tac_assign(ctx, idx.xs, idx.C, idx.cent_off, idx.assign, seg_off=idx.seg_off,
+                           precision=prec_id(tac, name))
             vals.append(ctx.kernel_ms(tac._lib.TAC_SLOT_ASSIGN))
         kms[name] = float(np.mean(vals))
         stats[name] = tac.tac_assign_stats(ctx)
@@ -529,11 +608,21 @@ def main():
     log(f"query path (gather + refine): {extra['query_path']}")
     del index
 
+    # the final centroids and codebooks of the headline precision for the index-based legs
+    idx.C.copy_(C0)
+    head.replay()
+    IX.final_assign(ctx, idx, precision=head.precision)
     if args.global_baseline:
         extra["global_kmeans"] = global_baseline(ctx, idx, w, lloyd_med / args.iters, args.global_baseline)
         log(f"global k-means: {extra['global_kmeans']}")
+    loops.clear()
+    del head
     if not args.no_serve:
         extra["encode_service"] = serve_bench(idx, w, args.serve_requests)
+    ctx.close()
+    del idx, P, x, tok, final_head
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -543,7 +632,7 @@ def main():
         if cpu1:
             extra["cpu_baseline_one_core"] = cpu1
 
-    line = {
+    return {
         "metric": "vectors assigned/sec per Lloyd iter, bf16 vs fp32 at equal argmin; encode p99",
         "value": value,
         "unit": "vectors/s",
@@ -562,12 +651,163 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[hl], "unit": "TFLOP/s",
                      "frac": achieved / PEAK[hl],
                      "traffic": measured_traffic(args.config, hl) if args.seed == 0 else None,
+                     "mfma_busy": measured_mfma_busy(args.config, hl) if args.seed == 0 else None,
                      "kernel": f"assign_main<{hl}> (persistent screen + per-lane top-3 + certificate)"},
         "cpu_baseline": cpu,
         **extra,
     }
-    print(json.dumps(line), flush=True)
+
+
+def run_c3(args, dev):
+    """The 50M-row, 2,097,152-centroid workload: one warm-up and one timed step
+    with the BF16 screen (Lloyd replayed from its graph), the FP16 and FP32
+    Lloyd legs run eagerly (launch overhead is negligible at about 0.5-1.8 s
+    per iteration) with their final assignments compared, per-token rooflines
+    of each precision's final-assignment kernel, and the encode service against
+    the built index."""
+    import torch
+
+    import datagen
+    import paper_2604_28142_amd as tac
+    from paper_2604_28142_amd import autotune
+    from paper_2604_28142_amd import index as IX
+
+    w = dataclasses.replace(datagen.WORKLOADS["c3"], seed=args.seed)
+    t0 = time.time()
+    x_h, tok_h = datagen.make(w)
+    N = x_h.shape[0]
+    x = torch.from_numpy(x_h).to(dev)
+    tok = torch.from_numpy(tok_h).to(dev)
+    del x_h, tok_h
+    log(f"c3 data: {N} x 128 generated and copied in {time.time() - t0:.1f}s")
+    ctx = tac.Context(0)
+    stream = torch.cuda.current_stream(dev)
+    P = prepare(ctx, w, x, tok)
+    idx, counts, kappa, C0, F = P["idx"], P["counts"], P["kappa"], P["C0"], P["F"]
+    out = {"workload": f"c3: {WORKLOAD_TEXT['c3']}", "vectors": N, "centroids": w.k, "lloyd_iters": args.iters,
+           "max_kappa": int(kappa.max()), "screen_flops_per_assign": F,
+           **speedup_bounds(counts, idx.host["spread"], kappa, w.k)}
+    legs = ["bf16"] + [nm for nm in ("f16", "fp32") if not getattr(args, f"no_{nm}", False)]
+    tuning = {}
+    for name in legs:
+        if name != "fp32" and not args.no_autotune:
+            r = autotune.tune_assign(ctx, idx.xs, idx.C, idx.cent_off, idx.seg_off, precision=prec_id(tac, name),
+                                     space={"tile_blocks": autotune.SPACE["tile_blocks"]},
+                                     host_seg_off=idx.host["seg_off"], host_cent_off=idx.host["cent_off"])
+            out[f"autotune_{name}"] = {"tuning": r["tuning"], "assign_ms": r["ms"], "default_assign_ms": r["default_ms"],
+                                       "cached": r["cached"], "trials": r.get("trials")}
+            log(f"c3 autotune {name}: {r['tuning']} {r['ms']:.1f} ms (default {r['default_ms']:.1f} ms)")
+        else:
+            ctx.set_tuning(**autotune.DEFAULT)
+        tuning[name] = ctx.get_tuning()
+
+    ctx.set_tuning(**tuning["bf16"])
+    lp = IX.LloydLoop(ctx, idx, iters=args.iters, precision=tac.TAC_BF16)
+    idx.C.copy_(C0)
+    lp.run()
+    torch.cuda.synchronize()
+    lp.capture()
+    step = make_step(ctx, w, x, tok, P, stream)
+    ctx.enable_timing(True)
+    warm = step(lp)
+    timed = step(lp)
+    ctx.enable_timing(False)
+    final_bf16 = idx.assign.clone()
+    C_bf16 = idx.C.clone()
+    lloyd = {"bf16": timed[1]}
+    kms = {"bf16": timed[2]}
+    out["bf16"] = {"step_ms": timed[0], "warmup_step_ms": warm[0], "lloyd_ms": timed[1],
+                   "lloyd_ms_per_iter": timed[1] / args.iters, "value": N * args.iters / (timed[1] / 1e3),
+                   "assign_kernel_ms": timed[2], "pq_encode_kernel_ms": timed[3]}
+    log(f"c3 bf16: step {timed[0]:.0f} ms, Lloyd {timed[1]:.0f} ms, assign kernel {timed[2]:.1f} ms")
+    del lp
+    same_all = True
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for name in legs[1:]:
+        ctx.set_tuning(**tuning[name])
+        lpx = IX.LloydLoop(ctx, idx, iters=args.iters, precision=prec_id(tac, name))
+        idx.C.copy_(C0)
+        ev[0].record(stream)
+        lpx.run()
+        ev[1].record(stream)
+        ev[1].synchronize()
+        lloyd[name] = ev[0].elapsed_time(ev[1])
+        del lpx
+        ctx.enable_timing(True)
+        IX.final_assign(ctx, idx, precision=prec_id(tac, name))
+        kms[name] = ctx.kernel_ms(tac._lib.TAC_SLOT_ASSIGN)
+        ctx.enable_timing(False)
+        same = bool(torch.equal(idx.assign, final_bf16))
+        same_all = same_all and same
+        out[name] = {"lloyd_ms": lloyd[name], "lloyd_ms_per_iter": lloyd[name] / args.iters,
+                     "value": N * args.iters / (lloyd[name] / 1e3), "assign_kernel_ms": kms[name],
+                     "final_argmin_identical_to_bf16": same, "assign_counters": tac.tac_assign_stats(ctx)}
+        log(f"c3 {name}: Lloyd {lloyd[name]:.0f} ms, assign kernel {kms[name]:.1f} ms, identical: {same}")
+    out["final_argmin_identical"] = same_all
+    if "fp32" in lloyd:
+        for name in ("bf16", "f16"):
+            if name in lloyd:
+                out[f"{name}_over_fp32"] = lloyd["fp32"] / lloyd[name]
+    out["roofline"] = {nm: {"achieved_tflops": F / (kms[nm] / 1e3) / 1e12, "peak": PEAK[nm],
+                            "frac": F / (kms[nm] / 1e3) / 1e12 / PEAK[nm]} for nm in kms}
+    copy_gbs = copy_bandwidth(torch, dev)
+    out["segment_roofline"] = {nm: segment_roofline(counts, kappa, kms[nm], nm, copy_gbs) for nm in kms}
+    log(f"c3 rooflines: {out['roofline']}")
+
+    # the built index (BF16 centroids and codebooks) for the encode service
+    idx.C.copy_(C_bf16)
+    idx.assign = final_bf16
+    del C_bf16
+    if not args.no_serve:
+        out["encode_service"] = serve_bench(idx, w, args.c3_serve_requests,
+                                            label=f"c3: K={w.k} centroids (max kappa {int(kappa.max())}), PQ 32x256")
     ctx.close()
+    del idx, P, x, tok
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c1", choices=["c0", "c1", "c3"])
+    ap.add_argument("--iters", type=int, default=10)
+    ap.add_argument("--seed", type=int, default=0, help="data seed of the workload (0: the headline data)")
+    ap.add_argument("--cpu-sample", type=int, default=300_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-one-core-sample", type=int, default=20_000,
+                    help="rows of the single-thread oracle timing (0: skip it)")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-f16", action="store_true", help="skip the FP16-screen comparison leg")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-screen comparison leg")
+    ap.add_argument("--headline", default="bf16", choices=["bf16", "f16"],
+                    help="16-bit screen timed in the steps (the other runs as a comparison leg)")
+    ap.add_argument("--serve-requests", type=int, default=20_000)
+    ap.add_argument("--c3-serve-requests", type=int, default=8_000)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 50M-row, 2,097,152-centroid block")
+    ap.add_argument("--global-baseline", type=int, default=200_000, metavar="ROWS",
+                    help="rows of the global k-means leg (one segment, all K centroids); 0 skips it")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="first run one plain 1 GiB device copy (reference dispatch for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
+              f"described but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    dev = torch.device("cuda:0")
+    line = run_headline(args, dev)
+    if args.config != "c3" and not args.no_c3:
+        t0 = time.time()
+        line["c3"] = run_c3(args, dev)
+        line["c3"]["block_wall_s"] = time.time() - t0
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

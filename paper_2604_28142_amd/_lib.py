@@ -152,6 +152,7 @@ class Context:
         h = _P()
         _check(lib.tac_ctx_create(device, self.stream.cuda_stream, max_workspace, C.byref(h)))
         self.handle = h
+        self.timing_enabled = False
 
     def set_stream(self, stream: torch.cuda.Stream):
         _check(load().tac_ctx_set_stream(self.handle, stream.cuda_stream))
@@ -159,6 +160,7 @@ class Context:
 
     def enable_timing(self, on: bool = True):
         _check(load().tac_ctx_enable_timing(self.handle, int(on)))
+        self.timing_enabled = bool(on)
 
     def kernel_ms(self, slot: int) -> float:
         """Elapsed ms of the last recording of a timing slot (HIP events on the context's stream)."""

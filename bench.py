@@ -692,7 +692,7 @@ def run_c3(args, dev):
     for name in legs:
         if name != "fp32" and not args.no_autotune:
             r = autotune.tune_assign(ctx, idx.xs, idx.C, idx.cent_off, idx.seg_off, precision=prec_id(tac, name),
-                                     space={"tile_blocks": autotune.SPACE["tile_blocks"]},
+                                     space={"tile": autotune.SPACE["tile"]},
                                      host_seg_off=idx.host["seg_off"], host_cent_off=idx.host["cent_off"])
             out[f"autotune_{name}"] = {"tuning": r["tuning"], "assign_ms": r["ms"], "default_assign_ms": r["default_ms"],
                                        "cached": r["cached"], "trials": r.get("trials")}

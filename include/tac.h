@@ -123,13 +123,22 @@ tac_status tac_kernel_ms(tac_ctx ctx, int slot, float* ms);
  *                    fit (default 0)
  *  tile_blocks       the 16-bit screens' tile shape: column blocks of 16 rows
  *                    per wave, so a work item is 64 * tile_blocks rows of one
- *                    token; 3, 4 or 5 (each is compiled), 0 = 5 (default 0).
- *                    The FP32 screen keeps its 512-row items. */
+ *                    token; 3, 4 or 5 (each is compiled), 0 = the default of
+ *                    the occupancy (3 at two work-groups per CU, 5 at one).
+ *                    The FP32 screen keeps its 512-row items.
+ *  waves_per_simd    the 16-bit screens' occupancy: 1 = one 256-thread
+ *                    work-group per compute unit (a wave per SIMD, the whole
+ *                    register file, 32 KiB centroid stages); 2 = two of them
+ *                    (two waves per SIMD, half of each, 16 KiB stages), whose
+ *                    tile is 3 column blocks (tile_blocks must then be 0 or 3);
+ *                    0 = two, unless tile_blocks is 4 or 5 (default 0).  The
+ *                    FP32 screen ignores it. */
 typedef struct {
     int32_t direct_max_kappa;
     int32_t heavy_kappa;
     int32_t groups_per_cu;
     int32_t tile_blocks;
+    int32_t waves_per_simd;
 } tac_tuning;
 tac_status tac_ctx_set_tuning(tac_ctx ctx, const tac_tuning* tuning);
 tac_status tac_ctx_get_tuning(tac_ctx ctx, tac_tuning* tuning);

@@ -50,7 +50,7 @@ class BudgetParams(C.Structure):
 class Tuning(C.Structure):
     """Launch tuning of tac_assign (results do not depend on it)."""
     _fields_ = [("direct_max_kappa", C.c_int32), ("heavy_kappa", C.c_int32), ("groups_per_cu", C.c_int32),
-                ("tile_blocks", C.c_int32)]
+                ("tile_blocks", C.c_int32), ("waves_per_simd", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -169,7 +169,8 @@ class Context:
         return float(v.value)
 
     def set_tuning(self, direct_max_kappa: int | None = None, heavy_kappa: int | None = None,
-                   groups_per_cu: int | None = None, tile_blocks: int | None = None):
+                   groups_per_cu: int | None = None, tile_blocks: int | None = None,
+                   waves_per_simd: int | None = None):
         """Change some fields of the context's tac_assign tuning; returns the new tuning as a dict."""
         t = Tuning()
         _check(load().tac_ctx_get_tuning(self.handle, C.byref(t)))
@@ -181,6 +182,8 @@ class Context:
             t.groups_per_cu = groups_per_cu
         if tile_blocks is not None:
             t.tile_blocks = tile_blocks
+        if waves_per_simd is not None:
+            t.waves_per_simd = waves_per_simd
         _check(load().tac_ctx_set_tuning(self.handle, C.byref(t)))
         return t.as_dict()
 

@@ -1,15 +1,20 @@
 """Measured launch tuning of tac_assign, cached per workload.
 
-The assignment kernel's launch has four knobs (``tac_tuning`` in the C ABI):
-the 16-bit screens' tile shape (``tile_blocks``: column blocks of 16 rows per
-wave, i.e. 192-, 256- or 320-row work items, each a separately compiled
-kernel), which tokens skip the matrix-core screen (``direct_max_kappa``),
+The assignment kernel's launch has five knobs (``tac_tuning`` in the C ABI).
+Two of them together pick the 16-bit screens' compiled kernel (the ``tile``
+knob here): the occupancy (``waves_per_simd``: one or two 256-thread
+work-groups per compute unit) and the tile shape (``tile_blocks``: column
+blocks of 16 rows per wave, i.e. 192-, 256- or 320-row work items; two
+work-groups per CU take 192).  The others choose which tokens skip the
+matrix-core screen (``direct_max_kappa``),
 which tokens the persistent work queue hands out first (``heavy_kappa``), and
 how many persistent work-groups share a compute unit (``groups_per_cu``).
 None of them changes a result, only the time, and the best values depend on
 the segment structure (how rows and centroids spread over tokens) and on the
 device.  A larger tile restages each centroid for more rows; a smaller one
-holds fewer registers and spreads a token's rows over more compute units.
+holds fewer registers and spreads a token's rows over more compute units; two
+work-groups per CU hide one's memory waits and vector work under the other's
+matrix work, with half the registers and LDS each.
 
 ``tune_assign`` measures candidate settings on the caller's resident buffers by
 coordinate search (one knob at a time, the others held at their best so far),
@@ -31,9 +36,12 @@ import torch
 
 from . import _lib as L
 
-DEFAULT = {"tile_blocks": 5, "direct_max_kappa": 4, "heavy_kappa": 1024, "groups_per_cu": 0}
+DEFAULT = {"waves_per_simd": 2, "tile_blocks": 3, "direct_max_kappa": 4, "heavy_kappa": 1024, "groups_per_cu": 0}
+# the 16-bit screens' compiled kernels: (occupancy, tile) pairs
+TILES = [{"waves_per_simd": 2, "tile_blocks": 3}, {"waves_per_simd": 1, "tile_blocks": 5},
+         {"waves_per_simd": 1, "tile_blocks": 4}, {"waves_per_simd": 1, "tile_blocks": 3}]
 SPACE = {
-    "tile_blocks": [5, 4, 3],
+    "tile": TILES,
     "direct_max_kappa": [0, 2, 4, 8, 16],
     "heavy_kappa": [128, 512, 1024, 4096],
     "groups_per_cu": [0, 1],
@@ -103,7 +111,7 @@ def tune_assign(ctx: L.Context, xs: torch.Tensor, C: torch.Tensor, cent_off: tor
     tuning must never change a result)."""
     space = dict(space or SPACE)
     if precision == L.TAC_FP32:
-        space.pop("tile_blocks", None)  # the FP32 screen has one tile shape
+        space.pop("tile", None)  # the FP32 screen has one tile shape
     cache_path = cache_path or default_cache_path()
     so = np.asarray(host_seg_off if host_seg_off is not None else seg_off.cpu().numpy())
     co = np.asarray(host_cent_off if host_cent_off is not None else cent_off.cpu().numpy())
@@ -146,7 +154,7 @@ def tune_assign(ctx: L.Context, xs: torch.Tensor, C: torch.Tensor, cent_off: tor
     best_ms = default_ms
     for knob, values in space.items():
         for v in values:
-            cand = dict(best, **{knob: v})
+            cand = dict(best, **(v if isinstance(v, dict) else {knob: v}))
             ms = measure(cand)
             if ms < best_ms:
                 best, best_ms = cand, ms

@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <mutex>
+#include <type_traits>
 
 #include "tac_internal.h"
 
@@ -453,7 +454,7 @@ __device__ __forceinline__ void direct_item(const Params& P, const ItemDesc& D) 
 // FP16 also stores each row's ||-2x - f16(-2x)||^2 at sdx[16 nb + col].  The
 // 16-bit screens pass xt, the wave's transpose area (16 rows of kXtStride words).
 constexpr int kXtStride = kDim + 4;
-template <int PREC, int NB>
+template <int PREC, int NB, int GROUP = NB, bool AGPR = true>
 __device__ __forceinline__ float load_x_frags(const Params& P, int64_t row0, int64_t s1, int g, int col,
                                               Frag<PREC, NB>& F, float* sdx = nullptr, float* xt = nullptr) {
     float xxmax = 0.f;
@@ -480,83 +481,89 @@ __device__ __forceinline__ float load_x_frags(const Params& P, int64_t row0, int
             xxmax = fmaxf(xxmax, xx);
         }
     } else {
-        // All of the wave's rows are loaded before any is converted, so that the
-        // loads of the NB column blocks are in flight together.  Each load
-        // instruction reads 1 KiB of contiguous memory (lane l: 16 bytes of row
-        // 2 i + l / 32), and each 16-row block is turned into the fragment
-        // layout through the wave's transpose area in LDS (rows padded to 528
-        // bytes); a fragment-layout load straight from memory would touch 64
-        // cache lines per instruction.
-        float4 ld[NB][8];
+        // The rows of GROUP column blocks are loaded before any is converted, so
+        // that their loads are in flight together (all NB blocks at once when a
+        // wave has the SIMD's registers to itself).  Each load instruction reads
+        // 1 KiB of contiguous memory (lane l: 16 bytes of row 2 i + l / 32), and
+        // each 16-row block is turned into the fragment layout through the
+        // wave's transpose area in LDS (rows padded to 528 bytes); a
+        // fragment-layout load straight from memory would touch 64 cache lines
+        // per instruction.  Row numbers fit in 32 bits (N <= INT32_MAX).
+        static_assert(NB % GROUP == 0, "whole groups of column blocks");
         const int lane = threadIdx.x & 63;
-        // physical rows first (the serving path's row map), all lookups in flight together
-        int64_t rr[NB][8];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
+        for (int nb0 = 0; nb0 < NB; nb0 += GROUP) {
+            float4 ld[GROUP][8];
+            // physical rows first (the serving path's row map), all lookups in flight together
+            int32_t rr[GROUP][8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int64_t v = row0 + nb * 16 + 2 * i + (lane >> 5);
-                rr[nb][i] = v < s1 ? v : -1;
-            }
-        if (P.rowmap) {  // unconditional lookups (rows past s1 read the last row's entry) keep them in flight together
-            int32_t m[NB][8];
+            for (int q = 0; q < GROUP; ++q)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-                for (int i = 0; i < 8; ++i) m[nb][i] = P.rowmap[rr[nb][i] >= 0 ? rr[nb][i] : s1 - 1];
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-                for (int i = 0; i < 8; ++i) rr[nb][i] = rr[nb][i] >= 0 ? (int64_t)m[nb][i] : -1;
-        }
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-                ld[nb][i] = rr[nb][i] >= 0 ? reinterpret_cast<const float4*>(P.x + rr[nb][i] * kDim)[lane & 31]
-                                           : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            float xx = 0.f, dyy = 0.f;
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-                *reinterpret_cast<float4*>(xt + (2 * i + (lane >> 5)) * kXtStride + 4 * (lane & 31)) = ld[nb][i];
-            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-            float4 fr[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) fr[q] = *reinterpret_cast<const float4*>(xt + col * kXtStride + 32 * g + 4 * q);
-            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the next block rewrites the area
-            // eight coordinates at a time straight into the 16-bit fragments
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const float4 a = fr[2 * s];
-                const float4 b = fr[2 * s + 1];
-                xx += a.x * a.x + a.y * a.y + a.z * a.z + a.w * a.w + b.x * b.x + b.y * b.y + b.z * b.z + b.w * b.w;
-                const float v8[8] = {-2.0f * a.x, -2.0f * a.y, -2.0f * a.z, -2.0f * a.w,
-                                     -2.0f * b.x, -2.0f * b.y, -2.0f * b.z, -2.0f * b.w};
-                if constexpr (PREC == TAC_BF16) {
-                    bf8 hi, lo;
-                    split_bf8(v8, hi, lo);
-                    F.xh[nb][s] = to_agpr(hi);
-                    F.xl[nb][s] = to_agpr(lo);
-                } else {
-                    h8 h;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        h[e] = (_Float16)v8[e];
-                        const float r = v8[e] - (float)h[e];  // exact: h is v rounded to a coarser grid
-                        dyy = dyy + r * r;
-                    }
-                    F.xh[nb][s] = to_agpr(h);
+                for (int i = 0; i < 8; ++i) {
+                    const int64_t v = row0 + (nb0 + q) * 16 + 2 * i + (lane >> 5);
+                    rr[q][i] = v < s1 ? (int32_t)v : -1;
                 }
+            if (P.rowmap) {  // unconditional lookups (rows past s1 read the last row's entry) keep them in flight together
+                int32_t m[GROUP][8];
+#pragma unroll
+                for (int q = 0; q < GROUP; ++q)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) m[q][i] = P.rowmap[rr[q][i] >= 0 ? (int64_t)rr[q][i] : s1 - 1];
+#pragma unroll
+                for (int q = 0; q < GROUP; ++q)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) rr[q][i] = rr[q][i] >= 0 ? m[q][i] : -1;
             }
-            xx += __shfl_xor(xx, 16);
-            xx += __shfl_xor(xx, 32);
-            xxmax = fmaxf(xxmax, xx);
-            if constexpr (PREC == TAC_F16) {
-                dyy += __shfl_xor(dyy, 16);
-                dyy += __shfl_xor(dyy, 32);
-                if (g == 0) sdx[nb * 16 + col] = dyy;
+#pragma unroll
+            for (int q = 0; q < GROUP; ++q)
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    ld[q][i] = rr[q][i] >= 0 ? reinterpret_cast<const float4*>(P.x + (int64_t)rr[q][i] * kDim)[lane & 31]
+                                             : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int q = 0; q < GROUP; ++q) {
+                const int nb = nb0 + q;
+                float xx = 0.f, dyy = 0.f;
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    *reinterpret_cast<float4*>(xt + (2 * i + (lane >> 5)) * kXtStride + 4 * (lane & 31)) = ld[q][i];
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+                float4 fr[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) fr[c] = *reinterpret_cast<const float4*>(xt + col * kXtStride + 32 * g + 4 * c);
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the next block rewrites the area
+                // eight coordinates at a time straight into the 16-bit fragments
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const float4 a = fr[2 * s];
+                    const float4 b = fr[2 * s + 1];
+                    xx += a.x * a.x + a.y * a.y + a.z * a.z + a.w * a.w + b.x * b.x + b.y * b.y + b.z * b.z + b.w * b.w;
+                    const float v8[8] = {-2.0f * a.x, -2.0f * a.y, -2.0f * a.z, -2.0f * a.w,
+                                         -2.0f * b.x, -2.0f * b.y, -2.0f * b.z, -2.0f * b.w};
+                    if constexpr (PREC == TAC_BF16) {
+                        bf8 hi, lo;
+                        split_bf8(v8, hi, lo);
+                        F.xh[nb][s] = AGPR ? to_agpr(hi) : hi;
+                        F.xl[nb][s] = AGPR ? to_agpr(lo) : lo;
+                    } else {
+                        h8 h;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            h[e] = (_Float16)v8[e];
+                            const float r = v8[e] - (float)h[e];  // exact: h is v rounded to a coarser grid
+                            dyy = dyy + r * r;
+                        }
+                        F.xh[nb][s] = AGPR ? to_agpr(h) : h;
+                    }
+                }
+                xx += __shfl_xor(xx, 16);
+                xx += __shfl_xor(xx, 32);
+                xxmax = fmaxf(xxmax, xx);
+                if constexpr (PREC == TAC_F16) {
+                    dyy += __shfl_xor(dyy, 16);
+                    dyy += __shfl_xor(dyy, 32);
+                    if (g == 0) sdx[nb * 16 + col] = dyy;
+                }
             }
         }
     }
@@ -634,7 +641,7 @@ __device__ __forceinline__ void epoch_flush(Key (&el)[NB][4], unsigned* glist, i
 //   rounds y = -2x and c once, and with dy = y - f16(y), dc = c - f16(c) the
 //   dot error y.c - f16(y).f16(c) = f16(y).dc + dy.f16(c) + dy.dc is bounded by
 //   Cauchy-Schwarz with the measured norms ||dy|| (per row) and max ||dc||.
-template <int PREC, int NB, int LK, bool SPLIT = false>
+template <int PREC, int NB, int LK, bool SPLIT = false, bool XREG = PREC != TAC_FP32>
 __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t row0, int64_t s1, int64_t klo,
                                             int64_t khi, const unsigned* glist, float beta, float cnmax, float cmax,
                                             int lane, const float* sdx = nullptr, SplitArgs S = {}) {
@@ -670,15 +677,16 @@ __device__ __forceinline__ void finish_item(const Params& P, int32_t j, int64_t 
         }
         const int64_t r = P.rowmap ? (int64_t)P.rowmap[v] : v;
         const float* xr = P.x + r * kDim;
-        // 16-bit screens: the row in registers, loaded once for all of its candidates
-        // (the FP32 screen's two waves per SIMD leave no room for it)
-        float4 xv[PREC == TAC_FP32 ? 1 : kDim / 4];
-        if constexpr (PREC != TAC_FP32) {
+        // XREG: the row in registers, loaded once for all of its candidates (a
+        // wave with the SIMD's registers to itself); with two waves per SIMD
+        // there is no room for it and each candidate reads the row again
+        float4 xv[XREG ? kDim / 4 : 1];
+        if constexpr (XREG) {
 #pragma unroll
             for (int i = 0; i < kDim / 4; ++i) xv[i] = reinterpret_cast<const float4*>(xr)[i];
         }
         auto dist = [&](int64_t k, float* xx) {
-            if constexpr (PREC == TAC_FP32)
+            if constexpr (!XREG)
                 return dist32_rows(xr, P.C + k * kDim, xx);
             else
                 return dist32_xreg(xv, P.C + k * kDim, xx);
@@ -895,59 +903,74 @@ constexpr int kBNBMin = 3;
 // extra med3.
 template <int PREC>
 constexpr int kBLK = PREC == TAC_F16 ? 4 : 3;
-constexpr int kBTileRows = kBWaves * kBNB * 16;
 constexpr int kBBufs = 3;                                 // stage buffers
-constexpr int kBStageWords = 8192;                        // 32 KiB per stage buffer
 constexpr int kBCnStride = 128;                           // norms per stage buffer (room for FP16's 128)
-constexpr size_t kBCnOffsetWords = (size_t)kBBufs * kBStageWords;
-constexpr size_t kBGlistOffsetWords = kBCnOffsetWords + (size_t)kBBufs * kBCnStride;
-constexpr size_t kBDxOffsetWords = kBGlistOffsetWords + (size_t)kBWaves * kBNB * 8 * 64;
-constexpr size_t kBLdsBytes = (kBDxOffsetWords + (size_t)kBWaves * kBNB * 16) * 4;
 // after the tiles: the persistent loop's work-item slots (two descriptors, two indices)
 constexpr size_t kSlotBytes = 80;
-static_assert(kBLdsBytes + kSlotBytes <= 160 * 1024, "fits the LDS of a CU");
+
+// LDS layout of a 16-bit screen work-group when OCC of them share a CU (one or
+// two waves per SIMD), in words: the norms of the three stage buffers, the
+// stage buffers, the waves' merged lists (room for kMaxNB column blocks), then
+// the FP16 screen's per-row rounding norms.  One work-group per CU stages
+// 32 KiB at a time and holds column blocks up to kBNB; two per CU stage 16 KiB
+// and hold three column blocks, so that both fit in the 160 KiB of LDS and in
+// half of the SIMD's registers each.
+template <int OCC>
+struct BLayout {
+    static constexpr int kStageWords = OCC == 1 ? 8192 : 4096;
+    static constexpr int kMaxNB = OCC == 1 ? kBNB : kBNBMin;
+    static constexpr size_t kCn = 0;
+    static constexpr size_t kStage = (size_t)kBBufs * kBCnStride;
+    static constexpr size_t kGlist = kStage + (size_t)kBBufs * kStageWords;
+    static constexpr size_t kDx = kGlist + (size_t)kBWaves * kMaxNB * 8 * 64;
+    static constexpr size_t kBytes = (kDx + (size_t)kBWaves * kMaxNB * 16) * 4;
+    // vector-memory instructions each wave issues per stage: its 1 KiB row
+    // transfers and one transfer of norms
+    static constexpr int kStageOps = kStageWords / 256 / kBWaves + 1;
+    static_assert(kStageWords / 256 % kBWaves == 0, "transfers split evenly over the waves");
+    static_assert(OCC * (kBytes + kSlotBytes) <= 160 * 1024, "fits the LDS of a CU");
+};
 
 // Stage geometry of a 16-bit screen: bytes per centroid row and centroids per stage.
-template <int PREC>
+template <int PREC, int OCC>
 struct StageGeom {
     static constexpr int kRowBytes = PREC == TAC_BF16 ? 512 : 256;
-    static constexpr int kCents = kBStageWords * 4 / kRowBytes;  // 64 or 128
-    static constexpr int kBlocks = kCents / 16;                  // 16-centroid blocks per stage
+    static constexpr int kCents = BLayout<OCC>::kStageWords * 4 / kRowBytes;  // 64 / 128, or 32 / 64
+    static constexpr int kBlocks = kCents / 16;                                // 16-centroid blocks per stage
 };
 
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
 
 // Issue the DMA of stage `st` (centroids st*S .. st*S+S-1 of the token) into
-// `buf` and its norms into `bcn`: the rows as 32 wave-wide transfers of 1 KiB
-// (two BF16 or four FP16 rows), eight per wave, and the norms as one 4-byte
-// transfer per wave (S / 4 lanes each), so that every wave issues exactly
-// kStageOps vector-memory instructions per stage.  Lane l moves 16 bytes of row
-// (1 KiB group) * rows + l / chunks into physical chunk l % chunks.  Rows past
-// the token's last centroid repeat it, and their norms come from
+// `buf` and its norms into `bcn`: the rows as wave-wide transfers of 1 KiB
+// (two BF16 or four FP16 rows), an equal share per wave, and the norms as one
+// 4-byte transfer per wave (S / 4 lanes each), so that every wave issues
+// exactly kStageOps vector-memory instructions per stage.  Lane l moves 16
+// bytes of row (1 KiB group) * rows + l / chunks into physical chunk l % chunks.
+// Rows past the token's last centroid repeat it, and their norms come from
 // g_invalid_norm, which makes their screen values huge.
-constexpr int kStageOps = kBStageWords / 256 / kBWaves + 1;
 __device__ const float g_invalid_norm = kInvalid;
-template <int PREC>
+template <int PREC, int OCC>
 __device__ __forceinline__ void bf_stage_issue(const char* __restrict__ chl, const float* __restrict__ cn, int64_t k0,
                                                int kc, int st, unsigned* buf, float* bcn, int wave, int lane) {
-    constexpr int RB = StageGeom<PREC>::kRowBytes;
+    constexpr int RB = StageGeom<PREC, OCC>::kRowBytes;
+    constexpr int SC = StageGeom<PREC, OCC>::kCents;
     constexpr int RPI = 1024 / RB;  // rows per transfer
     constexpr int CPR = RB / 16;    // chunks per row
-    static_assert(kBStageWords / 256 % kBWaves == 0, "transfers split evenly over the waves");
-    constexpr int PER = kBStageWords / 256 / kBWaves;
+    constexpr int PER = BLayout<OCC>::kStageWords / 256 / kBWaves;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int grp = wave * PER + i;
         const int row = RPI * grp + lane / CPR;
-        int kk = st * StageGeom<PREC>::kCents + row;
+        int kk = st * SC + row;
         kk = kk < kc ? kk : kc - 1;
         const int chunk = (lane % CPR) ^ (row & 15);
         const char* src = chl + (k0 + kk) * RB + chunk * 16;
         __builtin_amdgcn_global_load_lds(src, (lds_void_ptr)(buf + grp * 256), 16, 0, 0);
     }
-    constexpr int NPW = StageGeom<PREC>::kCents / kBWaves;  // norms per wave
+    constexpr int NPW = SC / kBWaves;  // norms per wave
     if (lane < NPW) {
-        const int kk = st * StageGeom<PREC>::kCents + wave * NPW + lane;
+        const int kk = st * SC + wave * NPW + lane;
         const float* src = kk < kc ? cn + k0 + kk : &g_invalid_norm;
         __builtin_amdgcn_global_load_lds(src, (lds_void_ptr)(bcn + wave * NPW), 4, 0, 0);
     }
@@ -980,12 +1003,14 @@ struct BBlock<TAC_F16> {
     f4 cb;
 };
 
-template <int PREC, int NB, bool SPLIT = false>
+template <int PREC, int NB, int OCC, bool SPLIT = false>
 __device__ __forceinline__ void screen_item_mx(const Params& P, const ItemDesc& D, unsigned* lds, SplitArgs S = {}) {
-    static_assert(NB >= kBNBMin && NB <= kBNB, "a compiled tile");
-    constexpr int SC = StageGeom<PREC>::kCents;
-    constexpr int BPS = StageGeom<PREC>::kBlocks;
-    constexpr int RW = StageGeom<PREC>::kRowBytes / 4;  // words per staged row
+    using LY = BLayout<OCC>;
+    static_assert(NB >= kBNBMin && NB <= LY::kMaxNB, "a compiled tile");
+    constexpr int SW = LY::kStageWords;
+    constexpr int SC = StageGeom<PREC, OCC>::kCents;
+    constexpr int BPS = StageGeom<PREC, OCC>::kBlocks;
+    constexpr int RW = StageGeom<PREC, OCC>::kRowBytes / 4;  // words per staged row
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4;
@@ -1004,22 +1029,26 @@ __device__ __forceinline__ void screen_item_mx(const Params& P, const ItemDesc& 
     const float cnmax = __uint_as_float(P.cstat[0]) * (1.0f + 1e-5f);
     const float cmax = sqrtf(cnmax) * (1.0f + 1e-6f);
 
-    unsigned* stage = lds;                                               // [3][kBStageWords]
-    float* stage_cn = reinterpret_cast<float*>(lds + kBCnOffsetWords);   // [3][kBCnStride]
-    unsigned* glist = lds + kBGlistOffsetWords + (unsigned)wave * (NB * 8 * 64) + lane;
-    float* sdx = reinterpret_cast<float*>(lds + kBDxOffsetWords) + wave * (NB * 16);
+    unsigned* stage = lds + LY::kStage;                                  // [3][SW]
+    float* stage_cn = reinterpret_cast<float*>(lds + LY::kCn);           // [3][kBCnStride]
+    unsigned* glist = lds + LY::kGlist + (unsigned)wave * (NB * 8 * 64) + lane;
+    float* sdx = reinterpret_cast<float*>(lds + LY::kDx) + wave * (NB * 16);
     const char* chl = static_cast<const char*>(P.cstage);
     const int nst = (kc + SC - 1) / SC;
     const int nblk = (kc + 15) / 16;
 
     // stage 0 first, so that its latency overlaps the x prologue
-    bf_stage_issue<PREC>(chl, P.cn, k0, kc, 0, stage, stage_cn, wave, lane);
+    bf_stage_issue<PREC, OCC>(chl, P.cn, k0, kc, 0, stage, stage_cn, wave, lane);
 
     Frag<PREC, NB> F;
-    // the x transpose areas sit in stage buffers 1 and 2, whose DMAs start after the prologue
-    float* xt = reinterpret_cast<float*>(stage + kBStageWords) + wave * (16 * kXtStride);
-    static_assert(kBWaves * 16 * kXtStride <= 2 * kBStageWords, "transpose areas fit in two stage buffers");
-    const float xxmax = load_x_frags<PREC, NB>(P, row0, s1, g, col, F, sdx, xt);
+    // the x transpose areas start at stage buffer 1: buffers 1 and 2 (whose DMAs
+    // start after the prologue) and, with 16 KiB stages, the merged lists (set
+    // up after it) hold them
+    float* xt = reinterpret_cast<float*>(stage + SW) + wave * (16 * kXtStride);
+    static_assert(LY::kStage + SW + kBWaves * 16 * kXtStride <= LY::kDx, "transpose areas end before the row norms");
+    // one wave per SIMD: the x operands in AGPRs; two: in VGPRs, since the
+    // compiler splits a half register file evenly between the two kinds
+    const float xxmax = load_x_frags<PREC, NB, OCC == 1 ? NB : 1, OCC == 1>(P, row0, s1, g, col, F, sdx, xt);
     // One shift for the whole wave makes every screen value positive (see the FP32 screen).
     const float beta = xxmax * (1.0f + 0.00390625f) + 0.00390625f * cnmax + 1e-30f;
     float el[NB][4];
@@ -1027,19 +1056,20 @@ __device__ __forceinline__ void screen_item_mx(const Params& P, const ItemDesc& 
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) el[nb][e] = FLT_MAX;
-    glist_init<NB>(glist);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
+    // the merged lists only now: with 16 KiB stages the last waves' transpose
+    // areas reach into the first waves' lists, so every prologue must be done
+    glist_init<NB>(glist);
     // stages 1 and 2 in flight: the pipeline keeps two stages ahead of the one being read
-    if (nst > 1) bf_stage_issue<PREC>(chl, P.cn, k0, kc, 1, stage + kBStageWords, stage_cn + kBCnStride, wave, lane);
-    if (nst > 2)
-        bf_stage_issue<PREC>(chl, P.cn, k0, kc, 2, stage + 2 * kBStageWords, stage_cn + 2 * kBCnStride, wave, lane);
+    if (nst > 1) bf_stage_issue<PREC, OCC>(chl, P.cn, k0, kc, 1, stage + SW, stage_cn + kBCnStride, wave, lane);
+    if (nst > 2) bf_stage_issue<PREC, OCC>(chl, P.cn, k0, kc, 2, stage + 2 * SW, stage_cn + 2 * kBCnStride, wave, lane);
 
     int epoch_first = 0;
     auto load_block = [&](int blk, BBlock<PREC>& B) {
         const int buf = (blk / BPS) % kBBufs;
         const int b = blk % BPS;
-        const unsigned* srow = stage + buf * kBStageWords + (b * 16 + col) * RW;
+        const unsigned* srow = stage + buf * SW + (b * 16 + col) * RW;
 #pragma unroll
         for (int st4 = 0; st4 < 4; ++st4) {
             if constexpr (PREC == TAC_BF16) {
@@ -1132,71 +1162,153 @@ __device__ __forceinline__ void screen_item_mx(const Params& P, const ItemDesc& 
         if (blk % BPS != BPS - 1) return;
         const int sn = blk / BPS + 1;
         if (sn >= nst) return;
-        static_assert(kStageOps == 9, "the counted wait below matches the transfers per stage");
+        // the count of one stage's transfers: stage s + 2's stay in flight
         if (sn + 1 < nst)
-            asm volatile("s_waitcnt vmcnt(9) lgkmcnt(0)" ::: "memory");
+            asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"(LY::kStageOps) : "memory");
         else
             asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
         bare_barrier();
         if (sn + 2 < nst)
-            bf_stage_issue<PREC>(chl, P.cn, k0, kc, sn + 2, stage + ((sn + 2) % kBBufs) * kBStageWords,
-                                 stage_cn + ((sn + 2) % kBBufs) * kBCnStride, wave, lane);
+            bf_stage_issue<PREC, OCC>(chl, P.cn, k0, kc, sn + 2, stage + ((sn + 2) % kBBufs) * SW,
+                                      stage_cn + ((sn + 2) % kBBufs) * kBCnStride, wave, lane);
     };
 
-    // Pipeline over the blocks: region(b) = MFMAs of b, operands of b + 1,
-    // inserts of b - 1.  Unrolled by two so that operand and accumulator
-    // sets alternate without copies.
-    BBlock<PREC> BA, BB;
-    f4 accA[NB], accB[NB];
-    load_block(0, BA);
-    if (nblk == 1) {
-        mfmas(BA, accA);
-        inserts(0, accA);
-        flush_if(0);
+    if constexpr (OCC == 1) {
+        // Pipeline over the blocks: region(b) = MFMAs of b, operands of b + 1,
+        // inserts of b - 1.  Unrolled by two so that operand and accumulator
+        // sets alternate without copies.
+        BBlock<PREC> BA, BB;
+        f4 accA[NB], accB[NB];
+        load_block(0, BA);
+        if (nblk == 1) {
+            mfmas(BA, accA);
+            inserts(0, accA);
+            flush_if(0);
+        } else {
+            load_block(1, BB);
+            mfmas(BA, accA);
+            for (int blk = 1;; ++blk) {
+                // odd block: operands BB -> accB, previous block in accA
+                stage_turn(blk);
+                if (blk + 1 >= nblk) {
+                    mfmas(BB, accB);
+                    inserts(blk - 1, accA);
+                    flush_if(blk - 1);
+                    inserts(blk, accB);
+                    flush_if(blk);
+                    break;
+                }
+                load_block(blk + 1, BA);
+                mfmas_inserts(BB, accB, blk - 1, accA);
+                flush_if(blk - 1);
+                ++blk;
+                // even block: operands BA -> accA, previous block in accB
+                stage_turn(blk);
+                if (blk + 1 >= nblk) {
+                    mfmas(BA, accA);
+                    inserts(blk - 1, accB);
+                    flush_if(blk - 1);
+                    inserts(blk, accA);
+                    flush_if(blk);
+                    break;
+                }
+                load_block(blk + 1, BB);
+                mfmas_inserts(BA, accA, blk - 1, accB);
+                flush_if(blk - 1);
+            }
+        }
     } else {
-        load_block(1, BB);
-        mfmas(BA, accA);
-        for (int blk = 1;; ++blk) {
-            // odd block: operands BB -> accB, previous block in accA
-            stage_turn(blk);
-            if (blk + 1 >= nblk) {
-                mfmas(BB, accB);
-                inserts(blk - 1, accA);
-                flush_if(blk - 1);
-                inserts(blk, accB);
-                flush_if(blk);
-                break;
+        // Two waves per SIMD leave half the registers.  A block's operands are
+        // read one k-step ahead instead of one block ahead, and one set of
+        // accumulators serves: the block's inserts follow its MFMAs, while the
+        // SIMD's other wave keeps the matrix cores busy.  Since a block's
+        // operands are read while its own MFMAs run, a stage's buffer is free
+        // only once its last block is done: the turn comes before the first
+        // block of the next stage (wait for that stage, barrier, then the DMA
+        // of the stage after the next one into the buffer just finished).
+        struct KOps {
+            typename std::conditional<PREC == TAC_BF16, bf8, h8>::type ch;
+            typename std::conditional<PREC == TAC_BF16, bf8, h8>::type cl;  // BF16 only
+        };
+        auto load_k = [&](int blk, int st4, KOps& K) {
+            const int buf = (blk / BPS) % kBBufs;
+            const unsigned* srow = stage + buf * SW + ((blk % BPS) * 16 + col) * RW;
+            const unsigned* hp = srow + 4 * ((4 * g + st4) ^ col);
+            if constexpr (PREC == TAC_BF16) {
+                // chunk (16 + c) ^ col = 16 + (c ^ col) for c, col < 16: the lo half
+                // sits 64 words after the hi half, one address for both
+                K.ch = *reinterpret_cast<const bf8*>(hp);
+                K.cl = *reinterpret_cast<const bf8*>(hp + 64);
+            } else {
+                K.ch = *reinterpret_cast<const h8*>(hp);
             }
-            load_block(blk + 1, BA);
-            mfmas_inserts(BB, accB, blk - 1, accA);
-            flush_if(blk - 1);
-            ++blk;
-            // even block: operands BA -> accA, previous block in accB
-            stage_turn(blk);
-            if (blk + 1 >= nblk) {
-                mfmas(BA, accA);
-                inserts(blk - 1, accB);
-                flush_if(blk - 1);
-                inserts(blk, accA);
-                flush_if(blk);
-                break;
+        };
+        auto load_cb = [&](int blk) {
+            const int buf = (blk / BPS) % kBBufs;
+            return *reinterpret_cast<const f4*>(stage_cn + buf * kBCnStride + (blk % BPS) * 16 + 4 * g) + beta;
+        };
+        auto turn_before = [&](int blk) {
+            if (blk == 0 || blk % BPS != 0) return;
+            const int sn = blk / BPS;  // the stage about to be read
+            if (sn + 1 < nst)
+                asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"(LY::kStageOps) : "memory");
+            else
+                asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+            bare_barrier();
+            if (sn + 2 < nst)
+                bf_stage_issue<PREC, OCC>(chl, P.cn, k0, kc, sn + 2, stage + ((sn + 2) % kBBufs) * SW,
+                                          stage_cn + ((sn + 2) % kBBufs) * kBCnStride, wave, lane);
+        };
+        KOps KA, KB;
+        f4 acc[NB];
+        for (int blk = 0; blk < nblk; ++blk) {
+            turn_before(blk);
+            load_k(blk, 0, KA);
+            const f4 cb = load_cb(blk);
+#pragma unroll
+            for (int st4 = 0; st4 < 4; ++st4) {
+                KOps& K = st4 % 2 == 0 ? KA : KB;
+                KOps& Kn = st4 % 2 == 0 ? KB : KA;
+                if (st4 < 3) load_k(blk, st4 + 1, Kn);
+                // FP16: the next step's reads stay ahead of this step's products
+                // (measured faster; BF16's longer steps measured faster without)
+                if constexpr (PREC == TAC_F16) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int pr = 0; pr < NPR; ++pr) {
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        if constexpr (PREC == TAC_BF16) {
+                            const bf8 av = pr == 2 ? K.cl : K.ch;
+                            const bf8 bv = pr == 1 ? F.xl[nb][st4] : F.xh[nb][st4];
+                            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, (st4 == 0 && pr == 0) ? cb : acc[nb],
+                                                                             0, 0, 0);
+                        } else {
+                            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(K.ch, F.xh[nb][st4],
+                                                                            st4 == 0 ? cb : acc[nb], 0, 0, 0);
+                        }
+                    }
+                    // round-robin over the accumulators: no product waits on the one before it
+                    if constexpr (PREC == TAC_F16) __builtin_amdgcn_sched_barrier(0);
+                }
             }
-            load_block(blk + 1, BB);
-            mfmas_inserts(BA, accA, blk - 1, accB);
-            flush_if(blk - 1);
+            inserts(blk, acc);
+            flush_if(blk);
         }
     }
-    finish_item<PREC, NB, kBLK<PREC>, SPLIT>(P, j, row0, s1, k0, k0 + kc, glist, beta, cnmax, cmax, lane, sdx, S);
+    finish_item<PREC, NB, kBLK<PREC>, SPLIT, OCC == 1>(P, j, row0, s1, k0, k0 + kc, glist, beta, cnmax, cmax, lane,
+                                                      sdx, S);
 }
 
-template <int PREC, int NB = kBNB>
-__global__ void __launch_bounds__(PREC == TAC_FP32 ? kThreads : kBThreads) assign_main(Params P) {
+// OCC: persistent work-groups per CU that the 16-bit screens are compiled for
+// (the register budget of a wave is the SIMD's file over OCC).
+template <int PREC, int NB = kBNB, int OCC = 1>
+__global__ void __launch_bounds__(PREC == TAC_FP32 ? kThreads : kBThreads, OCC) assign_main(Params P) {
     // All shared memory is dynamic so that it starts 16-byte aligned (a static
     // variable in front of it would shift every 16-byte LDS access off alignment).
     extern __shared__ __attribute__((aligned(16))) unsigned lds[];
     // the work-item slots after the kernel's tiles: descriptors of the current
     // and next item (by parity), then the indices of the next two items
-    ItemDesc* s_desc = reinterpret_cast<ItemDesc*>(lds + (PREC == TAC_FP32 ? kLdsBytes : kBLdsBytes) / 4);
+    ItemDesc* s_desc = reinterpret_cast<ItemDesc*>(lds + (PREC == TAC_FP32 ? kLdsBytes : BLayout<OCC>::kBytes) / 4);
     long long* s_idx = reinterpret_cast<long long*>(s_desc + 2);
     const int64_t total = P.item_off[3 * (int64_t)P.T];
     if (threadIdx.x == 0) {
@@ -1227,7 +1339,7 @@ __global__ void __launch_bounds__(PREC == TAC_FP32 ? kThreads : kBThreads) assig
             if (cls == 2)
                 direct_item<kBThreads>(P, D);
             else
-                screen_item_mx<PREC, NB>(P, D, lds);
+                screen_item_mx<PREC, NB, OCC>(P, D, lds);
         } else {
             if (cls == 2)
                 direct_item<kThreads>(P, D);
@@ -1247,13 +1359,13 @@ __global__ void __launch_bounds__(PREC == TAC_FP32 ? kThreads : kBThreads) assig
 // The split route's work items (items item_off[3T] .. item_off[4T]), one per
 // work-group at a time in a grid-stride loop: the same 16-bit screen and
 // finish as the persistent kernel, on one row tile and one centroid chunk.
-template <int PREC, int NB>
-__global__ void __launch_bounds__(kBThreads) assign_split(Params P, SplitArgs S) {
+template <int PREC, int NB, int OCC>
+__global__ void __launch_bounds__(kBThreads, OCC) assign_split(Params P, SplitArgs S) {
     extern __shared__ __attribute__((aligned(16))) unsigned lds[];
     const int64_t b = P.item_off[3 * (int64_t)P.T], e = P.item_off[4 * (int64_t)P.T];
     for (int64_t t = b + blockIdx.x; t < e; t += gridDim.x) {
         const ItemDesc D = P.desc[t];
-        screen_item_mx<PREC, NB, true>(P, D, lds, S);
+        screen_item_mx<PREC, NB, OCC, true>(P, D, lds, S);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();  // every wave is done with this item's LDS
     }
@@ -1514,22 +1626,39 @@ unsigned grid_for(int64_t work, int per_block) {
 }
 
 
-// The compiled 16-bit screen kernels of one precision and row tile.
+// The compiled 16-bit screen kernels of one precision, row tile and
+// occupancy, with the dynamic LDS their tiles take.
 struct Kernels16 {
     void (*main)(Params);
     void (*split)(Params, SplitArgs);
+    size_t lds;  // tile bytes (the persistent kernel adds kSlotBytes)
+    int nb;      // column blocks of 16 rows per wave
 };
 template <int PREC>
-Kernels16 kernels16_of(int nb) {
-    static_assert(kBNBMin == 3 && kBNB == 5, "one case per compiled tile");
+Kernels16 kernels16_of(int nb, int occ) {
+    static_assert(kBNBMin == 3 && kBNB == 5 && BLayout<2>::kMaxNB == 3, "one case per compiled tile");
+    if (occ == 2) return {assign_main<PREC, 3, 2>, assign_split<PREC, 3, 2>, BLayout<2>::kBytes, 3};
     switch (nb) {
-        case 3: return {assign_main<PREC, 3>, assign_split<PREC, 3>};
-        case 4: return {assign_main<PREC, 4>, assign_split<PREC, 4>};
-        default: return {assign_main<PREC, 5>, assign_split<PREC, 5>};
+        case 3: return {assign_main<PREC, 3, 1>, assign_split<PREC, 3, 1>, BLayout<1>::kBytes, 3};
+        case 4: return {assign_main<PREC, 4, 1>, assign_split<PREC, 4, 1>, BLayout<1>::kBytes, 4};
+        default: return {assign_main<PREC, 5, 1>, assign_split<PREC, 5, 1>, BLayout<1>::kBytes, 5};
     }
 }
-Kernels16 kernels16(int precision, int nb) {
-    return precision == TAC_BF16 ? kernels16_of<TAC_BF16>(nb) : kernels16_of<TAC_F16>(nb);
+Kernels16 kernels16(int precision, int nb, int occ) {
+    return precision == TAC_BF16 ? kernels16_of<TAC_BF16>(nb, occ) : kernels16_of<TAC_F16>(nb, occ);
+}
+// The 16-bit screen variant a context's tuning selects: two work-groups per CU
+// (three column blocks) for waves_per_simd 2, and by default unless
+// tile_blocks asks for a tile only one work-group per CU holds (4 or 5);
+// otherwise one work-group per CU with tile_blocks column blocks (default 5).
+int occupancy_of(const tac_tuning& t) {
+    if (t.waves_per_simd == 1 || t.waves_per_simd == 2) return t.waves_per_simd;
+    return t.tile_blocks == 4 || t.tile_blocks == 5 ? 1 : 2;
+}
+Kernels16 kernels16_for(const tac_tuning& t, int precision) {
+    const int occ = occupancy_of(t);
+    const int nb = occ == 2 ? 3 : t.tile_blocks >= kBNBMin && t.tile_blocks <= kBNB ? t.tile_blocks : kBNB;
+    return kernels16(precision, nb, occ);
 }
 
 }  // namespace
@@ -1743,11 +1872,11 @@ tac_status assign_run(tac_ctx ctx, char* ws, const AssignPlan& pl, const float* 
         rowmap = in1 ? v1 : v0;
     }
     const int threads = mx16 ? kBThreads : kThreads;
-    // the 16-bit screens' row tile: tile_blocks column blocks of 16 rows per wave
-    const int nb16 = ctx->tuning.tile_blocks >= kBNBMin && ctx->tuning.tile_blocks <= kBNB ? ctx->tuning.tile_blocks : kBNB;
-    const int screen_rows = mx16 ? kBWaves * nb16 * 16 : kTileRows;
+    // the 16-bit screens' kernels and row tile (column blocks of 16 rows per wave)
+    const Kernels16 k16 = kernels16_for(ctx->tuning, mx16 ? precision : TAC_BF16);
+    const int screen_rows = mx16 ? kBWaves * k16.nb * 16 : kTileRows;
     // dynamic LDS: the kernel's tiles plus the work-item slots
-    const size_t lds_bytes = (mx16 ? kBLdsBytes : kLdsBytes) + kSlotBytes;
+    const size_t lds_bytes = (mx16 ? k16.lds : kLdsBytes) + kSlotBytes;
     plan_count<<<grid_for(T, 256), 256, 0, s>>>(seg, cent_off_d, T, ctx->tuning.direct_max_kappa,
                                                   ctx->tuning.heavy_kappa, mx16 ? kSplitMinKappa : 0,
                                                   screen_rows, threads, cnt, cstat + 1);
@@ -1790,27 +1919,30 @@ tac_status assign_run(tac_ctx ctx, char* ws, const AssignPlan& pl, const float* 
     TAC_LAUNCH_CHECK("fb_zero");
     P.counters = ctx->counters;
     // persistent grid: as many work-group slots as the device holds at once
-    static int occ[3] = {0, 0, 0};
+    // (occupancy per kernel: FP32, then each 16-bit precision's tiles 3-5 at
+    // one work-group per CU and tile 3 at two)
+    static int occ[1 + 2 * 4] = {0};
+    auto occ_slot = [](int prec, int nb, int wps) { return 1 + (prec - TAC_BF16) * 4 + (wps == 2 ? 3 : nb - kBNBMin); };
     if (!occ[0]) {
         TAC_HIP(hipFuncSetAttribute((const void*)assign_main<TAC_FP32>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)(kLdsBytes + kSlotBytes)));
-        for (int pr = TAC_BF16; pr <= TAC_F16; ++pr)
-            for (int nb = kBNBMin; nb <= kBNB; ++nb) {
-                const Kernels16 k = kernels16(pr, nb);
-                TAC_HIP(hipFuncSetAttribute((const void*)k.main, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)(kBLdsBytes + kSlotBytes)));
-                TAC_HIP(hipFuncSetAttribute((const void*)k.split, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)kBLdsBytes));
-            }
-        TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], assign_main<TAC_BF16>, kBThreads,
-                                                             kBLdsBytes + kSlotBytes));
-        TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], assign_main<TAC_F16>, kBThreads,
-                                                             kBLdsBytes + kSlotBytes));
         TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], assign_main<TAC_FP32>, kThreads,
                                                              kLdsBytes + kSlotBytes));
-        for (int i = 0; i < 3; ++i) occ[i] = occ[i] < 1 ? 1 : occ[i];
+        for (int pr = TAC_BF16; pr <= TAC_F16; ++pr)
+            for (int v = 0; v < 4; ++v) {
+                const int wps = v == 3 ? 2 : 1, nb = v == 3 ? kBNBMin : kBNBMin + v;
+                const Kernels16 k = kernels16(pr, nb, wps);
+                TAC_HIP(hipFuncSetAttribute((const void*)k.main, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)(k.lds + kSlotBytes)));
+                TAC_HIP(hipFuncSetAttribute((const void*)k.split, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)k.lds));
+                TAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[occ_slot(pr, nb, wps)], k.main, kBThreads,
+                                                                     k.lds + kSlotBytes));
+            }
+        for (int& o : occ) o = o < 1 ? 1 : o;
     }
-    int per_cu = occ[precision];
+    const int occ16 = occupancy_of(ctx->tuning);
+    int per_cu = mx16 ? occ[occ_slot(precision, k16.nb, occ16)] : occ[0];
     if (ctx->tuning.groups_per_cu > 0 && ctx->tuning.groups_per_cu < per_cu) per_cu = ctx->tuning.groups_per_cu;
     const unsigned grid = (unsigned)ctx->props_cu * (unsigned)per_cu;
     time_start(ctx, TAC_SLOT_ASSIGN);
@@ -1818,7 +1950,7 @@ tac_status assign_run(tac_ctx ctx, char* ws, const AssignPlan& pl, const float* 
         assign_main<TAC_FP32><<<grid, threads, lds_bytes, s>>>(P);
         TAC_LAUNCH_CHECK("assign_main<fp32>");
     } else {
-        kernels16(precision, nb16).main<<<grid, threads, lds_bytes, s>>>(P);
+        k16.main<<<grid, threads, lds_bytes, s>>>(P);
         TAC_LAUNCH_CHECK(precision == TAC_BF16 ? "assign_main<bf16>" : "assign_main<f16>");
     }
     time_stop(ctx, TAC_SLOT_ASSIGN);
@@ -1826,7 +1958,7 @@ tac_status assign_run(tac_ctx ctx, char* ws, const AssignPlan& pl, const float* 
         // the split route (no work items outside serving-sized batches: then the
         // launches find an empty item range and return)
         const unsigned sgrid = (unsigned)ctx->props_cu;
-        kernels16(precision, nb16).split<<<sgrid, kBThreads, kBLdsBytes, s>>>(P, S);
+        k16.split<<<sgrid * (unsigned)occ16, kBThreads, k16.lds, s>>>(P, S);
         TAC_LAUNCH_CHECK("assign_split");
         split_resolve<<<sgrid, 128, 0, s>>>(cnt, table, T, rowmap, S.slot, S.flag, assign_d, dist, ctx->counters);
         TAC_LAUNCH_CHECK("split_resolve");

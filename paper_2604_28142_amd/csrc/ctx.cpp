@@ -107,9 +107,11 @@ extern "C" tac_status tac_ctx_set_stream(tac_ctx ctx, void* hip_stream) {
 extern "C" tac_status tac_ctx_set_tuning(tac_ctx ctx, const tac_tuning* t) {
     if (!ctx || !t) return set_error(TAC_E_INVAL, "tac_ctx_set_tuning: NULL argument");
     if (t->direct_max_kappa < 0 || t->direct_max_kappa > 16 || t->heavy_kappa < 1 || t->groups_per_cu < 0 ||
-        (t->tile_blocks != 0 && (t->tile_blocks < 3 || t->tile_blocks > 5)))
+        (t->tile_blocks != 0 && (t->tile_blocks < 3 || t->tile_blocks > 5)) || t->waves_per_simd < 0 ||
+        t->waves_per_simd > 2 || (t->waves_per_simd == 2 && t->tile_blocks != 0 && t->tile_blocks != 3))
         return set_error(TAC_E_INVAL, "tac_ctx_set_tuning: direct_max_kappa in [0, 16], heavy_kappa >= 1, "
-                                      "groups_per_cu >= 0, tile_blocks 0 or in [3, 5]");
+                                      "groups_per_cu >= 0, tile_blocks 0 or in [3, 5], waves_per_simd in [0, 2] "
+                                      "(with 2, tile_blocks 0 or 3)");
     ctx->tuning = *t;
     return TAC_OK;
 }

@@ -59,7 +59,7 @@ struct tac_ctx_s {
     // per-context device counters of the last tac_assign (rows, screened, fallback, unassigned)
     unsigned long long* counters = nullptr;
     int props_cu = 256;
-    tac_tuning tuning = {4, 1024, 0, 0};
+    tac_tuning tuning = {4, 1024, 0, 0, 0};
     // centroids declared unchanging (tac_ctx_set_static_centroids): the
     // assignment's per-call preparation (norms, bounds, 16-bit staging rows),
     // done once into sc_buf; replaced buffers are retired like workspaces

@@ -81,5 +81,9 @@ def test_autotune_workload_key_tracks_structure():
     assert k != autotune.workload_key(seg, cen, 0)
     assert k != autotune.workload_key(np.array([0, 11, 30, 31]), cen, 1)
     assert k != autotune.workload_key(seg, np.array([0, 3, 7, 8]), 1)
-    assert set(autotune.DEFAULT) == set(autotune.SPACE)
-    assert all(v in autotune.SPACE[n] for n, v in autotune.DEFAULT.items())
+    # every knob of the default is searched: the tile knob sets the occupancy and tile shape together
+    searched = {k for k in autotune.SPACE if k != "tile"} | {f for t in autotune.SPACE["tile"] for f in t}
+    assert set(autotune.DEFAULT) == searched
+    assert {"waves_per_simd": autotune.DEFAULT["waves_per_simd"],
+            "tile_blocks": autotune.DEFAULT["tile_blocks"]} in autotune.SPACE["tile"]
+    assert all(v in autotune.SPACE[n] for n, v in autotune.DEFAULT.items() if n in autotune.SPACE)

@@ -265,14 +265,17 @@ def test_graph_survives_workspace_growth():
         ctx2.close()
 
 
-@pytest.mark.parametrize("tuning", [dict(direct_max_kappa=0, heavy_kappa=1, groups_per_cu=1, tile_blocks=0),
-                                    dict(direct_max_kappa=16, heavy_kappa=64, groups_per_cu=0, tile_blocks=0),
-                                    dict(direct_max_kappa=4, heavy_kappa=1024, groups_per_cu=0, tile_blocks=3),
-                                    dict(direct_max_kappa=2, heavy_kappa=128, groups_per_cu=0, tile_blocks=4)])
+@pytest.mark.parametrize("tuning", [
+    dict(direct_max_kappa=0, heavy_kappa=1, groups_per_cu=1, tile_blocks=0, waves_per_simd=0),
+    dict(direct_max_kappa=16, heavy_kappa=64, groups_per_cu=0, tile_blocks=0, waves_per_simd=1),
+    dict(direct_max_kappa=4, heavy_kappa=1024, groups_per_cu=0, tile_blocks=3, waves_per_simd=1),
+    dict(direct_max_kappa=2, heavy_kappa=128, groups_per_cu=0, tile_blocks=4, waves_per_simd=0),
+    dict(direct_max_kappa=4, heavy_kappa=256, groups_per_cu=1, tile_blocks=3, waves_per_simd=2)])
 def test_tuning_keeps_results(ctx, tuning):
     """Launch tuning moves tokens between the direct and screened routes,
-    reorders the work queue and changes the 16-bit screens' tile shape (192-,
-    256- or 320-row items); the assignments stay those of the oracle."""
+    reorders the work queue and changes the 16-bit screens' kernel (one or two
+    work-groups per CU; 192-, 256- or 320-row items); the assignments stay
+    those of the oracle."""
     rng = np.random.default_rng(15)
     kappas = [1, 3, 4, 5, 16, 17, 70]
     sizes = [40, 3 * 5 + 7, 200, 513, 90, 1030, 700]
@@ -292,14 +295,20 @@ def test_tuning_keeps_results(ctx, tuning):
         ctx.set_tuning(direct_max_kappa=17)
     with pytest.raises(tac.TacError):
         ctx.set_tuning(tile_blocks=6)
+    with pytest.raises(tac.TacError):
+        ctx.set_tuning(waves_per_simd=3)
+    with pytest.raises(tac.TacError):
+        ctx.set_tuning(waves_per_simd=2, tile_blocks=5)
+    assert ctx.get_tuning() == before
 
 
-@pytest.mark.parametrize("tile_blocks", [3, 4])
-def test_tile_shapes_on_hot_tokens(ctx, tile_blocks):
-    """The smaller tiles on tokens of 9,000 rows and 2,500 / 4,097 centroids
-    (several epochs, ragged last tiles) and the split route (6,000 rows):
-    every tile returns the oracle's FP32-decision assignments and the same
-    distances as the default tile, bit for bit."""
+@pytest.mark.parametrize("wps,tile_blocks", [(1, 3), (1, 4), (1, 5)])
+def test_tile_shapes_on_hot_tokens(ctx, wps, tile_blocks):
+    """The one-work-group-per-CU tiles on tokens of 9,000 rows and 2,500 /
+    4,097 centroids (several epochs and stages, ragged last tiles) and the
+    split route (6,000 rows): every tile returns the oracle's FP32-decision
+    assignments and the same distances as the default kernel (two work-groups
+    per CU, 192-row items), bit for bit."""
     rng = np.random.default_rng(18)
     sizes, kappas = [9000, 9000, 6000, 700], [2500, 4097, 2500, 40]
     xs = np.concatenate([clustered(rng, n, 300, spread=0.3) for n in sizes])
@@ -310,9 +319,9 @@ def test_tile_shapes_on_hot_tokens(ctx, tile_blocks):
     before = ctx.get_tuning()
     try:
         for prec in (1, 2):
-            ctx.set_tuning(tile_blocks=0)
+            ctx.set_tuning(tile_blocks=0, waves_per_simd=0)
             a0, d0, J0 = run_assign(ctx, xs, seg_off, C, cent_off, prec)
-            ctx.set_tuning(tile_blocks=tile_blocks)
+            ctx.set_tuning(tile_blocks=tile_blocks, waves_per_simd=wps)
             a, d, J = run_assign(ctx, xs, seg_off, C, cent_off, prec)
             assert np.array_equal(a, a0) and np.array_equal(d.view(np.uint32), d0.view(np.uint32)) and J == J0
             check_assign(xs, seg_off, C, cent_off, a[rows], d[rows], rows=rows)

@@ -282,7 +282,8 @@ def serve_bench(idx, w, requests: int, seed: int = 0, label: str | None = None):
     r_sat = nsat / wall
     log(f"serve {label or w.name}: saturated {r_sat:.0f} docs/s")
     out = {"index": label or f"{w.name}: K={w.k} centroids, PQ 32x256", "requests_per_rate": requests,
-           "docs_mean_vectors": float(lens.mean()), "saturated_docs_per_s": r_sat, "rates": []}
+           "docs_mean_vectors": float(lens.mean()), "saturated_docs_per_s": r_sat,
+           "graph_buckets_rows": ex.buckets if ex.graphs else None, "ledger_bytes": svc.ledger_cap, "rates": []}
     for i, frac in enumerate(SERVE_FRACTIONS):
         rate = frac * r_sat
         arr = datagen.poisson_arrivals(rate, len(docs), seed=seed + 3 * (i + 1))

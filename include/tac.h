@@ -247,6 +247,16 @@ tac_status tac_assign_noalloc(tac_ctx ctx, const float* x_d, const int64_t* seg_
                               int64_t K, int32_t precision, int32_t* assign_d, float* dist_d,
                               double* inertia_d);
 
+/* Device workspace, in bytes, that tac_assign takes on this context for a call
+ * of N rows over T tokens and K centroids at `precision`, with token ids
+ * (with_tok != 0: the serving path) or token-sorted rows, with or without a
+ * dist_d output (with_dist), given the centroids the context has prepared
+ * (tac_ctx_set_static_centroids) for that precision.  For callers that budget
+ * device memory (an encode service admitting batches by memory).  Host-only:
+ * launches nothing.  TAC_E_INVAL for NULL arguments or sizes out of range. */
+tac_status tac_assign_workspace_bytes(tac_ctx ctx, int64_t N, int32_t T, const float* C_d, int64_t K,
+                                      int32_t precision, int with_tok, int with_dist, size_t* bytes);
+
 /* Counters of the last tac_assign on this context.  Synchronises the stream. */
 tac_status tac_assign_stats(tac_ctx ctx, tac_assign_counters* out);
 

@@ -27,7 +27,8 @@ EXPORTS = ["tac_ctx_create", "tac_ctx_set_stream", "tac_ctx_destroy", "tac_last_
            "tac_budget_from_stats",
            "tac_init_centroids", "tac_assign", "tac_assign_stats", "tac_update", "tac_residuals", "pq_train",
            "pq_encode", "tac_ctx_enable_timing", "tac_kernel_ms", "tac_ctx_set_tuning", "tac_ctx_get_tuning",
-           "tac_ivf_build", "tac_doc_layout", "tac_maxsim", "tac_gather", "tac_ctx_set_static_centroids"]
+           "tac_ivf_build", "tac_doc_layout", "tac_maxsim", "tac_gather", "tac_ctx_set_static_centroids",
+           "tac_assign_workspace_bytes"]
 TAC_SLOT_ASSIGN, TAC_SLOT_UPDATE, TAC_SLOT_ENCODE = 0, 1, 2
 
 
@@ -81,6 +82,8 @@ _SIGS = {
     "tac_assign": (C.c_int, [_P, _P, _P, _P, _I64, _I32, _I32, _P, _P, _I64, _I32, _P, _P, _P]),
     "tac_assign_noalloc": (C.c_int, [_P, _P, _P, _P, _I64, _I32, _I32, _P, _P, _I64, _I32, _P, _P, _P]),
     "tac_assign_stats": (C.c_int, [_P, C.POINTER(AssignCounters)]),
+    "tac_assign_workspace_bytes": (C.c_int, [_P, _I64, _I32, _P, _I64, _I32, C.c_int, C.c_int,
+                                             C.POINTER(C.c_size_t)]),
     "tac_update": (C.c_int, [_P, _P, _P, _I32, _I64, _I32, _P, _P, _I64, _P, _P]),
     "tac_residuals": (C.c_int, [_P, _P, _P, _P, _I64, _P, _I64, _I32, C.c_int, _P, _P]),
     "pq_train": (C.c_int, [_P, _P, _I64, _I32, _I32, _I32, _I32, _P, _P]),
@@ -291,6 +294,16 @@ def tac_assign_noalloc(ctx: Context, x, C_cent, cent_off, assign, seg_off=None, 
     _check(load().tac_assign_noalloc(ctx.handle, _dptr(x), _dptr(seg_off), _dptr(tok), N, d, T, _dptr(C_cent),
                                      _dptr(cent_off), C_cent.shape[0], precision, _dptr(assign), _dptr(dist),
                                      _dptr(inertia)))
+
+
+def tac_assign_workspace_bytes(ctx: Context, N: int, T: int, C_cent, K: int, precision: int,
+                               with_tok: bool = True, with_dist: bool = True) -> int:
+    """Device workspace bytes tac_assign takes on `ctx` for such a call (C_cent
+    matters only when the context holds it prepared)."""
+    out = C.c_size_t()
+    _check(load().tac_assign_workspace_bytes(ctx.handle, N, T, _dptr(C_cent), K,
+                                             precision, int(with_tok), int(with_dist), C.byref(out)))
+    return int(out.value)
 
 
 def tac_assign_stats(ctx: Context) -> dict:

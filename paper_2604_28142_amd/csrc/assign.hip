@@ -2050,6 +2050,22 @@ extern "C" tac_status tac_assign_noalloc(tac_ctx ctx, const float* x_d, const in
                       inertia_d);
 }
 
+extern "C" tac_status tac_assign_workspace_bytes(tac_ctx ctx, int64_t N, int32_t T, const float* C_d, int64_t K,
+                                                 int32_t precision, int with_tok, int with_dist, size_t* bytes) {
+    if (!ctx || !bytes) return set_error(TAC_E_INVAL, "tac_assign_workspace_bytes: NULL argument");
+    if (N < 0 || N > INT32_MAX || T < 1 || T > (1 << 24) || K < 0 || K > INT32_MAX)
+        return set_error(TAC_E_INVAL, "tac_assign_workspace_bytes: sizes out of range");
+    if (precision != TAC_FP32 && precision != TAC_BF16 && precision != TAC_F16)
+        return set_error(TAC_E_INVAL, "tac_assign_workspace_bytes: bad precision");
+    // the plan only tests the token-id pointer and the dist pointer for NULL
+    static const int32_t tok_marker = 0;
+    static float dist_marker = 0.f;
+    const AssignPlan pl = assign_plan(ctx, with_tok ? &tok_marker : nullptr, N, T, C_d, K, precision,
+                                      with_dist ? &dist_marker : nullptr);
+    *bytes = pl.bytes;
+    return TAC_OK;
+}
+
 extern "C" tac_status tac_assign_stats(tac_ctx ctx, tac_assign_counters* out) {
     if (!ctx || !out) return set_error(TAC_E_INVAL, "tac_assign_stats: NULL argument");
     TAC_HIP(hipSetDevice(ctx->device));

@@ -87,3 +87,36 @@ def test_poisson_load_reports_latency(served):
     lat = np.asarray(svc.stats.latencies[before:])
     assert lat.shape[0] == len(ok)
     assert np.all(lat > 0) and np.percentile(lat, 99) < wall
+
+
+def test_graph_replay_equals_eager_and_budget_binds(served):
+    """The replayed bucket graphs give bitwise the results of eager launches
+    (several replays of each bucket, eager work between them), also under a
+    device-memory budget that lets only about one large batch fly at a time."""
+    c, cb, docs, svc = served
+    present = c.kappa > 0
+    ok = [d for d in docs if np.all(present[d[1]])][:240]
+    index = svc.ex.index
+    eager = GpuExecutor(index, n_slots=2, max_rows=64 * 180, graphs=False)
+    s_eager = EncodeService(eager, max_docs=64)
+    ref, _ = run_load(s_eager, ok, None)
+    s_eager.close()
+    eager.close()
+    ex = GpuExecutor(index, n_slots=3, max_rows=64 * 180, graphs=True, buckets=[1024, 4096, 64 * 180])
+    assert ex.batch_bytes(100) == ex.batch_bytes(1024) < ex.batch_bytes(1025)
+    cap = ex.batch_bytes(64 * 180) + ex.batch_bytes(1024)
+    s_graph = EncodeService(ex, max_docs=64, ledger_bytes=cap)
+    try:
+        for rep in range(2):
+            res, _ = run_load(s_graph, ok, None)            # large batches (several buckets)
+            one = [s_graph.submit(*ok[i]).result() for i in range(0, 40, 3)]  # small batches
+            torch.cuda.synchronize()
+            for r0, r in zip(ref, res):
+                assert np.array_equal(r0.assign, r.assign) and np.array_equal(r0.codes, r.codes)
+                assert np.array_equal(r0.rnorm.view(np.uint32), r.rnorm.view(np.uint32))
+            for k, i in enumerate(range(0, 40, 3)):
+                assert np.array_equal(ref[i].assign, one[k].assign) and np.array_equal(ref[i].codes, one[k].codes)
+        assert s_graph.max_ledger_used <= cap
+    finally:
+        s_graph.close()
+        ex.close()

@@ -80,6 +80,68 @@ def test_ledger_bounds_memory_in_flight():
     assert ex.max_inflight_rows * ROW_BYTES <= cap
 
 
+class BudgetedExecutor(FakeExecutor):
+    """A stand-in that charges each batch its bytes like the GPU executor: a
+    fixed workspace plus the rows of its bucket (powers of two from 64)."""
+
+    FIXED, PER_ROW = 50_000, 600
+
+    def __init__(self, **kw):
+        super().__init__(**kw)
+        self.inflight_bytes = 0
+        self.max_inflight_bytes = 0
+        self.bytes_of = {}
+
+    def batch_bytes(self, rows):
+        b = 64
+        while b < rows:
+            b *= 2
+        return self.FIXED + min(b, self.max_rows) * self.PER_ROW
+
+    def launch(self, slot, xs, toks):
+        n = super().launch(slot, xs, toks)
+        with self.lock:
+            self.bytes_of[slot] = self.batch_bytes(n)
+            self.inflight_bytes += self.bytes_of[slot]
+            self.max_inflight_bytes = max(self.max_inflight_bytes, self.inflight_bytes)
+        return n
+
+    def wait(self, slot, n):
+        out = super().wait(slot, n)
+        with self.lock:
+            self.inflight_bytes -= self.bytes_of[slot]
+        return out
+
+
+def test_memory_budget_binds_and_results_stay():
+    """With a device-memory budget of one full batch and a bit, the three
+    slots never hold more than the budget together: requests wait for memory
+    (fewer batches in flight than slots) and every result is still the one a
+    document gets alone."""
+    D = docs(300, seed=7)
+    free = BudgetedExecutor(n_slots=3, max_rows=400, delay=0.004)
+    svc = EncodeService(free, max_docs=64)
+    assert svc.ledger_cap == 3 * free.batch_bytes(400)
+    ref, _ = run_load(svc, D, None)
+    svc.close()
+    ex = BudgetedExecutor(n_slots=3, max_rows=400, delay=0.004)
+    cap = ex.batch_bytes(400) + ex.batch_bytes(100)
+    svc = EncodeService(ex, max_docs=64, ledger_bytes=cap)
+    res, _ = run_load(svc, D, None)
+    svc.close()
+    assert ex.max_inflight_bytes <= cap and svc.max_ledger_used <= cap
+    assert ex.max_inflight_bytes > ex.batch_bytes(400)             # the budget was used, and it bound:
+    assert free.max_inflight_bytes > cap                           # unbudgeted, more was in flight
+    for r0, r in zip(ref, res):
+        assert np.array_equal(r0.assign, r.assign) and np.array_equal(r0.codes, r.codes)
+    tight = EncodeService(BudgetedExecutor(max_rows=400), ledger_bytes=60_000)
+    try:
+        with pytest.raises(ValueError):                            # a document alone beyond the budget
+            tight.submit(np.zeros((200, 128), np.float32), np.zeros(200, np.int32))
+    finally:
+        tight.close()
+
+
 def test_failed_batch_is_isolated_and_loop_continues():
     ex = FakeExecutor(fail_token=7)
     svc = EncodeService(ex, max_docs=1)          # one document per batch

@@ -351,7 +351,7 @@ def index_structures(ctx, idx, w, N):
     return info, (layout, doc_off, rnorm_in, list_off, list_docs)
 
 
-def query_path(ctx, idx, w, index, nqueries=64, nq=32, kc=40, ncand=1000):
+def query_path(ctx, idx, w, index, nqueries=64, nq=32, kc=40, ncand=1000, graph_leg=True):
     """Both phases of retrieval (Sect. 2.2) for synthetic queries against the
     built index: the gather phase (kappa_c = `kc` centroids per query token,
     kappa_d = `ncand` candidates per query) and the refine phase (MaxSim over
@@ -396,7 +396,8 @@ def query_path(ctx, idx, w, index, nqueries=64, nq=32, kc=40, ncand=1000):
     ok = cand_h >= 0
     tokens = int((off_h[cand_h[ok] + 1] - off_h[cand_h[ok]]).sum())
     K = idx.C.shape[0]
-    return {"queries": nqueries, "query_tokens": nq, "kappa_c": kc, "kappa_d": ncand,
+    graph = graph_gather(ctx, idx, Q, list_off, list_docs, D, kc, ncand, cand_h) if graph_leg else None
+    return {"queries": nqueries, "query_tokens": nq, "kappa_c": kc, "kappa_d": ncand, "graph_gather": graph,
             "gather": {"ms": tg, "queries_per_s": nqueries / (tg / 1e3), "candidates_filled": filled,
                        "similarity_TFLOPs": nqueries * nq * K * 2.0 * 128 / (tg / 1e3) / 1e12,
                        "note": "exact top-kappa_c centroids (the paper's HNSW approximates them); wall time of "
@@ -405,6 +406,73 @@ def query_path(ctx, idx, w, index, nqueries=64, nq=32, kc=40, ncand=1000):
                        "doc_tokens_scored": tokens, "GBps_algorithmic": tokens * 552 / (t / 1e3) / 1e9,
                        "TFLOPs_algorithmic": tokens * 2.0 * 128 * nq / (t / 1e3) / 1e12,
                        "scores_finite_where_filled": bool(torch.isfinite(scores[cand >= 0]).all().item())}}
+
+
+ROUTER_STRIDE = 16
+
+
+def graph_gather(ctx, idx, Q, list_off, list_docs, D, kc, kd, exact_cand):
+    """The gather with its centroid step on the neighbour graph instead of the
+    exact scan (the paper's HNSW setting: 32 neighbours, ef = 1.5 kappa_c):
+    graph build time, search time of every query token, recall of the exact
+    top-kappa_c, and the overlap of the kappa_d candidates with the exact
+    gather's.  Routers: the first centroid of every token with centroids and
+    every 16th centroid (a token's centroids sit in a few far-apart groups, so
+    one entry per token would start most searches in the wrong group)."""
+    import torch
+    import paper_2604_28142_amd as tac
+    dev = idx.xs.device
+    K = idx.C.shape[0]
+    B, nq = Q.shape[0], Q.shape[1]
+    ef = min(64, (3 * kc + 1) // 2)
+    coff = idx.host["cent_off"]
+    ent = np.union1d(coff[:-1][np.diff(coff) > 0], np.arange(0, K, ROUTER_STRIDE))
+    entry = torch.from_numpy(ent.astype(np.int32)).to(dev)
+    nbr = torch.empty((K, 64), dtype=torch.int32, device=dev)
+    stream = ctx.stream
+
+    def timed(fn, reps):
+        out = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return float(np.median(out))
+
+    torch.cuda.synchronize()
+    build_ms = timed(lambda: tac.tac_graph_build(ctx, idx.C, nbr), 1)   # one build (seconds at 2M centroids)
+    Qr = Q.reshape(B * nq, -1)
+    gid = torch.empty((B * nq, kc), dtype=torch.int32, device=dev)
+    gsim = torch.empty((B * nq, kc), dtype=torch.float32, device=dev)
+    eid = torch.empty_like(gid)
+    esim = torch.empty_like(gsim)
+    search = lambda: tac.tac_graph_search(ctx, Qr, idx.C, nbr, entry, ef, kc, gid, gsim)
+    search()
+    search_ms = timed(search, 5)
+    exact = lambda: tac.tac_centroid_topk(ctx, Qr, idx.C, kc, eid, esim)
+    exact()
+    exact_ms = timed(exact, 3)
+    g, e = gid.cpu().numpy(), eid.cpu().numpy()
+    recall = float(np.mean([len(set(g[r]) & set(e[r])) / kc for r in range(g.shape[0])]))
+    cand = torch.empty((B, kd), dtype=torch.int32, device=dev)
+    score = torch.empty((B, kd), dtype=torch.float32, device=dev)
+    lists = lambda: tac.tac_gather_lists(ctx, gid.view(B, nq, kc), gsim.view(B, nq, kc), list_off, list_docs, K, D,
+                                         kd, cand, score)
+    lists()
+    t0 = time.perf_counter()
+    lists()
+    lists_ms = (time.perf_counter() - t0) * 1e3
+    c = cand.cpu().numpy()
+    overlap = float(np.mean([len(set(c[b][c[b] >= 0]) & set(exact_cand[b][exact_cand[b] >= 0]))
+                             / max(1, int((exact_cand[b] >= 0).sum())) for b in range(B)]))
+    return {"degree": 32, "reverse_edges": 32, "ef": ef, "routers": int(entry.shape[0]),
+            "routers_rule": f"first centroid of every token, and every {ROUTER_STRIDE}th centroid", "build_ms": build_ms,
+            "search_ms": search_ms, "exact_topk_ms": exact_ms, "query_tokens": B * nq,
+            "recall_at_kappa_c": recall, "lists_gather_ms": lists_ms,
+            "gather_ms_total": search_ms + lists_ms, "candidate_overlap_with_exact": overlap}
 
 
 def prepare(ctx, w, x, tok):
@@ -755,10 +823,17 @@ def run_c3(args, dev):
     out["segment_roofline"] = {nm: segment_roofline(counts, kappa, kms[nm], nm, copy_gbs) for nm in kms}
     log(f"c3 rooflines: {out['roofline']}")
 
-    # the built index (BF16 centroids and codebooks) for the encode service
+    # the built index (BF16 centroids and codebooks) for the query path and the encode service
     idx.C.copy_(C_bf16)
     idx.assign = final_bf16
     del C_bf16
+    if not args.no_query:
+        t0 = time.time()
+        out["index_structures"], index = index_structures(ctx, idx, w, N)
+        out["query_path"] = query_path(ctx, idx, w, index)
+        out["query_path"]["wall_s"] = time.time() - t0
+        log(f"c3 query path: {out['query_path']}")
+        del index
     if not args.no_serve:
         out["encode_service"] = serve_bench(idx, w, args.c3_serve_requests,
                                             label=f"c3: K={w.k} centroids (max kappa {int(kappa.max())}), PQ 32x256")
@@ -791,6 +866,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the 50M-row, 2,097,152-centroid block")
+    ap.add_argument("--no-query", action="store_true", help="skip the 50M-row block's query path (graph build included)")
     ap.add_argument("--global-baseline", type=int, default=200_000, metavar="ROWS",
                     help="rows of the global k-means leg (one segment, all K centroids); 0 skips it")
     ap.add_argument("--calibration-copy", action="store_true",

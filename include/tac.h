@@ -347,6 +347,48 @@ tac_status tac_gather(tac_ctx ctx, const float* Q_d, int64_t B, int32_t nq, int3
                       const int64_t* list_off_d, const int32_t* list_docs_d, int64_t D, int32_t kc, int32_t kd,
                       int32_t* cand_d, float* score_d);
 
+/* Proximity graph over the centroids, the gather's centroid search (Sect.
+ * 2.2, "Index Structure": the paper builds an HNSW graph over the centroids,
+ * with M = 32 neighbours, Sect. 3).  Row i of nbr_d [K, 64] int32 (output)
+ * holds the 32 centroids of largest <c_i, c_j>, j != i (largest first, lower
+ * id on ties: exact, from float32 products on the matrix cores), then up to
+ * 32 reverse edges: the centroids whose own 32 list i and that i does not
+ * list, largest similarity first, lower id on ties; -1 fills the rest.
+ * C_d [K, d] float32, d = 128, 2 <= K < 2^31.  Asynchronous.  The workspace
+ * holds up to 4 GiB of similarities plus about 260 bytes per centroid. */
+tac_status tac_graph_build(tac_ctx ctx, const float* C_d, int64_t K, int32_t d, int32_t* nbr_d);
+
+/* Centroid search on that graph (step 1 of the gather, approximate like the
+ * paper's HNSW search): for each of the R query-token rows of Q_d [R, d],
+ * the ef router centroids (entry_d [nentry]: distinct centroid ids, e.g. one
+ * per token segment) of largest similarity start a beam of ef entries; the
+ * best entry not yet expanded is expanded (its listed and reverse neighbours
+ * scored once each) until every entry is, and the kc best entries are the
+ * result: top_id_d [R, kc] int32 and top_sim_d [R, kc] float32 (output, best
+ * first, (-1, -inf) where fewer), similarities being float32 dot products in a
+ * fixed order.  1 <= kc <= ef <= 64 (the paper takes ef_s = 1.5 kappa_c).
+ * Deterministic; asynchronous.  TAC_E_INVAL on bad sizes or NULL pointers. */
+tac_status tac_graph_search(tac_ctx ctx, const float* Q_d, int64_t R, int32_t d, const float* C_d, int64_t K,
+                            const int32_t* nbr_d, const int32_t* entry_d, int64_t nentry, int32_t ef, int32_t kc,
+                            int32_t* top_id_d, float* top_sim_d);
+
+/* Step 1 of the gather, exact (as tac_gather): top_id_d [R, kc] int32 and
+ * top_sim_d [R, kc] float32 (output) hold, per query-token row of Q_d [R, d],
+ * the kc centroids of largest <q, c> (float32 matrix-core products; ties to the
+ * lower id; (-1, -inf) where K < kc).  1 <= kc <= 256.  Asynchronous; the
+ * workspace holds up to 4 GiB of similarities. */
+tac_status tac_centroid_topk(tac_ctx ctx, const float* Q_d, int64_t R, int32_t d, const float* C_d, int64_t K,
+                             int32_t kc, int32_t* top_id_d, float* top_sim_d);
+
+/* Steps 2-4 of the gather (as tac_gather) for B queries of nq tokens whose
+ * top-kc centroid lists are given: top_id_d [B, nq, kc] int32 (-1 for an
+ * empty slot, ids < K) with top_sim_d [B, nq, kc] float32, e.g. from
+ * tac_graph_search.  Same inverted lists and outputs as tac_gather.
+ * Synchronous; not for graph capture. */
+tac_status tac_gather_lists(tac_ctx ctx, const int32_t* top_id_d, const float* top_sim_d, int64_t B, int32_t nq,
+                            int32_t kc, const int64_t* list_off_d, const int32_t* list_docs_d, int64_t K, int64_t D,
+                            int32_t kd, int32_t* cand_d, float* score_d);
+
 /* Refine phase of retrieval (Sect. 2.2, "Refine Phase: PQ-Optimized MaxSim
  * Computation"): the MaxSim score of each candidate document for its query,
  *   S(q, d) = sum_i max_{t in d} <q_i, c_{a_t} + rho_t * u_t>,

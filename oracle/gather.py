@@ -26,6 +26,13 @@ Readings (where the paper is silent or approximate):
 Arithmetic is float64; the sum over query tokens is sequential in i.  Pins: a
 hand-worked example, brute force over all documents and invariants in
 ``tests/test_oracle_gather.py``.
+
+The centroid graph the GPU path searches instead of the paper's HNSW
+(``knn_graph``), its best-first search (``beam_search``) and steps 2-4 from
+given top lists (``gather_from_top``) follow at the end; their pins (a
+hand-worked graph, the search reaching the exact set when the beam covers
+every centroid, greedy walks on a path graph, agreement with ``gather``) are
+in ``tests/test_oracle_graph.py``.
 """
 import numpy as np
 
@@ -130,3 +137,103 @@ def document_score_bounds(Q, C, list_off, list_docs, kc, tol):
             hi[d] = hi.get(d, 0.0) + h_i
         sure = set(sure_i) if sure is None else sure | set(sure_i)
     return (sure or set()), lo, hi
+
+
+# ---- the centroid graph (Sect. 2.2, "Index Structure") ---------------------------
+# The paper searches the centroids with an HNSW graph (M = 32 neighbours); the GPU
+# path builds a flat neighbour graph instead and searches it best-first.  These
+# functions state that graph and that search plainly, in float64, so that the
+# GPU's can be checked against them.
+
+def _key_order(sims, ids):
+    """Positions of (sims, ids) by similarity descending, then id ascending."""
+    return np.lexsort((np.asarray(ids), -np.asarray(sims)))
+
+
+def knn_graph(C, deg=32):
+    """Neighbour table int64 [K, 2 deg]: row i lists the deg centroids j != i of
+    largest <c_i, c_j> (ties: lower id), then up to deg reverse edges: the
+    centroids j whose own list holds i and that i does not list, largest <c_i,
+    c_j> first (ties: lower id); -1 fills the rest."""
+    C = np.asarray(C, dtype=np.float64)
+    K = C.shape[0]
+    S = C @ C.T
+    nbr = np.full((K, 2 * deg), -1, dtype=np.int64)
+    fwd = []
+    for i in range(K):
+        others = np.array([j for j in range(K) if j != i], dtype=np.int64)
+        order = others[_key_order(S[i, others], others)][:deg]
+        nbr[i, :order.size] = order
+        fwd.append(set(order.tolist()))
+    for i in range(K):
+        cands = np.array([j for j in range(K) if i in fwd[j] and j not in fwd[i]], dtype=np.int64)
+        if cands.size:
+            order = cands[_key_order(S[i, cands], cands)][:deg]
+            nbr[i, deg:deg + order.size] = order
+    return nbr
+
+
+def beam_search(q, C, nbr, entry, ef, kc):
+    """Best-first search of the neighbour graph for one query token q.
+
+    The ef entry centroids of largest <q, c> (ties: lower id) start the beam;
+    while the beam holds an entry not yet expanded, its best such entry is
+    expanded: each neighbour (in column order) not seen before is scored, and
+    the beam keeps the ef best of its entries and the new ones.  Returns (ids,
+    sims) of the kc best, padded with (-1, -inf)."""
+    q = np.asarray(q, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    entry = np.asarray(entry, dtype=np.int64)
+    es = C[entry] @ q
+    start = entry[_key_order(es, entry)][:ef]
+    seen = set(start.tolist())
+    beam = [(float(C[j] @ q), int(j), False) for j in start.tolist()]
+
+    def top(items):
+        items = sorted(items, key=lambda t: (-t[0], t[1]))
+        return items[:ef]
+
+    beam = top(beam)
+    while True:
+        open_ = [t for t in beam if not t[2]]
+        if not open_:
+            break
+        s, j, _ = open_[0]
+        beam = [(a, b, True) if b == j else (a, b, c) for a, b, c in beam]
+        new = []
+        for n in np.asarray(nbr[j]).tolist():
+            if n < 0 or n in seen:
+                continue
+            seen.add(n)
+            new.append((float(C[n] @ q), int(n), False))
+        beam = top(beam + new)
+    ids = np.full(kc, -1, dtype=np.int64)
+    sims = np.full(kc, -np.inf)
+    for r, (s, j, _) in enumerate(beam[:kc]):
+        ids[r] = j
+        sims[r] = s
+    return ids, sims
+
+
+def gather_from_top(ids, sims, list_off, list_docs, kd):
+    """Steps 2-4 of the gather for one query whose per-token top lists are given
+    (ids [n_q, kc], -1 for an empty slot; sims [n_q, kc]): (docs int32 [kd],
+    scores float64 [kd]) as ``gather`` returns them."""
+    S = {}
+    for i in range(ids.shape[0]):
+        best = {}
+        for j, s in zip(np.asarray(ids[i]).tolist(), np.asarray(sims[i], dtype=np.float64).tolist()):
+            if j < 0:
+                continue
+            for d in np.asarray(list_docs[int(list_off[j]):int(list_off[j + 1])]).tolist():
+                if d not in best or s > best[d]:
+                    best[d] = s
+        for d, s in best.items():
+            S[d] = S.get(d, 0.0) + s
+    items = sorted(S.items(), key=lambda t: (-t[1], t[0]))[:kd]
+    docs = np.full(kd, -1, dtype=np.int32)
+    scores = np.full(kd, -np.inf)
+    for r, (d, s) in enumerate(items):
+        docs[r] = d
+        scores[r] = s
+    return docs, scores

@@ -28,7 +28,8 @@ EXPORTS = ["tac_ctx_create", "tac_ctx_set_stream", "tac_ctx_destroy", "tac_last_
            "tac_init_centroids", "tac_assign", "tac_assign_stats", "tac_update", "tac_residuals", "pq_train",
            "pq_encode", "tac_ctx_enable_timing", "tac_kernel_ms", "tac_ctx_set_tuning", "tac_ctx_get_tuning",
            "tac_ivf_build", "tac_doc_layout", "tac_maxsim", "tac_gather", "tac_ctx_set_static_centroids",
-           "tac_assign_workspace_bytes"]
+           "tac_assign_workspace_bytes", "tac_graph_build", "tac_graph_search", "tac_gather_lists",
+           "tac_centroid_topk"]
 TAC_SLOT_ASSIGN, TAC_SLOT_UPDATE, TAC_SLOT_ENCODE = 0, 1, 2
 
 
@@ -82,6 +83,10 @@ _SIGS = {
     "tac_assign": (C.c_int, [_P, _P, _P, _P, _I64, _I32, _I32, _P, _P, _I64, _I32, _P, _P, _P]),
     "tac_assign_noalloc": (C.c_int, [_P, _P, _P, _P, _I64, _I32, _I32, _P, _P, _I64, _I32, _P, _P, _P]),
     "tac_assign_stats": (C.c_int, [_P, C.POINTER(AssignCounters)]),
+    "tac_graph_build": (C.c_int, [_P, _P, _I64, _I32, _P]),
+    "tac_centroid_topk": (C.c_int, [_P, _P, _I64, _I32, _P, _I64, _I32, _P, _P]),
+    "tac_graph_search": (C.c_int, [_P, _P, _I64, _I32, _P, _I64, _P, _P, _I64, _I32, _I32, _P, _P]),
+    "tac_gather_lists": (C.c_int, [_P, _P, _P, _I64, _I32, _I32, _P, _P, _I64, _I64, _I32, _P, _P]),
     "tac_assign_workspace_bytes": (C.c_int, [_P, _I64, _I32, _P, _I64, _I32, C.c_int, C.c_int,
                                              C.POINTER(C.c_size_t)]),
     "tac_update": (C.c_int, [_P, _P, _P, _I32, _I64, _I32, _P, _P, _I64, _P, _P]),
@@ -409,3 +414,33 @@ def tac_gather(ctx: Context, Q, C_cent, list_off, list_docs, D: int, kc: int, ca
         raise ValueError("tac_gather: inconsistent shapes")
     _check(load().tac_gather(ctx.handle, _dptr(Q), B, nq, d, _dptr(C_cent), K, _dptr(list_off), _dptr(list_docs),
                              D, kc, cand.shape[1], _dptr(cand), _dptr(scores)))
+
+
+def tac_graph_build(ctx: Context, C_cent, nbr):
+    """Neighbour table nbr [K, 64] int32 of the centroid graph (32 nearest, then up to 32 reverse edges)."""
+    _check_dtype(nbr, torch.int32, "nbr")
+    K, d = C_cent.shape
+    if tuple(nbr.shape) != (K, 64):
+        raise ValueError("nbr must be [K, 64]")
+    _check(load().tac_graph_build(ctx.handle, _dptr(C_cent), K, d, _dptr(nbr)))
+
+
+def tac_graph_search(ctx: Context, Q, C_cent, nbr, entry, ef: int, kc: int, top_id, top_sim):
+    """Top-kc centroids per query-token row of Q [R, 128] by beam search on the graph from the routers `entry`."""
+    R, d = Q.shape
+    _check(load().tac_graph_search(ctx.handle, _dptr(Q), R, d, _dptr(C_cent), C_cent.shape[0], _dptr(nbr),
+                                   _dptr(entry), entry.shape[0], ef, kc, _dptr(top_id), _dptr(top_sim)))
+
+
+def tac_gather_lists(ctx: Context, top_id, top_sim, list_off, list_docs, K: int, D: int, kd: int, cand, scores):
+    """Steps 2-4 of the gather from given top lists top_id / top_sim [B, nq, kc]."""
+    B, nq, kc = top_id.shape
+    _check(load().tac_gather_lists(ctx.handle, _dptr(top_id), _dptr(top_sim), B, nq, kc, _dptr(list_off),
+                                   _dptr(list_docs), K, D, kd, _dptr(cand), _dptr(scores)))
+
+
+def tac_centroid_topk(ctx: Context, Q, C_cent, kc: int, top_id, top_sim):
+    """Exact top-kc centroids by inner product per query-token row of Q [R, 128]."""
+    R, d = Q.shape
+    _check(load().tac_centroid_topk(ctx.handle, _dptr(Q), R, d, _dptr(C_cent), C_cent.shape[0], kc, _dptr(top_id),
+                                    _dptr(top_sim)))

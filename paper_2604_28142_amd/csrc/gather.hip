@@ -465,6 +465,247 @@ __global__ void __launch_bounds__(kSelThreads) topk_docs(const uint32_t* __restr
     }
 }
 
+// ---- proximity graph over the centroids (the gather's centroid search) ---------
+// The paper searches the centroids with an HNSW graph (Sect. 2.2, "Index
+// Structure"; built with M = 32 and ef_c = 1500, searched with ef_s = 1.5
+// kappa_c, Sect. 3).  Here the graph is built on the matrix cores and searched
+// one wave per query token:
+// * build: each centroid's kGraphDeg nearest centroids by inner product
+//   (exact: the similarity and top-k kernels above, the centroids as queries,
+//   itself dropped), then up to kGraphDeg reverse edges per centroid (the
+//   centroids that list it, largest similarity first, lower id on ties,
+//   without those it already lists), so that a centroid listed by many keeps
+//   its best in-links and one listed by none is still reachable;
+// * entry: an exhaustive scan of a set of router centroids (the caller's:
+//   e.g. one per token segment) picks the ef best as the starting beam;
+// * search: best-first expansion of a beam of ef <= 64 entries, one per lane,
+//   kept sorted by (similarity descending, id ascending); a visited set in LDS
+//   (open addressing) keeps every centroid from being scored twice; it stops
+//   when every beam entry has been expanded.  Similarities are float32 dot
+//   products accumulated in a fixed order, so the search is deterministic.
+constexpr int kGraphDeg = 32;
+constexpr int kGraphCols = 2 * kGraphDeg;
+constexpr int kSearchWaves = 4;
+constexpr int kHashSlots = 8192;     // visited-set slots per wave (32 KiB of LDS)
+constexpr int kHashProbes = 32;
+constexpr int kMaxEf = 64;
+
+// forward lists from the rows' kGraphDeg + 1 nearest: the centroid itself dropped
+__global__ void graph_forward(const int32_t* __restrict__ top_id, const float* __restrict__ top_sim, int64_t r0,
+                              int64_t R, int32_t* __restrict__ nbr, float* __restrict__ fsim) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const int64_t i = r0 + r;
+    int w = 0;
+    for (int t = 0; t <= kGraphDeg && w < kGraphDeg; ++t) {
+        const int32_t j = top_id[r * (kGraphDeg + 1) + t];
+        if (j < 0 || j == i) continue;
+        nbr[i * kGraphCols + w] = j;
+        fsim[i * kGraphDeg + w] = top_sim[r * (kGraphDeg + 1) + t];
+        ++w;
+    }
+    for (; w < kGraphDeg; ++w) {
+        nbr[i * kGraphCols + w] = -1;
+        fsim[i * kGraphDeg + w] = -INFINITY;
+    }
+}
+
+__global__ void rev_count(const int32_t* __restrict__ nbr, int64_t K, int64_t* __restrict__ cnt) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < K * kGraphDeg;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t j = nbr[(e / kGraphDeg) * kGraphCols + e % kGraphDeg];
+        if (j >= 0) atomicAdd(reinterpret_cast<unsigned long long*>(cnt + j), 1ull);
+    }
+}
+
+__global__ void rev_fill(const int32_t* __restrict__ nbr, const float* __restrict__ fsim, int64_t K,
+                         const int64_t* __restrict__ off, int64_t* __restrict__ cur, int32_t* __restrict__ rsrc,
+                         float* __restrict__ rsim) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < K * kGraphDeg;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / kGraphDeg;
+        const int32_t j = nbr[i * kGraphCols + e % kGraphDeg];
+        if (j < 0) continue;
+        const int64_t p = off[j] + (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(cur + j), 1ull);
+        rsrc[p] = (int32_t)i;
+        rsim[p] = fsim[e];
+    }
+}
+
+// Packed order key of a candidate: larger similarity first, then lower id.
+__device__ __forceinline__ unsigned long long cand_key(float sim, int32_t id) {
+    return ((unsigned long long)fkey(sim) << 32) | (unsigned long long)(~(uint32_t)id);
+}
+
+// One wave per centroid j: its reverse entries (the centroids listing it), those
+// it lists itself excluded, the kGraphDeg best by (similarity, lower id) into
+// columns kGraphDeg .. kGraphCols - 1, -1 where fewer.  The fill order of the
+// entries (atomic) does not matter: the selection is by key.
+__global__ void __launch_bounds__(256) rev_select(const int64_t* __restrict__ off, const int32_t* __restrict__ rsrc,
+                                                  const float* __restrict__ rsim, int64_t K,
+                                                  int32_t* __restrict__ nbr) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= K) return;
+    const int64_t s0 = off[j], n = off[j + 1] - s0;
+    const int32_t mine = lane < kGraphDeg ? nbr[j * kGraphCols + lane] : -1;
+    unsigned long long prev = ~0ull;
+    for (int r = 0; r < kGraphDeg; ++r) {
+        unsigned long long best = 0ull;
+        // whole-wave passes over the entries (lane t0 + lane), so that every lane
+        // takes part in the shuffles that compare a source with j's own list
+        for (int64_t t0 = 0; t0 < n; t0 += 64) {
+            const int64_t t = t0 + lane;
+            const int32_t src = t < n ? rsrc[s0 + t] : -1;
+            bool listed = false;
+            for (int u = 0; u < kGraphDeg; ++u) listed |= __shfl(mine, u) == src;
+            const unsigned long long k = (t >= n || listed) ? 0ull : cand_key(rsim[s0 + t], src);
+            if (k < prev && k > best) best = k;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long ob = __shfl_xor(best, o);
+            best = ob > best ? ob : best;
+        }
+        if (lane == 0) nbr[j * kGraphCols + kGraphDeg + r] = best ? (int32_t)~(uint32_t)best : -1;
+        if (!best) {
+            for (int q = r + 1 + lane; q < kGraphDeg; q += 64) nbr[j * kGraphCols + kGraphDeg + q] = -1;
+            break;
+        }
+        prev = best;
+    }
+}
+
+// router picks -> centroid ids
+__global__ void map_ids(const int32_t* __restrict__ pick, int64_t n, const int32_t* __restrict__ entry,
+                        int32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = pick[i] >= 0 ? entry[pick[i]] : -1;
+}
+
+// router rows; an id outside [0, K) gets a zero row (and its picks are dropped by the search)
+__global__ void gather_rows128(const float* __restrict__ C, int64_t K, const int32_t* __restrict__ ids, int64_t n,
+                               float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 8 + (threadIdx.x >> 5);
+    if (i >= n) return;
+    const int32_t id = ids[i];
+    reinterpret_cast<float4*>(out + i * kGDim)[threadIdx.x & 31] =
+        id >= 0 && id < K ? reinterpret_cast<const float4*>(C + (int64_t)id * kGDim)[threadIdx.x & 31]
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// <q, c> in float32, four interleaved partial sums over the coordinates (i mod 4), then (s0 + s1) + (s2 + s3)
+__device__ __forceinline__ float dot128(const float4 (&q)[32], const float* __restrict__ c) {
+    const float4* cv = reinterpret_cast<const float4*>(c);
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        const float4 v = cv[i];
+        s0 = fmaf(q[i].x, v.x, s0);
+        s1 = fmaf(q[i].y, v.y, s1);
+        s2 = fmaf(q[i].z, v.z, s2);
+        s3 = fmaf(q[i].w, v.w, s3);
+    }
+    return (s0 + s1) + (s2 + s3);
+}
+
+struct SearchShared {
+    int32_t hash[kSearchWaves][kHashSlots];
+    unsigned long long all[kSearchWaves][2 * kMaxEf];
+    unsigned long long beam[kSearchWaves][kMaxEf];
+    int32_t done[kSearchWaves][kMaxEf];
+};
+
+// Visited-set insertion: true when `id` was not in the set (and now is).  A
+// full probe sequence counts as visited, so the search skips that centroid.
+__device__ __forceinline__ bool visit(int32_t* __restrict__ H, int32_t id) {
+    unsigned h = ((unsigned)id * 2654435761u) >> (32 - 13);
+    static_assert(kHashSlots == 1 << 13, "13-bit hash");
+    for (int p = 0; p < kHashProbes; ++p) {
+        const int32_t old = atomicCAS(&H[h], -1, id);
+        if (old == -1) return true;
+        if (old == id) return false;
+        h = (h + 1) & (kHashSlots - 1);
+    }
+    return false;
+}
+
+// One wave per query-token row.  Lane l < ef holds beam entry l (sorted); `done`
+// marks expanded entries.  Each step expands the best entry not expanded yet:
+// its kGraphCols neighbours (one per lane) not visited before are scored, and
+// the ef best of beam and new entries become the beam (every one of the 2 * 64
+// keys is ranked against the others, each lands at its rank).
+__global__ void __launch_bounds__(64 * kSearchWaves) graph_search(const float* __restrict__ Q, int64_t R,
+                                                                   const float* __restrict__ C, int64_t K,
+                                                                   const int32_t* __restrict__ nbr,
+                                                                   const int32_t* __restrict__ init, int ef, int kc,
+                                                                   int max_steps, int32_t* __restrict__ top_id,
+                                                                   float* __restrict__ top_sim,
+                                                                   int32_t* __restrict__ steps_out) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char search_lds[];
+    SearchShared& sh = *reinterpret_cast<SearchShared*>(search_lds);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t row = (int64_t)blockIdx.x * kSearchWaves + w;
+    if (row >= R) return;  // waves are independent: no work-group barrier follows
+    int32_t* H = sh.hash[w];
+    unsigned long long* all = sh.all[w];
+    unsigned long long* bm = sh.beam[w];
+    int32_t* dn = sh.done[w];
+    for (int i = lane; i < kHashSlots; i += 64) H[i] = -1;
+    float4 q[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) q[i] = reinterpret_cast<const float4*>(Q + row * kGDim)[i];
+    // an empty slot's key: below every real key, distinct per position
+    const unsigned long long empty_lo = (unsigned long long)lane, empty_hi = 64ull + lane;
+    // starting beam: the router picks, scored like every other centroid
+    unsigned long long mykey = empty_lo;
+    if (lane < ef) {
+        const int32_t id = init[row * ef + lane];
+        if (id >= 0 && id < K && visit(H, id)) mykey = cand_key(dot128(q, C + (int64_t)id * kGDim), id);
+    }
+    int mydone = 0;
+    // sort by ranking: position = number of larger keys
+    auto rank_merge = [&](unsigned long long a, int da, unsigned long long b) {
+        all[lane] = a;
+        all[64 + lane] = b;
+        __builtin_amdgcn_wave_barrier();
+        int ra = 0, rb = 0;
+        for (int t = 0; t < 128; ++t) {
+            const unsigned long long v = all[t];
+            ra += v > a;
+            rb += v > b;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (ra < ef) { bm[ra] = a; dn[ra] = da; }
+        if (rb < ef) { bm[rb] = b; dn[rb] = 0; }
+        __builtin_amdgcn_wave_barrier();
+        mykey = lane < ef ? bm[lane] : empty_lo;
+        mydone = lane < ef ? dn[lane] : 1;
+        __builtin_amdgcn_wave_barrier();
+    };
+    rank_merge(mykey, 0, empty_hi);
+    int step = 0;
+    for (; step < max_steps; ++step) {
+        const unsigned long long open = __ballot(lane < ef && mykey > 127ull && !mydone);
+        if (!open) break;
+        const int p = __ffsll((long long)open) - 1;
+        const int32_t node = (int32_t)~(uint32_t)__shfl((unsigned)(mykey & 0xFFFFFFFFull), p);
+        if (lane == p) mydone = 1;
+        const int32_t nid = nbr[(int64_t)node * kGraphCols + lane];
+        unsigned long long nk = empty_hi;
+        if (nid >= 0 && nid < K && visit(H, nid)) nk = cand_key(dot128(q, C + (int64_t)nid * kGDim), nid);
+        // the beam's last key: a new key at or below it cannot enter a full beam
+        const unsigned long long worst = __shfl(mykey, ef - 1);
+        if (!__ballot(nk > worst)) continue;
+        rank_merge(mykey, mydone, nk);
+    }
+    if (lane < kc) {
+        const bool ok = mykey > 127ull;
+        top_id[row * kc + lane] = ok ? (int32_t)~(uint32_t)mykey : -1;
+        top_sim[row * kc + lane] = ok ? key_float((uint32_t)(mykey >> 32)) : -INFINITY;
+    }
+    if (steps_out && lane == 0) steps_out[row] = step;
+}
+
 int bits_for(uint64_t maxkey) {
     int b = 1;
     while (b < 32 && (uint64_t(1) << b) <= maxkey) ++b;
@@ -607,6 +848,265 @@ extern "C" tac_status tac_gather(tac_ctx ctx, const float* Q_d, int64_t B, int32
         TAC_LAUNCH_CHECK("seg_qoff");
         topk_docs<<<(unsigned)qc, kSelThreads, 0, s>>>(seg_key, seg_score, qoff, D, kd, cand, score);
         TAC_LAUNCH_CHECK("topk_docs");
+    }
+    return TAC_OK;
+}
+
+namespace {
+
+// Steps 2-4 of the gather for qc queries of nq tokens whose top lists (kc
+// centroids and similarities per token, -1 for an empty slot) are given:
+// list expansion, the per-(query, document) maxima and sums, the kd best
+// documents.  The workspace from `base` on is this function's.
+tac_status gather_from_top(tac_ctx ctx, const int32_t* top_id, const float* top_sim, int64_t qc, int32_t nq,
+                           int32_t kc, const int64_t* list_off_d, const int32_t* list_docs_d, int64_t K, int64_t D,
+                           int32_t kd, int32_t* cand, float* score, size_t base) {
+    hipStream_t s = ctx->stream;
+    const int64_t nent = qc * nq * kc;
+    Carve ca;
+    ca.off = base;
+    const size_t o_eoff = ca.take<int64_t>(nent + 1);
+    const size_t o_scan = ca.take<char>(scan_scratch_bytes(nent));
+    const size_t base_b = ca.off;
+    size_t need = ca.off;
+    int64_t E = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        tac_status st = ws_reserve(ctx, need);
+        if (st != TAC_OK) return st;
+        int64_t* eoff = ws_at<int64_t>(ctx, o_eoff);
+        emit_count<<<grid_for(nent, 256), 256, 0, s>>>(top_id, nent, list_off_d, K, eoff);
+        TAC_LAUNCH_CHECK("emit_count");
+        st = exclusive_scan_i64(s, eoff, eoff, nent, ws_at<void>(ctx, o_scan));
+        if (st != TAC_OK) return st;
+        TAC_HIP(hipMemcpyAsync(&E, eoff + nent, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        TAC_HIP(hipStreamSynchronize(s));
+        Carve cb;
+        cb.off = base_b;
+        const int64_t En = std::max<int64_t>(E, 1);
+        cb.take<uint32_t>(En);
+        cb.take<uint32_t>(En);
+        cb.take<int32_t>(En);
+        cb.take<int32_t>(En);
+        cb.take<int32_t>(En);
+        cb.take<float>(En);
+        cb.take<char>(radix_sort_scratch_bytes(En));
+        cb.take<int64_t>(En + 1);
+        cb.take<int64_t>(En + 1);
+        cb.take<char>(scan_scratch_bytes(En + 1));
+        cb.take<int64_t>(En + 1);
+        cb.take<uint32_t>(En);
+        cb.take<float>(En);
+        cb.take<int64_t>(qc + 1);
+        if (cb.off <= ctx->ws_cap) break;
+        need = cb.off;  // growing drops the workspace's contents: count again after it
+    }
+    int64_t* eoff = ws_at<int64_t>(ctx, o_eoff);
+    Carve cb;
+    cb.off = base_b;
+    if (E == 0) {
+        int64_t* qoff = ws_at<int64_t>(ctx, cb.take<int64_t>(qc + 1));
+        TAC_HIP(hipMemsetAsync(qoff, 0, (qc + 1) * sizeof(int64_t), s));
+        topk_docs<<<(unsigned)qc, kSelThreads, 0, s>>>(nullptr, nullptr, qoff, D, kd, cand, score);
+        TAC_LAUNCH_CHECK("topk_docs");
+        return TAC_OK;
+    }
+    uint32_t* keys = ws_at<uint32_t>(ctx, cb.take<uint32_t>(E));
+    uint32_t* k1 = ws_at<uint32_t>(ctx, cb.take<uint32_t>(E));
+    int32_t* v0 = ws_at<int32_t>(ctx, cb.take<int32_t>(E));
+    int32_t* v1 = ws_at<int32_t>(ctx, cb.take<int32_t>(E));
+    int32_t* tok = ws_at<int32_t>(ctx, cb.take<int32_t>(E));
+    float* simv = ws_at<float>(ctx, cb.take<float>(E));
+    void* sort_scr = ws_at<void>(ctx, cb.take<char>(radix_sort_scratch_bytes(E)));
+    int64_t* flag = ws_at<int64_t>(ctx, cb.take<int64_t>(E + 1));
+    int64_t* fidx = ws_at<int64_t>(ctx, cb.take<int64_t>(E + 1));
+    void* scan2 = ws_at<void>(ctx, cb.take<char>(scan_scratch_bytes(E + 1)));
+    int64_t* start = ws_at<int64_t>(ctx, cb.take<int64_t>(E + 1));
+    uint32_t* seg_key = ws_at<uint32_t>(ctx, cb.take<uint32_t>(E));
+    float* seg_score = ws_at<float>(ctx, cb.take<float>(E));
+    int64_t* qoff = ws_at<int64_t>(ctx, cb.take<int64_t>(qc + 1));
+    {
+        const int waves_per_block = 4;
+        emit_kernel<<<grid_for(nent, waves_per_block), 64 * waves_per_block, 0, s>>>(
+            top_id, top_sim, nent, kc, nq, list_off_d, list_docs_d, K, D, eoff, keys, tok, simv);
+        TAC_LAUNCH_CHECK("emit_kernel");
+    }
+    const uint32_t limit = (uint32_t)(qc * D);
+    int in1 = 0;
+    tac_status st = radix_sort(s, E, bits_for(limit), keys, v0, k1, v1, nullptr, sort_scr, &in1);
+    if (st != TAC_OK) return st;
+    const uint32_t* sk = in1 ? k1 : keys;
+    const int32_t* sv = in1 ? v1 : v0;
+    seg_flags<<<grid_for(E, 256), 256, 0, s>>>(sk, E, limit, flag);
+    TAC_LAUNCH_CHECK("seg_flags");
+    st = exclusive_scan_i64(s, flag, fidx, E, scan2);
+    if (st != TAC_OK) return st;
+    seg_compact<<<grid_for(E, 256), 256, 0, s>>>(flag, fidx, E, start);
+    TAC_LAUNCH_CHECK("seg_compact");
+    seg_reduce<<<grid_for(E, 256), 256, 0, s>>>(sk, sv, E, tok, simv, start, fidx + E, seg_key, seg_score);
+    TAC_LAUNCH_CHECK("seg_reduce");
+    seg_qoff<<<grid_for(qc + 1, 256), 256, 0, s>>>(seg_key, fidx + E, qc, D, qoff);
+    TAC_LAUNCH_CHECK("seg_qoff");
+    topk_docs<<<(unsigned)qc, kSelThreads, 0, s>>>(seg_key, seg_score, qoff, D, kd, cand, score);
+    TAC_LAUNCH_CHECK("topk_docs");
+    return TAC_OK;
+}
+
+bool g_attr_search = false;
+
+}  // namespace
+
+extern "C" tac_status tac_graph_build(tac_ctx ctx, const float* C_d, int64_t K, int32_t d, int32_t* nbr_d) {
+    if (!ctx) return set_error(TAC_E_INVAL, "tac_graph_build: ctx is NULL");
+    if (d != kGDim) return set_error(TAC_E_INVAL, "tac_graph_build: d must be 128");
+    if (K < 2 || K > INT32_MAX) return set_error(TAC_E_INVAL, "tac_graph_build: K must be in [2, 2^31)");
+    if (!C_d || !nbr_d) return set_error(TAC_E_INVAL, "tac_graph_build: NULL pointer");
+    TAC_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int64_t ldS = (K + 3) / 4 * 4;
+    const int kk = kGraphDeg + 1;
+    // rows per pass: the similarity block within kSimBudget
+    const int64_t RC = std::max<int64_t>(64, std::min<int64_t>(K, kSimBudget / (ldS * 4)));
+    Carve cw;
+    const size_t o_fsim = cw.take<float>(K * kGraphDeg);
+    const size_t o_id = cw.take<int32_t>(RC * kk), o_sim = cw.take<float>(RC * kk);
+    const size_t o_S = cw.take<float>(RC * ldS);
+    // the reverse-edge stage reuses the similarity block's memory
+    Carve cr;
+    cr.off = o_S;
+    const size_t o_cnt = cr.take<int64_t>(K + 1), o_off = cr.take<int64_t>(K + 1), o_cur = cr.take<int64_t>(K + 1);
+    const size_t o_scan = cr.take<char>(scan_scratch_bytes(K + 1));
+    const size_t o_rsrc = cr.take<int32_t>(K * kGraphDeg), o_rsim = cr.take<float>(K * kGraphDeg);
+    tac_status st = ws_reserve(ctx, std::max(cw.off, cr.off));
+    if (st != TAC_OK) return st;
+    float* fsim = ws_at<float>(ctx, o_fsim);
+    int32_t* tid = ws_at<int32_t>(ctx, o_id);
+    float* tsim = ws_at<float>(ctx, o_sim);
+    float* S = ws_at<float>(ctx, o_S);
+    for (int64_t r0 = 0; r0 < K; r0 += RC) {
+        const int64_t R = std::min<int64_t>(RC, K - r0);
+        const dim3 sg((unsigned)((K + 1023) / 1024), (unsigned)((R + 63) / 64));
+        sim_kernel<<<sg, 256, 0, s>>>(C_d + r0 * kGDim, R, C_d, K, S, ldS);
+        TAC_LAUNCH_CHECK("sim_kernel");
+        topk_rows<<<(unsigned)R, kSelThreads, 0, s>>>(S, ldS, K, kk, tid, tsim);
+        TAC_LAUNCH_CHECK("topk_rows");
+        graph_forward<<<grid_for(R, 256), 256, 0, s>>>(tid, tsim, r0, R, nbr_d, fsim);
+        TAC_LAUNCH_CHECK("graph_forward");
+    }
+    int64_t* cnt = ws_at<int64_t>(ctx, o_cnt);
+    int64_t* off = ws_at<int64_t>(ctx, o_off);
+    int64_t* cur = ws_at<int64_t>(ctx, o_cur);
+    TAC_HIP(hipMemsetAsync(cnt, 0, (K + 1) * sizeof(int64_t), s));
+    TAC_HIP(hipMemsetAsync(cur, 0, (K + 1) * sizeof(int64_t), s));
+    const unsigned eg = grid_for(K * kGraphDeg, 256);
+    rev_count<<<eg, 256, 0, s>>>(nbr_d, K, cnt);
+    TAC_LAUNCH_CHECK("rev_count");
+    st = exclusive_scan_i64(s, cnt, off, K + 1, ws_at<void>(ctx, o_scan));
+    if (st != TAC_OK) return st;
+    rev_fill<<<eg, 256, 0, s>>>(nbr_d, fsim, K, off, cur, ws_at<int32_t>(ctx, o_rsrc), ws_at<float>(ctx, o_rsim));
+    TAC_LAUNCH_CHECK("rev_fill");
+    rev_select<<<grid_for(K, 4), 256, 0, s>>>(off, ws_at<int32_t>(ctx, o_rsrc), ws_at<float>(ctx, o_rsim), K, nbr_d);
+    TAC_LAUNCH_CHECK("rev_select");
+    return TAC_OK;
+}
+
+extern "C" tac_status tac_graph_search(tac_ctx ctx, const float* Q_d, int64_t R, int32_t d, const float* C_d,
+                                       int64_t K, const int32_t* nbr_d, const int32_t* entry_d, int64_t nentry,
+                                       int32_t ef, int32_t kc, int32_t* top_id_d, float* top_sim_d) {
+    if (!ctx) return set_error(TAC_E_INVAL, "tac_graph_search: ctx is NULL");
+    if (d != kGDim) return set_error(TAC_E_INVAL, "tac_graph_search: d must be 128");
+    if (R < 0 || K < 2 || K > INT32_MAX || nentry < 1 || nentry > K)
+        return set_error(TAC_E_INVAL, "tac_graph_search: bad sizes");
+    if (ef < 1 || ef > kMaxEf || kc < 1 || kc > ef)
+        return set_error(TAC_E_INVAL, "tac_graph_search: need 1 <= kappa_c <= ef <= 64");
+    if (R == 0) return TAC_OK;
+    if (!Q_d || !C_d || !nbr_d || !entry_d || !top_id_d || !top_sim_d)
+        return set_error(TAC_E_INVAL, "tac_graph_search: NULL pointer");
+    TAC_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int64_t ldE = (nentry + 3) / 4 * 4;
+    // query rows per pass: the router similarities within kSimBudget
+    const int64_t RC = std::max<int64_t>(64, std::min<int64_t>(R, kSimBudget / (ldE * 4)));
+    Carve cw;
+    const size_t o_er = cw.take<float>(nentry * kGDim);
+    const size_t o_pick = cw.take<int32_t>(RC * ef), o_psim = cw.take<float>(RC * ef), o_init = cw.take<int32_t>(RC * ef);
+    const size_t o_S = cw.take<float>(RC * ldE);
+    tac_status st = ws_reserve(ctx, cw.off);
+    if (st != TAC_OK) return st;
+    float* Er = ws_at<float>(ctx, o_er);
+    gather_rows128<<<grid_for(nentry, 8), 256, 0, s>>>(C_d, K, entry_d, nentry, Er);
+    TAC_LAUNCH_CHECK("gather_rows128");
+    if (!g_attr_search) {
+        TAC_HIP(hipFuncSetAttribute((const void*)graph_search, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)sizeof(SearchShared)));
+        g_attr_search = true;
+    }
+    for (int64_t r0 = 0; r0 < R; r0 += RC) {
+        const int64_t Rc = std::min<int64_t>(RC, R - r0);
+        const dim3 sg((unsigned)((nentry + 1023) / 1024), (unsigned)((Rc + 63) / 64));
+        sim_kernel<<<sg, 256, 0, s>>>(Q_d + r0 * kGDim, Rc, Er, nentry, ws_at<float>(ctx, o_S), ldE);
+        TAC_LAUNCH_CHECK("sim_kernel");
+        topk_rows<<<(unsigned)Rc, kSelThreads, 0, s>>>(ws_at<float>(ctx, o_S), ldE, nentry, ef,
+                                                       ws_at<int32_t>(ctx, o_pick), ws_at<float>(ctx, o_psim));
+        TAC_LAUNCH_CHECK("topk_rows");
+        map_ids<<<grid_for(Rc * ef, 256), 256, 0, s>>>(ws_at<int32_t>(ctx, o_pick), Rc * ef, entry_d,
+                                                      ws_at<int32_t>(ctx, o_init));
+        TAC_LAUNCH_CHECK("map_ids");
+        graph_search<<<(unsigned)((Rc + kSearchWaves - 1) / kSearchWaves), 64 * kSearchWaves, sizeof(SearchShared),
+                       s>>>(Q_d + r0 * kGDim, Rc, C_d, K, nbr_d, ws_at<int32_t>(ctx, o_init), ef, kc, 64 * ef,
+                            top_id_d + r0 * kc, top_sim_d + r0 * kc, nullptr);
+        TAC_LAUNCH_CHECK("graph_search");
+    }
+    return TAC_OK;
+}
+
+extern "C" tac_status tac_gather_lists(tac_ctx ctx, const int32_t* top_id_d, const float* top_sim_d, int64_t B,
+                                       int32_t nq, int32_t kc, const int64_t* list_off_d, const int32_t* list_docs_d,
+                                       int64_t K, int64_t D, int32_t kd, int32_t* cand_d, float* score_d) {
+    if (!ctx) return set_error(TAC_E_INVAL, "tac_gather_lists: ctx is NULL");
+    if (B < 0 || nq < 1 || nq > 1024 || K < 1 || K > INT32_MAX || D < 1 || D > INT32_MAX)
+        return set_error(TAC_E_INVAL, "tac_gather_lists: bad sizes");
+    if (kc < 1 || kc > kMaxKc) return set_error(TAC_E_INVAL, "tac_gather_lists: kappa_c must be in [1, 256]");
+    if (kd < 1 || kd > kMaxKd) return set_error(TAC_E_INVAL, "tac_gather_lists: kappa_d must be in [1, 4096]");
+    if (B == 0) return TAC_OK;
+    if (!top_id_d || !top_sim_d || !list_off_d || !list_docs_d || !cand_d || !score_d)
+        return set_error(TAC_E_INVAL, "tac_gather_lists: NULL pointer");
+    TAC_HIP(hipSetDevice(ctx->device));
+    // queries per pass: the keys q * D + d within 32 bits
+    const int64_t QC = std::min<int64_t>(B, ((int64_t)UINT32_MAX - 1) / D);
+    if (QC < 1) return set_error(TAC_E_INVAL, "tac_gather_lists: too many documents for 32-bit keys");
+    for (int64_t q0 = 0; q0 < B; q0 += QC) {
+        const int64_t qc = std::min<int64_t>(QC, B - q0);
+        const tac_status st = gather_from_top(ctx, top_id_d + q0 * nq * kc, top_sim_d + q0 * nq * kc, qc, nq, kc,
+                                              list_off_d, list_docs_d, K, D, kd, cand_d + q0 * kd, score_d + q0 * kd, 0);
+        if (st != TAC_OK) return st;
+    }
+    return TAC_OK;
+}
+
+extern "C" tac_status tac_centroid_topk(tac_ctx ctx, const float* Q_d, int64_t R, int32_t d, const float* C_d,
+                                        int64_t K, int32_t kc, int32_t* top_id_d, float* top_sim_d) {
+    if (!ctx) return set_error(TAC_E_INVAL, "tac_centroid_topk: ctx is NULL");
+    if (d != kGDim) return set_error(TAC_E_INVAL, "tac_centroid_topk: d must be 128");
+    if (R < 0 || K < 1 || K > INT32_MAX) return set_error(TAC_E_INVAL, "tac_centroid_topk: bad sizes");
+    if (kc < 1 || kc > kMaxKc) return set_error(TAC_E_INVAL, "tac_centroid_topk: kappa_c must be in [1, 256]");
+    if (R == 0) return TAC_OK;
+    if (!Q_d || !C_d || !top_id_d || !top_sim_d) return set_error(TAC_E_INVAL, "tac_centroid_topk: NULL pointer");
+    TAC_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int64_t ldS = (K + 3) / 4 * 4;
+    const int64_t RC = std::max<int64_t>(64, std::min<int64_t>(R, kSimBudget / (ldS * 4)));
+    Carve cw;
+    const size_t o_S = cw.take<float>(RC * ldS);
+    tac_status st = ws_reserve(ctx, cw.off);
+    if (st != TAC_OK) return st;
+    for (int64_t r0 = 0; r0 < R; r0 += RC) {
+        const int64_t Rc = std::min<int64_t>(RC, R - r0);
+        const dim3 sg((unsigned)((K + 1023) / 1024), (unsigned)((Rc + 63) / 64));
+        sim_kernel<<<sg, 256, 0, s>>>(Q_d + r0 * kGDim, Rc, C_d, K, ws_at<float>(ctx, o_S), ldS);
+        TAC_LAUNCH_CHECK("sim_kernel");
+        topk_rows<<<(unsigned)Rc, kSelThreads, 0, s>>>(ws_at<float>(ctx, o_S), ldS, K, kc, top_id_d + r0 * kc,
+                                                       top_sim_d + r0 * kc);
+        TAC_LAUNCH_CHECK("topk_rows");
     }
     return TAC_OK;
 }

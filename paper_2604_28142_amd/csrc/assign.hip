@@ -57,8 +57,8 @@ __device__ __forceinline__ float dist32_rows(const float* __restrict__ x, const 
     const float4* xv = reinterpret_cast<const float4*>(x);
     const float4* cv = reinterpret_cast<const float4*>(c);
     float acc = 0.f, sx = 0.f;
-    // eight iterations' loads are issued together: four latency rounds per row
-#pragma unroll 8
+    // sixteen iterations' loads are issued together: two latency rounds per row
+#pragma unroll 16
     for (int i = 0; i < kDim / 4; ++i) {
         const float4 a = xv[i];
         const float4 b = cv[i];
@@ -1219,9 +1219,9 @@ __device__ __forceinline__ void screen_item_mx(const Params& P, const ItemDesc& 
         }
     } else {
         // Two waves per SIMD leave half the registers.  A block's operands are
-        // read one k-step ahead instead of one block ahead, and one set of
-        // accumulators serves: the block's inserts follow its MFMAs, while the
-        // SIMD's other wave keeps the matrix cores busy.  Since a block's
+        // read one k-step ahead instead of one block ahead; two accumulator
+        // sets let the previous block's inserts run between this block's
+        // products.  Since a block's
         // operands are read while its own MFMAs run, a stage's buffer is free
         // only once its last block is done: the turn comes before the first
         // block of the next stage (wait for that stage, barrier, then the DMA
@@ -1260,9 +1260,8 @@ __device__ __forceinline__ void screen_item_mx(const Params& P, const ItemDesc& 
                                           stage_cn + ((sn + 2) % kBBufs) * kBCnStride, wave, lane);
         };
         KOps KA, KB;
-        f4 acc[NB];
-        for (int blk = 0; blk < nblk; ++blk) {
-            turn_before(blk);
+        // The MFMAs of block blk into acc; after the i-th product, between(i).
+        auto block_mfmas = [&](int blk, f4 (&acc)[NB], auto&& between) {
             load_k(blk, 0, KA);
             const f4 cb = load_cb(blk);
 #pragma unroll
@@ -1286,13 +1285,57 @@ __device__ __forceinline__ void screen_item_mx(const Params& P, const ItemDesc& 
                             acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(K.ch, F.xh[nb][st4],
                                                                             st4 == 0 ? cb : acc[nb], 0, 0, 0);
                         }
+                        between((st4 * NPR + pr) * NB + nb);
                     }
-                    // round-robin over the accumulators: no product waits on the one before it
-                    if constexpr (PREC == TAC_F16) __builtin_amdgcn_sched_barrier(0);
                 }
             }
-            inserts(blk, acc);
-            flush_if(blk);
+        };
+        // The vector work of block pblk's inserts spread over the next block's
+        // products: one insert after every NPR-th product (the matrix core hides
+        // about two vector instructions per product issued from the same wave,
+        // but none issued from the SIMD's other wave), each key packed one
+        // insert ahead so that no vector instruction waits on the one before.
+        auto pipelined = [&](int blk, f4 (&acc)[NB], int pblk, const f4 (&prev)[NB]) {
+            const unsigned lb = (unsigned)(pblk - epoch_first) * 4u;
+            auto key = [&](int v) {
+                return __uint_as_float(
+                    __builtin_amdgcn_perm(__float_as_uint(prev[v % NB][v / NB]), lb + (unsigned)(v / NB), 0x07060500u));
+            };
+            float kcur = key(0);
+            block_mfmas(blk, acc, [&](int i) {
+                if (i % NPR == NPR - 1) {
+                    const int v = i / NPR;
+                    if (v < 4 * NB) {
+                        const float knext = v + 1 < 4 * NB ? key(v + 1) : 0.f;
+                        list_insert<kBLK<PREC>>(el[v % NB], kcur);
+                        kcur = knext;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            });
+        };
+        // unrolled by two so that the two accumulator sets alternate without copies
+        f4 accA[NB], accB[NB];
+        turn_before(0);
+        block_mfmas(0, accA, [](int) {});
+        for (int blk = 1;; ++blk) {
+            if (blk >= nblk) {
+                inserts(blk - 1, accA);
+                flush_if(blk - 1);
+                break;
+            }
+            turn_before(blk);
+            pipelined(blk, accB, blk - 1, accA);
+            flush_if(blk - 1);
+            ++blk;
+            if (blk >= nblk) {
+                inserts(blk - 1, accB);
+                flush_if(blk - 1);
+                break;
+            }
+            turn_before(blk);
+            pipelined(blk, accA, blk - 1, accB);
+            flush_if(blk - 1);
         }
     }
     finish_item<PREC, NB, kBLK<PREC>, SPLIT, OCC == 1>(P, j, row0, s1, k0, k0 + kc, glist, beta, cnmax, cmax, lane,

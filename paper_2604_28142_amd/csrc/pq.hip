@@ -236,22 +236,30 @@ __global__ void __launch_bounds__(512) train_encode(const float* __restrict__ R,
 
 // ---- matrix-core PQ encoding (M = 32 subspaces, ksub a multiple of 16) ----
 // For subspace m the screen values ||b||^2 + beta - 2 u.b of 16 codes x 16 rows
-// come from one v_mfma_f32_16x16x4f32 (the four coordinates of the subspace
-// are the contraction): lane (g, col) supplies coordinate g of code 16 t + col
-// and of row col, and receives codes 16 t + 4 g + r of row col.  Each lane
-// keeps a top-2 of packed keys over its ksub / 4 codes; the four lanes of a row
-// then rescore their first entries with the canonical distance, take the
-// lexicographic minimum and certify it against every other code, whose screen
-// value is at least the smallest second entry of the four lists (so a second
-// entry can never beat a certified winner and is not rescored); a row that
-// fails is scanned exhaustively after all four row blocks of the wave are
-// certified.
+// come from one v_mfma_f32_16x16x16_f16.  Its contraction holds three products
+// of 16-bit splits: with w = -2u = wh + wl + ew and b = bh + bl + eb (wh, bh
+// the FP16 roundings, wl, bl the FP16 roundings of what is left), the
+// sixteen terms are bh.wh + bl.wh + bh.wl (+ four zeros), so the screen misses
+// only bl.wl, bh.ew, bl.ew and eb.w, a few 2^-22 of ||b|| ||w||.  (On this
+// chip the FP32 matrix instruction and vector instructions do not overlap,
+// while a 16-bit one hides about two vector instructions issued beside it,
+// and costs half the cycles.)  Lane (g, col) supplies k-slice 4g..4g+3: of code
+// 16 t + col (bh, bl, bh, bh) and of row col (wh, wh, wl, 0), and receives
+// codes 16 t + 4 g + r of row col.  Each lane keeps a top-2 of packed keys over
+// its ksub / 4 codes; the four lanes of a row then rescore their first entries
+// with the canonical distance, take the lexicographic minimum and certify it
+// against every other code, whose screen value is at least the smallest
+// second entry of the four lists (so a second entry can never beat a certified
+// winner and is not rescored); a row that fails is scanned exhaustively after
+// all four row blocks of the wave are certified.  The four lanes of a row
+// exchange values with the two lane-swap instructions (rows of 16 lanes
+// swapped in pairs, halves of the wave swapped), not through LDS.
 // Codes are bitwise those of the scalar screen.
 // Work split: the 32 subspaces are encoded by two work-groups per block of
-// 512 rows (16 subspaces each, 80 KiB of codebooks and norms in LDS), so two
-// work-groups share a CU and hide each other's load and shuffle latency.  An
-// input of few row blocks (a serving batch) is split into eight work-groups of
-// 4 subspaces per block instead, so that it spreads over more CUs.
+// 512 rows (16 subspaces each, 80 KiB of split codebooks and norms in LDS), so
+// two work-groups share a CU and hide each other's load latency.  An input of
+// few row blocks (a serving batch) is split into eight work-groups of 4
+// subspaces per block instead, so that it spreads over more CUs.
 constexpr int kEThreads = 512;
 constexpr int kENB = 4;
 constexpr int kERows = (kEThreads / 64) * kENB * 16;
@@ -259,6 +267,8 @@ constexpr int kEHalf = 16;  // subspaces per work-group
 static_assert(kENB * 16 == 64, "one prologue row per lane");
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
 
 // Top-2 (l0 <= l1) of packed keys after two more keys a and b.  The keys are
 // bit patterns of positive floats, so unsigned order is value order.  The new
@@ -293,6 +303,57 @@ __device__ __forceinline__ unsigned screen_key(float v, unsigned codes) {
     return __builtin_amdgcn_perm(__float_as_uint(v), codes, 0x07060500u + r);
 }
 
+// The four lanes (g, col), g = 0..3, of one row exchange one 32-bit value v:
+// afterwards every one of them holds the values of rows g = 0, 1, 2, 3 of the
+// wave's 16-lane rows, in that order.  A swap of odd and even 16-lane rows
+// gives each lane rows (g & ~1, g | 1); a swap of the wave's halves then
+// spreads those over all four rows.
+__device__ __forceinline__ void gather4(unsigned v, unsigned (&o)[4]) {
+    const u2v p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    const u2v q0 = __builtin_amdgcn_permlane32_swap(p[0], p[0], false, false);
+    const u2v q1 = __builtin_amdgcn_permlane32_swap(p[1], p[1], false, false);
+    o[0] = q0[0];
+    o[1] = q1[0];
+    o[2] = q0[1];
+    o[3] = q1[1];
+}
+
+// The value of lane (g ^ 1, col) and of lane (g ^ 2, col) next to the lane's
+// own: the two swaps each return the own value and the partner's, in an order
+// that depends on g, which a symmetric combination does not see.
+__device__ __forceinline__ u2v pair16(unsigned v) { return __builtin_amdgcn_permlane16_swap(v, v, false, false); }
+__device__ __forceinline__ u2v pair32(unsigned v) { return __builtin_amdgcn_permlane32_swap(v, v, false, false); }
+
+// Split FP16 codebook fragments: per code bh = f16(b) and bl = f16(b - bh)
+// (8 bytes each, bh first) and ||b||^2 into LDS; returns the largest ||b||^2,
+// or +inf when a coordinate lies outside the FP16 range (no screen bound then
+// holds and every row is scanned exhaustively).
+__device__ float load_split_codebooks(const float* __restrict__ cbg, int M, int ksub, uint2* lfr, float* lcn) {
+    const int n = M * ksub;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const float4 v = reinterpret_cast<const float4*>(cbg)[i];
+        h4 hi, lo;
+        hi[0] = (_Float16)v.x;
+        hi[1] = (_Float16)v.y;
+        hi[2] = (_Float16)v.z;
+        hi[3] = (_Float16)v.w;
+        lo[0] = (_Float16)(v.x - (float)hi[0]);
+        lo[1] = (_Float16)(v.y - (float)hi[1]);
+        lo[2] = (_Float16)(v.z - (float)hi[2]);
+        lo[3] = (_Float16)(v.w - (float)hi[3]);
+        lfr[2 * i] = __builtin_bit_cast(uint2, hi);
+        lfr[2 * i + 1] = __builtin_bit_cast(uint2, lo);
+        const float nn = v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w;
+        const float am = fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w)));
+        lcn[i] = am < 32768.f ? nn : INFINITY;  // fails for NaN too
+    }
+    __syncthreads();
+    float mx = 0.f;
+    for (int i = threadIdx.x & 63; i < n; i += 64) mx = fmaxf(mx, lcn[i]);
+    for (int m = 32; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
+    return mx;
+}
+
 template <bool RESID, int SUB = kEHalf>
 __global__ void __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(4))) encode_screen(const float* __restrict__ x,
                                                               const int32_t* __restrict__ assign,
@@ -305,19 +366,24 @@ __global__ void __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(
     static_assert(M % SUB == 0 && SUB % 4 == 0, "whole 4-code words per work-group");
     constexpr int G = M / SUB;  // work-groups per row block
     constexpr unsigned kNoKey = 0x7F7FFFFFu;  // FLT_MAX: an empty list entry
-    extern __shared__ float4 lds4[];
+    extern __shared__ uint2 lds2[];
     const int m0 = (int)(blockIdx.x % G) * SUB;
-    float4* lcb = lds4;
-    float* lcn = reinterpret_cast<float*>(lds4 + SUB * ksub);
-    const float cnmax = load_codebooks_norms(cbg + (size_t)m0 * ksub * kDsub, SUB, ksub, lcb, lcn);
-    const float* lcbf = reinterpret_cast<const float*>(lcb);
+    uint2* lfr = lds2;
+    float* lcn = reinterpret_cast<float*>(lds2 + 2 * SUB * ksub);
+    const float cnmax = load_split_codebooks(cbg + (size_t)m0 * ksub * kDsub, SUB, ksub, lfr, lcn);
+    const float4* cbv4 = reinterpret_cast<const float4*>(cbg);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
     const double uc = 5.9604644775390625e-8;  // 2^-24
     const double g6 = 6.0 * uc / (1.0 - 6.0 * uc);
-    const double g10 = 10.0 * uc / (1.0 - 10.0 * uc);
+    const double g44 = 44.0 * uc / (1.0 - 44.0 * uc);
     const double cm2 = (double)cnmax * (1.0 + 1e-5);
     const double scm = sqrt(cm2);
     const int nt = ksub / 16;
+    // lane g's fragment of a code: bh for g = 0, 2, 3 (zero rows of w face g = 3), bl for g = 1
+    const int fsel = g == 1 ? 1 : 0;
+    // bytes of the gathered (wh, wl) pairs that form lane g's k-slice of w: the
+    // four wh, the four wl, or zeros
+    const unsigned wsel = g < 2 ? 0x05040100u : (g == 2 ? 0x07060302u : 0x0C0C0C0Cu);
     const int64_t nblk = gridDim.x / G;
     for (int64_t base = (int64_t)(blockIdx.x / G) * kERows; base < n; base += nblk * kERows) {
         const int64_t wbase = base + wave * (kENB * 16);
@@ -336,48 +402,80 @@ __global__ void __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(
                 ok_row = 1;
             }
         }
-        int arow[kENB], vrow[kENB];
+        // per row block: the centroid row's offset (32-bit; the host keeps K * 128 below 2^32), the norm, validity
+        unsigned coff[kENB];
+        int vrow[kENB];
         float rrow[kENB];
         uint32_t word[kENB];
 #pragma unroll
         for (int nb = 0; nb < kENB; ++nb) {
-            arow[nb] = __shfl(a, nb * 16 + col);
+            const int ar = __shfl(a, nb * 16 + col);
             rrow[nb] = __shfl(rho, nb * 16 + col);
             vrow[nb] = __shfl(ok_row, nb * 16 + col);
+            coff[nb] = vrow[nb] && RESID ? (unsigned)ar * (unsigned)kDim + (unsigned)g : 0u;
             word[nb] = 0u;
         }
         // coordinate 4 m + g of every row block, one subspace ahead of its use
+        // (addresses from the wave's first row and 32-bit lane offsets, so that
+        // no 64-bit address stays live across the subspaces)
+        const float* xw = x + wbase * kDim;
+        const unsigned xl = (unsigned)(col * kDim + g);
         float xs[kENB] = {}, cs[kENB] = {};
         auto fetch = [&](int m) {
 #pragma unroll
             for (int nb = 0; nb < kENB; ++nb) {
                 if (vrow[nb]) {
-                    const int64_t row = wbase + nb * 16 + col;
-                    xs[nb] = x[row * kDim + kDsub * m + g];
-                    if constexpr (RESID) cs[nb] = C[(int64_t)arow[nb] * kDim + kDsub * m + g];
+                    xs[nb] = xw[(unsigned)(nb * 16 * kDim + kDsub * m) + xl];
+                    if constexpr (RESID) cs[nb] = C[coff[nb] + (unsigned)(kDsub * m)];
                 }
             }
         };
         fetch(m0);
         for (int mi = 0; mi < SUB; ++mi) {
             const int m = m0 + mi;
-            float u[kENB], sq[kENB], um = 0.f;
+            // coordinate g of the row's subvector u (canonical residual,
+            // normalised), the FP16 split of w = -2u as this lane's k-slice of
+            // the row (the row's w gathered from its four lanes), and ||u||^2;
+            // the whole u is gathered again where the rescoring needs it
+            float ug[kENB];
+            h4 wk[kENB];
+            float sq[kENB], um = 0.f;
+            bool wok = true;
 #pragma unroll
             for (int nb = 0; nb < kENB; ++nb) {
-                float v = 0.f;
-                if (vrow[nb]) {
-                    if constexpr (RESID) {
-                        v = __fsub_rn(xs[nb], cs[nb]);
-                        if (normalize) v = rrow[nb] > 0.f ? __fdiv_rn(v, rrow[nb]) : 0.f;
-                    } else {
-                        v = xs[nb];
-                    }
+                float v;
+                if constexpr (RESID) {
+                    // without branches: a row out of range has xs = cs = 0
+                    const float dlt = __fsub_rn(xs[nb], cs[nb]);
+                    const float r = rrow[nb];
+                    const float q = __fdiv_rn(dlt, r > 0.f ? r : 1.0f);
+                    v = normalize ? (r > 0.f ? q : 0.f) : dlt;
+                } else {
+                    v = xs[nb];
                 }
-                u[nb] = v;
-                float s = v * v;
-                s += __shfl_xor(s, 16);
-                s += __shfl_xor(s, 32);
-                sq[nb] = s;  // the row's ||u||^2, within a relative 3 u of the exact value
+                v = vrow[nb] ? v : 0.f;
+                ug[nb] = v;
+                const float w = -2.0f * v;
+                const _Float16 wh = (_Float16)w;
+                const _Float16 wl = (_Float16)(w - (float)wh);
+                // |w| within the FP16 range (NaN fails too)
+                wok = wok && fabsf(w) < 32768.f;
+                unsigned dw[4];
+                gather4((unsigned)__builtin_bit_cast(unsigned short, wh) |
+                            ((unsigned)__builtin_bit_cast(unsigned short, wl) << 16),
+                        dw);
+                u2v k2;
+                k2[0] = __builtin_amdgcn_perm(dw[1], dw[0], wsel);
+                k2[1] = __builtin_amdgcn_perm(dw[3], dw[2], wsel);
+                wk[nb] = __builtin_bit_cast(h4, k2);
+                // the row's ||u||^2 (the four lanes' squares summed in pairs),
+                // within a relative 3 u of the exact value
+                const float v2 = __fmul_rn(v, v);
+                const u2v s1 = pair16(__float_as_uint(v2));
+                const float h = __fadd_rn(__uint_as_float(s1[0]), __uint_as_float(s1[1]));
+                const u2v s2 = pair32(__float_as_uint(h));
+                const float s = __fadd_rn(__uint_as_float(s2[0]), __uint_as_float(s2[1]));
+                sq[nb] = s;
                 um = fmaxf(um, s);
             }
             if (mi + 1 < SUB) fetch(m + 1);
@@ -390,75 +488,153 @@ __global__ void __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(
                 l0[nb] = kNoKey;
                 l1[nb] = kNoKey;
             }
-            const float* cbm = lcbf + (size_t)mi * ksub * kDsub;
+            const uint2* frm = lfr + (size_t)mi * ksub * 2 + fsel;
             const float* cnm = lcn + (size_t)mi * ksub;
             // codes 16 t + 4 g + r, r = 0..3, one per byte (at most 255: no carry between bytes)
             unsigned cb4 = (unsigned)(4 * g) * 0x01010101u + 0x03020100u;
             for (int t = 0; t < nt; ++t) {
-                const float af = cbm[(16 * t + col) * kDsub + g];
+                const h4 af = __builtin_bit_cast(h4, frm[(16 * t + col) * 2]);
                 const f4 ci = *reinterpret_cast<const f4*>(cnm + 16 * t + 4 * g) + beta;
 #pragma unroll
                 for (int nb = 0; nb < kENB; ++nb) {
-                    const f4 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af, -2.0f * u[nb], ci, 0, 0, 0);
+                    const f4 acc = __builtin_amdgcn_mfma_f32_16x16x16f16(af, wk[nb], ci, 0, 0, 0);
                     top2_insert2(l0[nb], l1[nb], screen_key<0>(acc[0], cb4), screen_key<1>(acc[1], cb4));
                     top2_insert2(l0[nb], l1[nb], screen_key<2>(acc[2], cb4), screen_key<3>(acc[3], cb4));
                 }
                 cb4 += 0x10101010u;
             }
-            // The screen's error bound for every row of the wave: um bounds ||u||^2 within 3 u.
+            // The first entries' codes, their FP32 codebook rows (from global
+            // memory) requested for all row blocks before any is used.
+            const float4* cbm = cbv4 + (size_t)m * ksub;
+            float4 bv[kENB];
+#pragma unroll
+            for (int nb = 0; nb < kENB; ++nb) bv[nb] = cbm[min((int)(l0[nb] & 0xFFu), ksub - 1)];
             const double bt = (double)beta;
-            const double E = 1.1 * g10 * (2.0 * (cm2 + bt) + 2.0 * sqrt((double)um * (1.0 + g6)) * scm) + 1e-30;
-            const float4* cbv = lcb + (size_t)mi * ksub;
-            int code[kENB];
-            unsigned fail = 0u;
+            float4 uv[kENB];
 #pragma unroll
             for (int nb = 0; nb < kENB; ++nb) {
-                // the row's subvector in every lane of the row
-                float4 uv;
-                uv.x = __shfl(u[nb], col);
-                uv.y = __shfl(u[nb], 16 + col);
-                uv.z = __shfl(u[nb], 32 + col);
-                uv.w = __shfl(u[nb], 48 + col);
+                unsigned uo[4];
+                gather4(__float_as_uint(ug[nb]), uo);
+                uv[nb] = make_float4(__uint_as_float(uo[0]), __uint_as_float(uo[1]), __uint_as_float(uo[2]),
+                                     __uint_as_float(uo[3]));
+            }
+            int code[kENB];
+            float bdr[kENB];
+            unsigned fail = 0u;
+            // a w outside the FP16 range anywhere in the wave: no screen bound holds there
+            const bool wave_bounded = __ballot(!wok) == 0ull;
+#pragma unroll
+            for (int nb = 0; nb < kENB; ++nb) {
                 const unsigned k0 = l0[nb];
                 const int i0 = min((int)(k0 & 0xFFu), ksub - 1);
-                const float e0 = dist4(uv, cbv[i0]);
+                const float e0 = dist4(uv[nb], bv[nb]);
                 float bd = k0 != kNoKey ? e0 : INFINITY;
                 int bi = k0 != kNoKey ? i0 : INT32_MAX;
                 float tau = __uint_as_float(l1[nb] & ~0xFFu);
-#pragma unroll
-                for (int o = 16; o <= 32; o <<= 1) {
-                    const float od = __shfl_xor(bd, o);
-                    const int oi = __shfl_xor(bi, o);
-                    const bool take = od < bd || (od == bd && oi < bi);
-                    bd = take ? od : bd;
-                    bi = take ? oi : bi;
-                    tau = fminf(tau, __shfl_xor(tau, o));
+                // lexicographic minimum of (distance, code) and the smallest
+                // second entry over the row's four lanes
+                {
+                    const u2v pd = pair16(__float_as_uint(bd)), pi = pair16((unsigned)bi);
+                    const bool t1 = __uint_as_float(pd[1]) < __uint_as_float(pd[0]) ||
+                                    (pd[1] == pd[0] && (int)pi[1] < (int)pi[0]);
+                    bd = __uint_as_float(t1 ? pd[1] : pd[0]);
+                    bi = (int)(t1 ? pi[1] : pi[0]);
+                    const u2v pt = pair16(__float_as_uint(tau));
+                    tau = fminf(__uint_as_float(pt[0]), __uint_as_float(pt[1]));
                 }
+                {
+                    const u2v pd = pair32(__float_as_uint(bd)), pi = pair32((unsigned)bi);
+                    const bool t1 = __uint_as_float(pd[1]) < __uint_as_float(pd[0]) ||
+                                    (pd[1] == pd[0] && (int)pi[1] < (int)pi[0]);
+                    bd = __uint_as_float(t1 ? pd[1] : pd[0]);
+                    bi = (int)(t1 ? pi[1] : pi[0]);
+                    const u2v pt = pair32(__float_as_uint(tau));
+                    tau = fminf(__uint_as_float(pt[0]), __uint_as_float(pt[1]));
+                }
+                // The screen's error bound for this row (see the split above):
+                // FP32 accumulation of the norm, the shift and sixteen products
+                // (doubled for the matrix core's unknown summation order), the
+                // dropped split terms, and the FP16 roundings' absolute floor.
+                const double xn = sqrt((double)sq[nb] * (1.0 + g6));  // >= ||u||
+                const double E = 1.1 * (g44 * (2.0 * (cm2 + bt) + 2.02 * 2.0 * xn * scm) +
+                                        6.1 * 2.384185791015625e-7 * 2.0 * xn * scm +
+                                        1.1920928955078125e-7 * (scm + 2.02 * xn)) +
+                                 1e-12;
                 // every code no list kept has screen >= tau; L bounds its canonical distance from below
                 const double L = ((double)tau - E - bt + (double)sq[nb] * (1.0 - g6)) * (1.0 - g6);
                 code[nb] = bi;
-                if (!(bi != INT32_MAX && L > (double)bd)) fail |= 1u << nb;
+                bdr[nb] = bd;
+                const bool bounded = wave_bounded && E < 1e30;
+                if (!(bounded && bi != INT32_MAX && L > (double)bd)) fail |= 1u << nb;
             }
+            // A failed row (every lane of a row has the same verdict) screens
+            // its codes again, bitwise the same values, and rescores every code
+            // whose screen value admits a canonical distance within its best so
+            // far (the certificate's bound read the other way round); rows with
+            // no bound (non-finite or out-of-range operands) scan every code.
             if (__ballot(fail != 0u) != 0ull) {
+                const double bt = (double)beta;
 #pragma unroll
                 for (int nb = 0; nb < kENB; ++nb) {
-                    float4 uv;
-                    uv.x = __shfl(u[nb], col);
-                    uv.y = __shfl(u[nb], 16 + col);
-                    uv.z = __shfl(u[nb], 32 + col);
-                    uv.w = __shfl(u[nb], 48 + col);
-                    if ((fail >> nb) & 1u) {
-                        float best = INFINITY;
-                        int bc = 0;
+                    if (__ballot((fail >> nb) & 1u) == 0ull) continue;
+                    const bool mine = (fail >> nb) & 1u;
+                    const double xn = sqrt((double)sq[nb] * (1.0 + g6));
+                    const double E = 1.1 * (g44 * (2.0 * (cm2 + bt) + 2.02 * 2.0 * xn * scm) +
+                                            6.1 * 2.384185791015625e-7 * 2.0 * xn * scm +
+                                            1.1920928955078125e-7 * (scm + 2.02 * xn)) +
+                                     1e-12;
+                    const bool bounded = wave_bounded && E < 1e30 && bdr[nb] < INFINITY;
+                    float best = mine ? bdr[nb] : INFINITY;
+                    int bc = mine ? code[nb] : INT32_MAX;
+                    if (mine && !bounded) {
+                        best = INFINITY;
+                        bc = 0;
                         for (int b = 0; b < ksub; ++b) {
-                            const float d = dist4(uv, cbv[b]);
+                            const float d = dist4(uv[nb], cbm[b]);
                             if (d < best) {
                                 best = d;
                                 bc = b;
                             }
                         }
-                        code[nb] = bc;
                     }
+                    // canonical distance <= best requires screen <= thr
+                    const float thr = mine && bounded
+                                          ? __double2float_ru((double)best / (1.0 - g6) + E + bt -
+                                                              (double)sq[nb] * (1.0 - g6))
+                                          : -INFINITY;
+                    unsigned cb4 = (unsigned)(4 * g) * 0x01010101u + 0x03020100u;
+                    for (int t = 0; t < nt; ++t) {
+                        const h4 af = __builtin_bit_cast(h4, frm[(16 * t + col) * 2]);
+                        const f4 ci = *reinterpret_cast<const f4*>(cnm + 16 * t + 4 * g) + beta;
+                        const f4 acc = __builtin_amdgcn_mfma_f32_16x16x16f16(af, wk[nb], ci, 0, 0, 0);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            if (acc[r] <= thr) {
+                                const int k = (int)((cb4 >> (8 * r)) & 0xFFu);
+                                const float d = dist4(uv[nb], cbm[k]);
+                                if (d < best || (d == best && k < bc)) {
+                                    best = d;
+                                    bc = k;
+                                }
+                            }
+                        }
+                        cb4 += 0x10101010u;
+                    }
+                    // the row's lexicographic minimum over its four lanes
+                    {
+                        const u2v pd = pair16(__float_as_uint(best)), pi = pair16((unsigned)bc);
+                        const bool t1 = __uint_as_float(pd[1]) < __uint_as_float(pd[0]) ||
+                                        (pd[1] == pd[0] && (int)pi[1] < (int)pi[0]);
+                        best = __uint_as_float(t1 ? pd[1] : pd[0]);
+                        bc = (int)(t1 ? pi[1] : pi[0]);
+                    }
+                    {
+                        const u2v pd = pair32(__float_as_uint(best)), pi = pair32((unsigned)bc);
+                        const bool t1 = __uint_as_float(pd[1]) < __uint_as_float(pd[0]) ||
+                                        (pd[1] == pd[0] && (int)pi[1] < (int)pi[0]);
+                        bc = (int)(t1 ? pi[1] : pi[0]);
+                    }
+                    if (mine) code[nb] = bc;
                 }
             }
 #pragma unroll
@@ -481,8 +657,9 @@ __global__ void __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(
 
 bool g_attr_screen[2] = {false, false};
 
-// LDS of one encode_screen work-group: codebooks and norms of its 16 subspaces.
-size_t screen_lds(int ksub, int sub = kEHalf) { return (size_t)sub * ksub * (kDsub + 1) * sizeof(float); }
+// LDS of one encode_screen work-group: split codebook fragments (16 bytes per
+// code) and norms (4 bytes) of its subspaces.
+size_t screen_lds(int ksub, int sub = kEHalf) { return (size_t)sub * ksub * (4 * sizeof(uint16_t) * 2 + sizeof(float)); }
 bool g_attr_screen4 = false;
 
 // off[t] = first sorted position with key >= t, t in [0, nkeys]
@@ -587,6 +764,7 @@ extern "C" tac_status pq_encode(tac_ctx ctx, const float* x_d, const int32_t* as
     tac_status st = check_pq(d, M, ksub, "pq_encode");
     if (st != TAC_OK) return st;
     if (n < 0 || K < 0) return set_error(TAC_E_INVAL, "pq_encode: bad sizes");
+    if (K >= ((int64_t)1 << 32) / kDim) return set_error(TAC_E_INVAL, "pq_encode: K * 128 must stay below 2^32");
     if (n == 0) return TAC_OK;
     if (!x_d || !assign_d || !codebooks_d || !codes_d || (K > 0 && !C_d))
         return set_error(TAC_E_INVAL, "pq_encode: NULL pointer");

@@ -510,6 +510,18 @@ __global__ void __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
             for (int nb = 0; nb < kENB; ++nb) bv[nb] = cbm[min((int)(l0[nb] & 0xFFu), ksub - 1)];
             const double bt = (double)beta;
+            // The screen's error bound for a row with ||u|| <= xn is E0 + E1 xn
+            // (see the split above): FP32 accumulation of the norm, the shift
+            // and sixteen products (doubled for the matrix core's unknown
+            // summation order), the dropped split terms, and the FP16
+            // roundings' absolute floor, with a 10% margin.
+            const double E0 = 1.1 * (g44 * 2.0 * (cm2 + bt) + 1.1920928955078125e-7 * scm) + 1e-12;
+            const double E1 = 1.1 * (g44 * 2.02 * 2.0 * scm + 6.1 * 2.384185791015625e-7 * 2.0 * scm +
+                                     1.1920928955078125e-7 * 2.02);
+            // xn >= sqrt(||u||^2 (1 + g6)): the hardware square root (within an
+            // ulp or two; a flushed tiny input only drops a term far below E0's
+            // absolute floor) with a relative 2^-19 margin
+            auto xnorm = [](float q) { return (double)(__builtin_amdgcn_sqrtf(q) * (1.0f + 1.9073486328125e-6f)); };
             float4 uv[kENB];
 #pragma unroll
             for (int nb = 0; nb < kENB; ++nb) {
@@ -551,15 +563,7 @@ __global__ void __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(
                     const u2v pt = pair32(__float_as_uint(tau));
                     tau = fminf(__uint_as_float(pt[0]), __uint_as_float(pt[1]));
                 }
-                // The screen's error bound for this row (see the split above):
-                // FP32 accumulation of the norm, the shift and sixteen products
-                // (doubled for the matrix core's unknown summation order), the
-                // dropped split terms, and the FP16 roundings' absolute floor.
-                const double xn = sqrt((double)sq[nb] * (1.0 + g6));  // >= ||u||
-                const double E = 1.1 * (g44 * (2.0 * (cm2 + bt) + 2.02 * 2.0 * xn * scm) +
-                                        6.1 * 2.384185791015625e-7 * 2.0 * xn * scm +
-                                        1.1920928955078125e-7 * (scm + 2.02 * xn)) +
-                                 1e-12;
+                const double E = E0 + E1 * xnorm(sq[nb]);
                 // every code no list kept has screen >= tau; L bounds its canonical distance from below
                 const double L = ((double)tau - E - bt + (double)sq[nb] * (1.0 - g6)) * (1.0 - g6);
                 code[nb] = bi;
@@ -573,16 +577,11 @@ __global__ void __launch_bounds__(kEThreads) __attribute__((amdgpu_waves_per_eu(
             // far (the certificate's bound read the other way round); rows with
             // no bound (non-finite or out-of-range operands) scan every code.
             if (__ballot(fail != 0u) != 0ull) {
-                const double bt = (double)beta;
 #pragma unroll
                 for (int nb = 0; nb < kENB; ++nb) {
                     if (__ballot((fail >> nb) & 1u) == 0ull) continue;
                     const bool mine = (fail >> nb) & 1u;
-                    const double xn = sqrt((double)sq[nb] * (1.0 + g6));
-                    const double E = 1.1 * (g44 * (2.0 * (cm2 + bt) + 2.02 * 2.0 * xn * scm) +
-                                            6.1 * 2.384185791015625e-7 * 2.0 * xn * scm +
-                                            1.1920928955078125e-7 * (scm + 2.02 * xn)) +
-                                     1e-12;
+                    const double E = E0 + E1 * xnorm(sq[nb]);
                     const bool bounded = wave_bounded && E < 1e30 && bdr[nb] < INFINITY;
                     float best = mine ? bdr[nb] : INFINITY;
                     int bc = mine ? code[nb] : INT32_MAX;

@@ -415,3 +415,28 @@ def test_pq_encode_ties_and_fallback(ctx):
     got = host(codes)
     assert np.array_equal(got, exp)
     assert not np.any(got == 40)
+
+
+@pytest.mark.parametrize("n", [700, 40_000])
+def test_pq_encode_beyond_fp16_range(ctx, n):
+    """Operands the split 16-bit screen cannot hold: a codebook coordinate
+    beyond the FP16 range (every row of those subspaces is scanned
+    exhaustively) and, without normalisation, residuals too large for FP16
+    (the whole wave falls back); the codes are still the oracle's."""
+    rng = np.random.default_rng(130)
+    K = 7
+    x = clustered(rng, n, 5)
+    C = x[rng.choice(n, K, replace=False)].copy()
+    a = rng.integers(0, K, n).astype(np.int32)
+    cb = (0.25 * rng.standard_normal((32, 256, 4))).astype(np.float32)
+    cb[9, 17] = [1.0e5, 0.0, 0.0, 0.0]   # never the nearest code, but outside FP16
+    codes = torch.empty((n, 32), dtype=torch.uint8, device="cuda")
+    tac.pq_encode(ctx, dev(x), dev(a), dev(C), dev(cb), codes, normalize=True)
+    u32, _ = oracle.residuals(x, C[a], normalize=True, mode="fp32")
+    assert np.array_equal(host(codes), oracle.pq_encode(u32, cb, decide="fp32"))
+    xb = (x * np.float32(1.0e6)).astype(np.float32)
+    Cb = (C * np.float32(1.0e6)).astype(np.float32)
+    cb2 = (1.0e6 * cb).astype(np.float32)
+    tac.pq_encode(ctx, dev(xb), dev(a), dev(Cb), dev(cb2), codes, normalize=False)
+    u32b, _ = oracle.residuals(xb, Cb[a], normalize=False, mode="fp32")
+    assert np.array_equal(host(codes), oracle.pq_encode(u32b, cb2, decide="fp32"))

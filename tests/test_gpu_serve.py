@@ -120,3 +120,51 @@ def test_graph_replay_equals_eager_and_budget_binds(served):
     finally:
         s_graph.close()
         ex.close()
+
+
+def test_service_large_kappa_routes_match_oracle():
+    """The service on an index with tokens of 2,048 to 9,000 centroids, as the
+    10M- and 50M-row indexes have: batches that hold at most 8,192 rows of such
+    a token take the split route, a batch with more of one takes the persistent
+    route, and every document's assignments, codes and norms equal the oracle's."""
+    rng = np.random.default_rng(77)
+    kappa = np.array([9000, 4096, 2500, 2048, 700, 300, 64, 16, 4, 1], dtype=np.int64)
+    T = kappa.shape[0]
+    cent_off = np.concatenate([[0], np.cumsum(kappa)]).astype(np.int64)
+    K = int(cent_off[-1])
+    base = rng.standard_normal((T, 128)).astype(np.float32)
+    C = np.concatenate([base[j] + 0.35 * rng.standard_normal((kappa[j], 128)).astype(np.float32) for j in range(T)])
+    C /= np.linalg.norm(C, axis=1, keepdims=True)
+    C = C.astype(np.float32)
+    cb = (0.25 * rng.standard_normal((32, 256, 4))).astype(np.float32)
+    index = ResidentIndex(T=T, K=K, C=dev(C), cent_off=dev(cent_off), codebooks=dev(cb))
+
+    def doc(n, weights):
+        t = rng.choice(T, n, p=weights).astype(np.int32)
+        k = cent_off[t] + (rng.random(n) * kappa[t]).astype(np.int64)
+        x = C[k] + 0.2 * rng.standard_normal((n, 128)).astype(np.float32)
+        x /= np.linalg.norm(x, axis=1, keepdims=True)
+        return x.astype(np.float32), t
+
+    w_mix = np.array([0.3, 0.2, 0.15, 0.1, 0.1, 0.05, 0.04, 0.03, 0.02, 0.01])
+    w_one = np.zeros(T)
+    w_one[0] = 1.0
+    docs = [doc(int(rng.integers(40, 200)), w_mix) for _ in range(48)]
+    heavy = [doc(200, w_one) for _ in range(48)]     # 9,600 rows of the 9,000-centroid token in one batch
+    ex = GpuExecutor(index, n_slots=2, max_rows=64 * 200)
+    svc = EncodeService(ex, max_docs=64)
+    try:
+        for group in (docs, heavy):
+            res, _ = run_load(svc, group, None)
+            for (x, t), r in zip(group, res):
+                perm, seg_off, _ = oracle.group_by_token(t, T)
+                o = oracle.assign(x[perm], seg_off, C, cent_off, decide="fp32")
+                a = np.empty_like(o["a"])
+                a[perm] = o["a"]
+                u, rho = oracle.residuals(x, C[a], mode="fp32")
+                assert np.array_equal(r.assign, a)
+                assert np.array_equal(r.codes, oracle.pq_encode(u, cb, decide="fp32"))
+                assert np.array_equal(r.rnorm, rho)
+    finally:
+        svc.close()
+        ex.close()

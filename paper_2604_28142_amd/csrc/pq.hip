@@ -250,8 +250,10 @@ __global__ void __launch_bounds__(512) train_encode(const float* __restrict__ R,
 // with the canonical distance, take the lexicographic minimum and certify it
 // against every other code, whose screen value is at least the smallest
 // second entry of the four lists (so a second entry can never beat a certified
-// winner and is not rescored); a row that fails is scanned exhaustively after
-// all four row blocks of the wave are certified.  The four lanes of a row
+// winner and is not rescored); once all four row blocks of the wave are
+// certified, a row that failed screens its codes again and rescores every
+// code the bound admits (rows without a finite bound scan every code).  The
+// four lanes of a row
 // exchange values with the two lane-swap instructions (rows of 16 lanes
 // swapped in pairs, halves of the wave swapped), not through LDS.
 // Codes are bitwise those of the scalar screen.

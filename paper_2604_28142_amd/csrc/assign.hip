@@ -163,17 +163,22 @@ static_assert(sizeof(ItemDesc) == 32, "one 32-byte record per item");
 
 // item descriptors from the scanned item offsets: items of (class, token) pair
 // idx = class * T + token cut the token's rows into tiles of the class's size,
-// and (class 3) each tile's centroids into chunks; for a split token this also
-// clears its rows' slots (row s0 + q: slot item_off[4T + j] - item_off[4T] + q)
+// split-route items (class 3) into (row tile, centroid chunk) pairs.  One
+// thread per item, which finds its (class, token) by binary search over the
+// offsets, so that a token of thousands of items does not fall to one thread.
 __global__ void plan_fill(const int64_t* __restrict__ item_off, const int64_t* __restrict__ seg_off,
                           const int64_t* __restrict__ cent_off, int32_t T, int screen_rows, int direct_rows,
-                          ItemDesc* __restrict__ desc, unsigned long long* __restrict__ sslot,
-                          int32_t* __restrict__ sflag) {
+                          ItemDesc* __restrict__ desc) {
     const int64_t ncls = 4 * (int64_t)T;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < ncls;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = item_off[idx], e = item_off[idx + 1];
-        if (b == e) continue;
+    const int64_t total = item_off[ncls];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = ncls;  // the last idx with item_off[idx] <= t (a non-empty range)
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (item_off[mid] <= t) lo = mid; else hi = mid;
+        }
+        const int64_t idx = lo, b = item_off[idx];
         const int cls = (int)(idx / T);
         const int32_t j = (int32_t)(idx - (int64_t)cls * T);
         const int64_t rows = cls == 2 ? direct_rows : screen_rows;
@@ -186,23 +191,29 @@ __global__ void plan_fill(const int64_t* __restrict__ item_off, const int64_t* _
         if (cls == 3) {
             const int64_t k0 = d.k0, kc = d.kc;
             const int64_t chunks = (kc + kSplitChunk - 1) / kSplitChunk;
-            for (int64_t t = b; t < e; ++t) {
-                const int64_t tile = (t - b) / chunks, c = (t - b) - tile * chunks;
-                d.row0 = s0 + tile * rows;
-                d.k0 = k0 + c * kSplitChunk;
-                d.kc = (int32_t)min((int64_t)kSplitChunk, kc - c * kSplitChunk);
-                desc[t] = d;
-            }
-            const int64_t sb = item_off[4 * (int64_t)T + j] - item_off[4 * (int64_t)T];
-            for (int64_t q = 0; q < d.s1 - s0; ++q) {
-                sslot[sb + q] = ~0ull;
-                sflag[sb + q] = 0;
-            }
-            continue;
-        }
-        for (int64_t t = b; t < e; ++t) {
+            const int64_t tile = (t - b) / chunks, c = (t - b) - tile * chunks;
+            d.row0 = s0 + tile * rows;
+            d.k0 = k0 + c * kSplitChunk;
+            d.kc = (int32_t)min((int64_t)kSplitChunk, kc - c * kSplitChunk);
+        } else {
             d.row0 = s0 + (t - b) * rows;
-            desc[t] = d;
+        }
+        desc[t] = d;
+    }
+}
+
+// the split route's per-row slots (best candidate, queued flag), one thread per
+// (split token, row)
+__global__ void plan_split_slots(const int64_t* __restrict__ item_off, const int64_t* __restrict__ seg_off,
+                                 int32_t T, unsigned long long* __restrict__ sslot, int32_t* __restrict__ sflag) {
+    const int64_t base = item_off[4 * (int64_t)T];
+    for (int64_t j = blockIdx.x; j < T; j += gridDim.x) {
+        if (item_off[3 * (int64_t)T + j] == item_off[3 * (int64_t)T + j + 1]) continue;
+        const int64_t sb = item_off[4 * (int64_t)T + j] - base;
+        const int64_t n = seg_off[j + 1] - seg_off[j];
+        for (int64_t q = threadIdx.x; q < n; q += blockDim.x) {
+            sslot[sb + q] = ~0ull;
+            sflag[sb + q] = 0;
         }
     }
 }
@@ -1930,9 +1941,14 @@ tac_status assign_run(tac_ctx ctx, char* ws, const AssignPlan& pl, const float* 
     SplitArgs S;
     S.slot = at<unsigned long long>(ws, pl.o_sslot);
     S.flag = at<int32_t>(ws, pl.o_sflag);
-    plan_fill<<<grid_for(ncls, 256), 256, 0, s>>>(cnt, seg, cent_off_d, T, screen_rows, threads,
-                                                    table, S.slot, S.flag);
+    // one thread per item: the grid covers the largest item count a call can have
+    plan_fill<<<grid_for(N / 64 + 4 * (int64_t)T, 256), 256, 0, s>>>(cnt, seg, cent_off_d, T, screen_rows, threads,
+                                                                      table);
     TAC_LAUNCH_CHECK("plan_fill");
+    if (mx16) {
+        plan_split_slots<<<std::min<unsigned>(grid_for(T, 1), 1024u), 256, 0, s>>>(cnt, seg, T, S.slot, S.flag);
+        TAC_LAUNCH_CHECK("plan_split_slots");
+    }
     if (K > 0 && !prepared) {
         // a grid-stride launch of a few blocks per CU keeps the per-block atomicMax on the norm bound cheap
         const unsigned pgrid = std::min<unsigned>(grid_for(K * 32, 256), (unsigned)ctx->props_cu * 16);

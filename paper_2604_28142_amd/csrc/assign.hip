@@ -2004,6 +2004,20 @@ tac_status assign_run(tac_ctx ctx, char* ws, const AssignPlan& pl, const float* 
     int per_cu = mx16 ? occ[occ_slot(precision, k16.nb, occ16)] : occ[0];
     if (ctx->tuning.groups_per_cu > 0 && ctx->tuning.groups_per_cu < per_cu) per_cu = ctx->tuning.groups_per_cu;
     const unsigned grid = (unsigned)ctx->props_cu * (unsigned)per_cu;
+    const unsigned sgrid = (unsigned)ctx->props_cu;
+    if (mx16) {
+        // The split route (no work items outside serving-sized batches: then
+        // the launch finds an empty item range and returns) on the context's
+        // second stream, beside the persistent kernel: its work groups take the
+        // CUs the persistent kernel's tail frees.  The two write disjoint rows
+        // (a split token's rows have only split items) and count fallbacks
+        // with atomics.
+        TAC_HIP(hipEventRecord(ctx->fork_ev, s));
+        TAC_HIP(hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0));
+        k16.split<<<sgrid * (unsigned)occ16, kBThreads, k16.lds, ctx->aux>>>(P, S);
+        TAC_LAUNCH_CHECK("assign_split");
+        TAC_HIP(hipEventRecord(ctx->join_ev, ctx->aux));
+    }
     time_start(ctx, TAC_SLOT_ASSIGN);
     if (precision == TAC_FP32) {
         assign_main<TAC_FP32><<<grid, threads, lds_bytes, s>>>(P);
@@ -2014,11 +2028,7 @@ tac_status assign_run(tac_ctx ctx, char* ws, const AssignPlan& pl, const float* 
     }
     time_stop(ctx, TAC_SLOT_ASSIGN);
     if (mx16) {
-        // the split route (no work items outside serving-sized batches: then the
-        // launches find an empty item range and return)
-        const unsigned sgrid = (unsigned)ctx->props_cu;
-        k16.split<<<sgrid * (unsigned)occ16, kBThreads, k16.lds, s>>>(P, S);
-        TAC_LAUNCH_CHECK("assign_split");
+        TAC_HIP(hipStreamWaitEvent(s, ctx->join_ev, 0));
         split_resolve<<<sgrid, 128, 0, s>>>(cnt, table, T, rowmap, S.slot, S.flag, assign_d, dist, ctx->counters);
         TAC_LAUNCH_CHECK("split_resolve");
     }

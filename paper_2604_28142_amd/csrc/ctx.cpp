@@ -94,6 +94,17 @@ extern "C" tac_status tac_ctx_create(int device, void* hip_stream, size_t max_wo
         delete c;
         return hip_error(e, "hipMemset(counters)");
     }
+    e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        if (c->join_ev) (void)hipEventDestroy(c->join_ev);
+        if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+        if (c->aux) (void)hipStreamDestroy(c->aux);
+        (void)hipFree(c->counters);
+        delete c;
+        return hip_error(e, "tac_ctx_create: auxiliary stream");
+    }
     *out = c;
     return TAC_OK;
 }
@@ -154,5 +165,11 @@ extern "C" void tac_ctx_destroy(tac_ctx ctx) {
     if (ctx->sc_buf) (void)hipFree(ctx->sc_buf);
     for (void* p : ctx->ws_retired) (void)hipFree(p);
     if (ctx->counters) (void)hipFree(ctx->counters);
+    if (ctx->aux) {
+        (void)hipStreamSynchronize(ctx->aux);
+        (void)hipStreamDestroy(ctx->aux);
+    }
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
     delete ctx;
 }

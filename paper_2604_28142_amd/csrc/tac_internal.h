@@ -68,6 +68,10 @@ struct tac_ctx_s {
     int32_t sc_prec = -1;
     void* sc_buf = nullptr;
     size_t sc_bytes = 0;
+    // a second stream (default priority) and two events: the assignment runs
+    // its split route's kernel there, beside the persistent kernel
+    hipStream_t aux = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     // optional HIP-event timing of each entry point's dominant kernel
     bool timing = false;
     hipEvent_t ev[TAC_KERNEL_SLOTS][2] = {};

@@ -92,7 +92,11 @@ typedef struct {
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
  * (a hipStream_t; NULL = the device's null stream).  The context's device
  * allocations (current and replaced workspaces) stay within
- * max_workspace_bytes (0 = no limit).  On success *out holds the context. */
+ * max_workspace_bytes (0 = no limit).  The context also owns a second stream
+ * (default priority) on which tac_assign runs its split-route kernel; every
+ * call forks it from and joins it back to the context's stream with events, so
+ * callers only ever order work on the context's stream.  On success *out holds
+ * the context. */
 tac_status tac_ctx_create(int device, void* hip_stream, size_t max_workspace_bytes, tac_ctx* out);
 
 /* Switch the stream later calls enqueue on.  The caller orders it after any

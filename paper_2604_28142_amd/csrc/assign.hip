@@ -1664,6 +1664,65 @@ __global__ void serve_keys(const int32_t* __restrict__ tok, int64_t n, int32_t T
     }
 }
 
+// The grouping of a small serving batch in one work group: the same stable
+// order and offsets as serve_keys + the radix sort + serve_offsets, without
+// their dozen launches.  Keys (token << 16 | row, rows out of range taking
+// token T) are unique, so an ascending bitonic sort in LDS gives the stable
+// order; offset t is the number of keys below t (a binary search per token).
+constexpr int kSmallGroupThreads = 1024;
+constexpr int kSmallGroupRows = 4096;  // N at most this, T + 1 below 2^16
+__global__ void __launch_bounds__(kSmallGroupThreads) serve_group_small(const int32_t* __restrict__ tok, int32_t n,
+                                                                         int32_t T, int32_t* __restrict__ rowmap,
+                                                                         int64_t* __restrict__ seg_off,
+                                                                         int32_t* __restrict__ assign,
+                                                                         float* __restrict__ dist,
+                                                                         unsigned long long* __restrict__ counters) {
+    __shared__ uint32_t key[kSmallGroupRows];
+    int p2 = 1;
+    while (p2 < n) p2 <<= 1;
+    unsigned bad = 0;
+    for (int i = threadIdx.x; i < p2; i += blockDim.x) {
+        uint32_t k = 0xFFFFFFFFu;  // padding sorts last
+        if (i < n) {
+            const int32_t t = tok[i];
+            const bool ok = t >= 0 && t < T;
+            if (!ok) {
+                assign[i] = -1;
+                dist[i] = 0.f;
+                ++bad;
+            }
+            k = ((uint32_t)(ok ? t : T) << 16) | (uint32_t)i;
+        }
+        key[i] = k;
+    }
+    if (bad) atomicAdd(&counters[kCntUnassigned], (unsigned long long)bad);
+    __syncthreads();
+    for (int size = 2; size <= p2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int q = threadIdx.x; q < (p2 >> 1); q += blockDim.x) {
+                const int lo = 2 * q - (q & (stride - 1));  // pairs (lo, lo + stride)
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const uint32_t a = key[lo], b = key[hi];
+                if ((a > b) == up) {
+                    key[lo] = b;
+                    key[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) rowmap[i] = (int32_t)(key[i] & 0xFFFFu);
+    for (int t = threadIdx.x; t <= T + 1; t += blockDim.x) {
+        int a = 0, b = n;  // the first sorted position whose token is >= t
+        while (a < b) {
+            const int m = (a + b) >> 1;
+            if ((int)(key[m] >> 16) < t) a = m + 1; else b = m;
+        }
+        seg_off[t] = a;
+    }
+}
+
 __global__ void serve_offsets(const uint32_t* __restrict__ keys, int64_t n, int32_t T, int64_t* __restrict__ seg_off) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t prev = i == 0 ? -1 : (int64_t)keys[i - 1];
@@ -1911,19 +1970,28 @@ tac_status assign_run(tac_ctx ctx, char* ws, const AssignPlan& pl, const float* 
         int32_t* v0 = at<int32_t>(ws, pl.o_v0);
         uint32_t* k1 = at<uint32_t>(ws, pl.o_k1);
         int32_t* v1 = at<int32_t>(ws, pl.o_v1);
-        if (N > 0) {
-            serve_keys<<<grid_for(N, 256), 256, 0, s>>>(tok_d, N, T, k0, assign_d, dist, ctx->counters);
-            TAC_LAUNCH_CHECK("serve_keys");
+        if (N <= kSmallGroupRows && (int64_t)T + 1 < 65536) {
+            // a small batch: one work group groups it
+            serve_group_small<<<1, kSmallGroupThreads, 0, s>>>(tok_d, (int32_t)N, T, v0, sseg, assign_d, dist,
+                                                               ctx->counters);
+            TAC_LAUNCH_CHECK("serve_group_small");
+            seg = sseg;
+            rowmap = v0;
+        } else {
+            if (N > 0) {
+                serve_keys<<<grid_for(N, 256), 256, 0, s>>>(tok_d, N, T, k0, assign_d, dist, ctx->counters);
+                TAC_LAUNCH_CHECK("serve_keys");
+            }
+            int bits = 1;
+            while (bits < 31 && (int64_t(1) << bits) < (int64_t)T + 1) ++bits;
+            int in1 = 0;
+            st = radix_sort(s, N, bits, k0, v0, k1, v1, nullptr, at<void>(ws, pl.o_sort), &in1);
+            if (st != TAC_OK) return st;
+            serve_offsets<<<grid_for(N + 1, 256), 256, 0, s>>>(in1 ? k1 : k0, N, T, sseg);
+            TAC_LAUNCH_CHECK("serve_offsets");
+            seg = sseg;
+            rowmap = in1 ? v1 : v0;
         }
-        int bits = 1;
-        while (bits < 31 && (int64_t(1) << bits) < (int64_t)T + 1) ++bits;
-        int in1 = 0;
-        st = radix_sort(s, N, bits, k0, v0, k1, v1, nullptr, at<void>(ws, pl.o_sort), &in1);
-        if (st != TAC_OK) return st;
-        serve_offsets<<<grid_for(N + 1, 256), 256, 0, s>>>(in1 ? k1 : k0, N, T, sseg);
-        TAC_LAUNCH_CHECK("serve_offsets");
-        seg = sseg;
-        rowmap = in1 ? v1 : v0;
     }
     const int threads = mx16 ? kBThreads : kThreads;
     // the 16-bit screens' kernels and row tile (column blocks of 16 rows per wave)

@@ -184,22 +184,26 @@ def test_dyadic_exact_ties_bitwise(ctx):
     check_centroids(host(Cn), C1)
 
 
-def test_serving_path_groups_unsorted_rows(ctx):
+@pytest.mark.parametrize("n", [1, 700, 4096, 4097, 5000])
+def test_serving_path_groups_unsorted_rows(ctx, n):
     """tac_assign with token ids (rows in any order) equals the sorted path;
-    ids outside [0, T) and tokens without centroids give -1."""
+    ids outside [0, T) and tokens without centroids give -1.  Batches of at
+    most 4,096 rows are grouped in one work group, larger ones by the radix
+    sort: both, and the boundary, give the oracle's grouping."""
     c = Case("small")
     rng = np.random.default_rng(14)
-    idx = rng.permutation(c.x.shape[0])[:5000]
+    idx = rng.permutation(c.x.shape[0])[:n]
     x, t = c.x[idx].copy(), c.tok[idx].copy()
-    t[:7] = c.T + 3                                    # invalid ids
+    bad = min(7, n - 1)
+    t[:bad] = c.T + 3                                  # invalid ids
     a = torch.empty(x.shape[0], dtype=torch.int32, device="cuda")
     d = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
     for prec in (0, 1, 2):
         tac.tac_assign(ctx, dev(x), dev(c.C0), dev(c.cent_off), a, tok=dev(t), precision=prec, dist=d)
         ga = host(a)
-        assert np.all(ga[:7] == -1)
-        assert tac.tac_assign_stats(ctx)["unassigned"] >= 7
-        keep = np.arange(7, x.shape[0])
+        assert np.all(ga[:bad] == -1)
+        assert tac.tac_assign_stats(ctx)["unassigned"] >= bad
+        keep = np.arange(bad, x.shape[0])
         perm, seg_off, _ = oracle.group_by_token(t[keep], c.T)
         ref = oracle.assign(x[keep][perm], seg_off, c.C0, c.cent_off, decide="fp32")
         exp = np.empty(keep.shape[0], np.int64)

@@ -33,7 +33,7 @@ __global__ void member_offsets(const uint32_t* __restrict__ keys, int64_t n, int
     }
 }
 
-constexpr int kUnroll = 8;
+constexpr int kUnroll = 16;
 constexpr int64_t kChunk = 256;  // members per chunk of a long run
 
 // wide[k] = 1 when centroid k's token has more than kFp64Rows rows (the token is
@@ -57,48 +57,60 @@ __global__ void centroid_flags(const int64_t* __restrict__ seg_off, int32_t T, c
     }
 }
 
-// Sum of members [b, e) of a run (two dimensions per lane, lane's pair of x
-// columns), in member order; the rows of kUnroll members are loaded before
-// they are added, so that many loads are in flight per wave.  Wide: float64;
-// else a compensated float32 sum, returned as its corrected value.
+// Sum of members [b, e) of a run (b, e wave-uniform; two dimensions per lane,
+// lane's pair of x columns), in member order.  The run's row indices come in
+// with one coalesced load per 64 members and are read out lane by lane, so that
+// the kUnroll row loads of a round depend on no other load and are in flight
+// together; a short round reloads its last row (a cache hit) instead of
+// branching around loads.  Wide: float64; else a compensated float32 sum,
+// returned as its corrected value.
+template <bool Wide>
 __device__ __forceinline__ double2 run_sum(const float* __restrict__ xs, const int32_t* __restrict__ rows, int64_t b,
-                                           int64_t e, bool wide, int lane) {
-    if (wide) {
-        double s0 = 0.0, s1 = 0.0;
-        for (int64_t p = b; p < e; p += kUnroll) {
+                                           int64_t e, int lane) {
+    const float2* xv = reinterpret_cast<const float2*>(xs) + lane;
+    double d0 = 0.0, d1 = 0.0;
+    float s0 = 0.f, s1 = 0.f, c0 = 0.f, c1 = 0.f;
+    for (int64_t g = b; g < e; g += 64) {
+        const int n = (int)(e - g < 64 ? e - g : 64);
+        const int32_t mine = lane < n ? rows[g + lane] : 0;
+        for (int q = 0; q < n; q += kUnroll) {
             float2 v[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
-                if (p + u < e) v[u] = reinterpret_cast<const float2*>(xs + (int64_t)rows[p + u] * kDim)[lane];
+            for (int u = 0; u < kUnroll; ++u) {
+                const int src = q + u < n ? q + u : n - 1;
+                v[u] = xv[(int64_t)__builtin_amdgcn_readlane(mine, src) * (kDim / 2)];
+            }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
-                if (p + u < e) {
-                    s0 += (double)v[u].x;
-                    s1 += (double)v[u].y;
+            for (int u = 0; u < kUnroll; ++u) {
+                if (q + u >= n) continue;
+                if (Wide) {
+                    d0 += (double)v[u].x;
+                    d1 += (double)v[u].y;
+                } else {
+                    float y = __fsub_rn(v[u].x, c0);
+                    float t = __fadd_rn(s0, y);
+                    c0 = __fsub_rn(__fsub_rn(t, s0), y);
+                    s0 = t;
+                    y = __fsub_rn(v[u].y, c1);
+                    t = __fadd_rn(s1, y);
+                    c1 = __fsub_rn(__fsub_rn(t, s1), y);
+                    s1 = t;
                 }
-        }
-        return make_double2(s0, s1);
-    }
-    float s0 = 0.f, s1 = 0.f, c0 = 0.f, c1 = 0.f;
-    for (int64_t p = b; p < e; p += kUnroll) {
-        float2 v[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-            if (p + u < e) v[u] = reinterpret_cast<const float2*>(xs + (int64_t)rows[p + u] * kDim)[lane];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            if (p + u >= e) break;
-            float y = __fsub_rn(v[u].x, c0);
-            float t = __fadd_rn(s0, y);
-            c0 = __fsub_rn(__fsub_rn(t, s0), y);
-            s0 = t;
-            y = __fsub_rn(v[u].y, c1);
-            t = __fadd_rn(s1, y);
-            c1 = __fsub_rn(__fsub_rn(t, s1), y);
-            s1 = t;
+            }
         }
     }
+    if (Wide) return make_double2(d0, d1);
     return make_double2((double)__fsub_rn(s0, c0), (double)__fsub_rn(s1, c1));
+}
+
+__device__ __forceinline__ double2 run_sum(const float* __restrict__ xs, const int32_t* __restrict__ rows, int64_t b,
+                                           int64_t e, bool wide, int lane) {
+    return wide ? run_sum<true>(xs, rows, b, e, lane) : run_sum<false>(xs, rows, b, e, lane);
+}
+
+// wave index, known to the compiler as wave-uniform (scalar loads of off[k])
+__device__ __forceinline__ int64_t wave_id() {
+    return __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
 }
 
 __device__ __forceinline__ float2 run_mean(double2 sum, int64_t cnt, bool wide) {
@@ -115,7 +127,7 @@ __global__ void __launch_bounds__(256) centroid_means(const float* __restrict__ 
                                                       const float* __restrict__ C_old, float* __restrict__ C_new,
                                                       int64_t* __restrict__ count) {
     const int lane = threadIdx.x & 63;
-    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t wave0 = wave_id();
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t k = wave0; k < K; k += nwaves) {
         const int64_t b = off[k], e = off[k + 1];
@@ -147,7 +159,7 @@ __global__ void __launch_bounds__(256) chunk_sums(const float* __restrict__ xs, 
                                                   int64_t K, const int64_t* __restrict__ choff,
                                                   double* __restrict__ part) {
     const int lane = threadIdx.x & 63;
-    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t wave0 = wave_id();
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t total = choff[K];
     for (int64_t c = wave0; c < total; c += nwaves) {

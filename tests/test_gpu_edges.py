@@ -152,6 +152,76 @@ def test_update_long_runs(ctx):
     assert empty.sum() == 2 and np.array_equal(outs[0][empty], C_old[empty])
 
 
+def _kahan32(vals):
+    """Compensated float32 sum of the rows of `vals` in row order, returned as s - c."""
+    s = np.zeros(vals.shape[1], np.float32)
+    c = np.zeros(vals.shape[1], np.float32)
+    for v in vals:
+        y = v - c
+        t = s + y
+        c = (t - s) - y
+        s = t
+    return s - c
+
+
+def _means_in_member_order(xs, a, K, wide_rows, chunk=256):
+    """The update's arithmetic written out: members in ascending row order,
+    runs above `chunk` members summed chunk by chunk and the chunk sums added in
+    chunk order; float64 sums for the centroids in `wide_rows`, compensated
+    float32 sums otherwise."""
+    out = np.zeros((K, xs.shape[1]), np.float32)
+    for k in range(K):
+        m = xs[np.flatnonzero(a == k)]
+        n = m.shape[0]
+        if n == 0:
+            continue
+        parts = [m] if n <= chunk else [m[i:i + chunk] for i in range(0, n, chunk)]
+        if k in wide_rows:
+            sums = [np.cumsum(p.astype(np.float64), axis=0)[-1] for p in parts]
+            tot = np.cumsum(np.stack(sums), axis=0)[-1]
+            out[k] = (tot / n).astype(np.float32)
+        else:
+            sums = np.stack([_kahan32(p) for p in parts]).astype(np.float32)
+            tot = sums[0] if len(parts) == 1 else _kahan32(sums)
+            out[k] = tot / np.float32(n)
+    return out
+
+
+def test_update_run_length_boundaries(ctx):
+    """Cluster sizes at every boundary of the update's loops (16-row load
+    rounds, 64-index groups, 256-member chunks), members interleaved across
+    each token, in a compensated-float32 token and a float64 one (more than
+    65,536 rows): exact counts, means within 1e-5 of the float64 oracle, and
+    bitwise equal to the update's summation order written out in numpy."""
+    rng = np.random.default_rng(29)
+    lens32 = [1, 2, 15, 16, 17, 31, 63, 64, 65, 127, 128, 129, 255, 256, 257, 300, 511, 512, 513, 1000, 0]
+    lens64 = [65, 257, 66000, 0]
+    xs, a, seg, k0 = [], [], [0], 0
+    for lens in (lens32, lens64):
+        lab = np.repeat(np.arange(len(lens)), lens)
+        rng.shuffle(lab)
+        xs.append(clustered(rng, lab.size, 4, spread=0.5))
+        a.append(k0 + lab)
+        seg.append(seg[-1] + lab.size)
+        k0 += len(lens)
+    xs = np.concatenate(xs)
+    a = np.concatenate(a).astype(np.int64)
+    seg_off = np.array(seg, np.int64)
+    K = k0
+    C_old = rng.standard_normal((K, 128)).astype(np.float32)
+    C1, cnt1 = oracle.update(xs, a, C_old)
+    Cn = torch.empty((K, 128), dtype=torch.float32, device="cuda")
+    cnt = torch.empty(K, dtype=torch.int64, device="cuda")
+    tac.tac_update(ctx, dev(xs), dev(seg_off), dev(a.astype(np.int32)), dev(C_old), Cn, cnt)
+    got = host(Cn)
+    assert np.array_equal(host(cnt), cnt1)
+    check_centroids(got, C1)
+    want = _means_in_member_order(xs, a, K, wide_rows=set(range(len(lens32), K)))
+    empty = cnt1 == 0
+    want[empty] = C_old[empty]
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
 def test_dyadic_exact_ties_bitwise(ctx):
     """Dyadic 1-D values in coordinate 0 make every float operation exact, so
     equal distances are exact ties; both paths break them to the lowest index

@@ -43,7 +43,7 @@ TILES = [{"waves_per_simd": 2, "tile_blocks": 3}, {"waves_per_simd": 1, "tile_bl
 SPACE = {
     "tile": TILES,
     "direct_max_kappa": [0, 2, 4, 8, 16],
-    "heavy_kappa": [128, 512, 1024, 2048, 4096, 8192, 16384],
+    "heavy_kappa": [128, 512, 1024, 2048, 4096, 8192, 16384, 1 << 30],  # 2^30: no token queued first
     "groups_per_cu": [0, 1],
 }
 CACHE_ENV = "TAC_AUTOTUNE_CACHE"

@@ -1460,10 +1460,14 @@ __global__ void split_resolve(const int64_t* __restrict__ item_off, const ItemDe
 // queue holds each token's failed rows together (see Params), so a work item
 // is (token j, batch of kFbRows of its failed rows, chunk c of its
 // centroids): the chunk's centroid rows stream once for the whole batch, the
-// FP32 matrix-core screen value cn - 2 x.c of every (row, centroid) pair goes
-// to LDS, and each row rescores exactly every centroid of the chunk whose
-// screen lower bound (screen - E + ||x||^2) (1 - g130) does not exceed the
-// distance in its slot (E is the FP32 screen's error bound).  The slot starts
+// screen value cn - 2 x.c of every (row, centroid) pair goes to LDS, and each
+// row rescores exactly every centroid of the chunk whose screen lower bound
+// (screen - E + ||x||^2) (1 - g130) does not exceed the distance in its slot.
+// The screen is the split-BF16 one of the assignment (three products per
+// coordinate, error bound E as in finish_item); with the FP32 matrix-core
+// product instead, the fallback of the 10M-row workload's second Lloyd
+// assignment took 4.85 ms (FP16 screen, 110,837 rows) and 0.53 ms (BF16,
+// 12,945 rows) against 3.76 and 0.45 ms, with bitwise the same results.  The slot starts
 // at the row's best exact candidate from the screen and takes the 64-bit
 // atomicMin over chunks: non-negative float bits in the high word order like
 // the distances, so it ends at the exact lexicographic (distance, index)
@@ -1473,7 +1477,7 @@ __global__ void split_resolve(const int64_t* __restrict__ item_off, const ItemDe
 constexpr int kFbRows = 32;
 constexpr int kFbChunk = 256;
 constexpr int kFbGroupsPerCu = 3;
-constexpr int kFbXStride = kDim + 4;         // LDS row stride of x (fewer bank conflicts)
+constexpr int kFbBStride = kDim + 8;         // LDS row stride (16-bit values) of the x splits
 constexpr int kFbSStride = kFbChunk + 16;    // LDS row stride of the screen values
 
 __global__ void fb_zero(int32_t* __restrict__ fbcnt, int32_t T) {
@@ -1500,10 +1504,12 @@ __global__ void __launch_bounds__(256) fb_screen(const float* __restrict__ x, co
                                                  const int32_t* __restrict__ fbcnt, const int32_t* __restrict__ fbq,
                                                  const float* __restrict__ fbxx,
                                                  unsigned long long* __restrict__ fbslot) {
-    __shared__ __attribute__((aligned(16))) float xs[kFbRows * kFbXStride];
+    // the batch's rows as BF16 hi / lo splits of -2x (the matrix-core operand), and the screen values
+    __shared__ __attribute__((aligned(16))) unsigned short xb[2 * kFbRows * kFbBStride];
     __shared__ float sv[kFbRows * kFbSStride];
     const double u = 5.9604644775390625e-8;  // 2^-24
     const double g130 = 130.0 * u / (1.0 - 130.0 * u);
+    const double g386 = 386.0 * u / (1.0 - 386.0 * u);
     const float cnmax = __uint_as_float(cstat[0]) * (1.0f + 1e-5f);
     const double cn2 = (double)cnmax, cm = (double)(sqrtf(cnmax) * (1.0f + 1e-6f));
     const int64_t total = woff[T];
@@ -1511,6 +1517,8 @@ __global__ void __launch_bounds__(256) fb_screen(const float* __restrict__ x, co
     const int g = lane >> 4, col = lane & 15;
     constexpr int kTpr = 256 / kFbRows;  // row phase: threads per row
     const int rr = threadIdx.x / kTpr, sub = threadIdx.x % kTpr;
+    unsigned short* xbh = xb;
+    unsigned short* xbl = xb + kFbRows * kFbBStride;
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
         // token: the last j with woff[j] <= w
         int lo_j = 0, hi_j = T;
@@ -1528,37 +1536,51 @@ __global__ void __launch_bounds__(256) fb_screen(const float* __restrict__ x, co
         const int n = (int)min((int64_t)kFbChunk, k0 + kc - lo);
         const int nr = (int)min((int64_t)kFbRows, (int64_t)fbcnt[j] - e0);
         const int64_t qb = seg_off[j] + e0;
-        __syncthreads();  // the previous work item is done with xs and sv
-        for (int e = threadIdx.x; e < kFbRows * (kDim / 4); e += blockDim.x) {
-            const int r = e / (kDim / 4);
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (r < nr) v = reinterpret_cast<const float4*>(x + (int64_t)fbq[qb + r] * kDim)[e % (kDim / 4)];
-            *reinterpret_cast<float4*>(xs + r * kFbXStride + 4 * (e % (kDim / 4))) = v;
+        __syncthreads();  // the previous work item is done with xb and sv
+        for (int e = threadIdx.x; e < kFbRows * (kDim / 8); e += blockDim.x) {
+            const int r = e / (kDim / 8), c8 = e % (kDim / 8);
+            float v8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (r < nr) {
+                const float4* xr = reinterpret_cast<const float4*>(x + (int64_t)fbq[qb + r] * kDim) + 2 * c8;
+                const float4 a = xr[0], b = xr[1];
+                v8[0] = -2.0f * a.x; v8[1] = -2.0f * a.y; v8[2] = -2.0f * a.z; v8[3] = -2.0f * a.w;
+                v8[4] = -2.0f * b.x; v8[5] = -2.0f * b.y; v8[6] = -2.0f * b.z; v8[7] = -2.0f * b.w;
+            }
+            bf8 hi, lo8;
+            split_bf8(v8, hi, lo8);
+            *reinterpret_cast<bf8*>(xbh + r * kFbBStride + 8 * c8) = hi;
+            *reinterpret_cast<bf8*>(xbl + r * kFbBStride + 8 * c8) = lo8;
         }
         __syncthreads();
-        // screen: wave w takes 16-centroid blocks w, w + 4; lane (g, col) holds the
-        // block's centroid row col (coordinates 32 g + [0, 32)) and runs it against
-        // every 16-row block of the batch
+        // screen: wave w takes 16-centroid blocks w, w + 4, ...; lane (g, col) holds
+        // the BF16 hi / lo splits of the block's centroid row col at coordinates
+        // 32 s + 8 g + [0, 8) for the four k-steps s, and runs three products per
+        // k-step (hi.hi, hi.lo, lo.hi) against every 16-row block of the batch
         const int nrb = (nr + 15) / 16;
         for (int cb = wave; cb * 16 < n; cb += 4) {
             const int64_t kb = lo + cb * 16;
-            const float4* cr = reinterpret_cast<const float4*>(C + min(kb + col, lo + n - 1) * kDim + 32 * g);
-            float4 c4[8];
+            const float* cr = C + min(kb + col, lo + n - 1) * kDim + 8 * g;
+            bf8 ch[4], cl[4];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) c4[q] = cr[q];
+            for (int st = 0; st < 4; ++st) {
+                const float4 a = *reinterpret_cast<const float4*>(cr + 32 * st);
+                const float4 b = *reinterpret_cast<const float4*>(cr + 32 * st + 4);
+                const float v8[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+                split_bf8(v8, ch[st], cl[st]);
+            }
             f4 cinit;
 #pragma unroll
             for (int r = 0; r < 4; ++r) cinit[r] = cb * 16 + 4 * g + r < n ? cn[kb + 4 * g + r] : 0.f;
             for (int rb = 0; rb < nrb; ++rb) {
-                const float* xr = xs + (rb * 16 + col) * kFbXStride + 32 * g;
+                const int xo = (rb * 16 + col) * kFbBStride + 8 * g;
                 f4 acc = cinit;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const float4 x4 = *reinterpret_cast<const float4*>(xr + 4 * q);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(c4[q].x, -2.0f * x4.x, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(c4[q].y, -2.0f * x4.y, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(c4[q].z, -2.0f * x4.z, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(c4[q].w, -2.0f * x4.w, acc, 0, 0, 0);
+                for (int st = 0; st < 4; ++st) {
+                    const bf8 xh = *reinterpret_cast<const bf8*>(xbh + xo + 32 * st);
+                    const bf8 xl = *reinterpret_cast<const bf8*>(xbl + xo + 32 * st);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch[st], xh, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch[st], xl, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl[st], xh, acc, 0, 0, 0);
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -1573,10 +1595,12 @@ __global__ void __launch_bounds__(256) fb_screen(const float* __restrict__ x, co
             const unsigned long long s0 = fbslot[qi];
             float bd = s0 == ~0ull ? INFINITY : __uint_as_float((unsigned)(s0 >> 32));
             const double xx = (double)fbxx[qi];
-            const double E = 1.1 * (g130 * (2.0 * cn2 + 2.0 * sqrt(xx * (1.0 + g130)) * cm)) + 1e-30;
+            // the split-BF16 screen's error bound (as in the screen of the item)
+            const double xn = sqrt(xx * (1.0 + g130));
+            const double E = 1.1 * (g386 * (2.0 * cn2 + 2.2 * xn * cm) + 6.2 * 1.52587890625e-5 * xn * cm) + 1e-30;
             const double shift = -E + xx * (1.0 - g130);
             const float* srow = sv + rr * kFbSStride;
-            const float* xrow = xs + rr * kFbXStride;
+            const float* xrow = x + (int64_t)fbq[qi] * kDim;
             float lbd = INFINITY;
             int lbk = INT32_MAX;
             for (int k = sub; k < n; k += kTpr) {

@@ -93,8 +93,7 @@ __device__ __forceinline__ float dist32_xreg(const float4 (&xv)[kDim / 4], const
 }
 
 __device__ __forceinline__ unsigned short bf16_rne(float v) {
-    const unsigned u = __float_as_uint(v);
-    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+    return __builtin_bit_cast(unsigned short, (__bf16)v);  // v_cvt_pk_bf16_f32: round to nearest even
 }
 __device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
@@ -1506,7 +1505,7 @@ __global__ void __launch_bounds__(256) fb_screen(const float* __restrict__ x, co
                                                  unsigned long long* __restrict__ fbslot) {
     // the batch's rows as BF16 hi / lo splits of -2x (the matrix-core operand), and the screen values
     __shared__ __attribute__((aligned(16))) unsigned short xb[2 * kFbRows * kFbBStride];
-    __shared__ float sv[kFbRows * kFbSStride];
+    __shared__ __attribute__((aligned(16))) float sv[kFbRows * kFbSStride];
     const double u = 5.9604644775390625e-8;  // 2^-24
     const double g130 = 130.0 * u / (1.0 - 130.0 * u);
     const double g386 = 386.0 * u / (1.0 - 386.0 * u);
@@ -1603,12 +1602,25 @@ __global__ void __launch_bounds__(256) fb_screen(const float* __restrict__ x, co
             const float* xrow = x + (int64_t)fbq[qi] * kDim;
             float lbd = INFINITY;
             int lbk = INT32_MAX;
-            for (int k = sub; k < n; k += kTpr) {
-                if (((double)srow[k] + shift) * (1.0 - g130) > (double)bd) continue;
-                const float d = dist32_rows(xrow, C + (lo + k) * kDim, nullptr);
-                if (d < lbd || (d == lbd && k < lbk)) {
-                    lbd = d;
-                    lbk = k;
+            // A centroid is a candidate when ((double)s + shift) (1 - g130) <= bd.  The
+            // same test as one float comparison against that bound on s, rounded up
+            // with a margin for the double roundings: its candidates are a superset,
+            // and rescoring more of them changes no result.  A NaN screen value stays
+            // a candidate, as before.
+            const double T0 = (double)bd / (1.0 - g130) - shift;
+            const float thr = __double2float_ru(T0 + fabs(T0) * 1e-12 + 1e-30);
+            for (int k4 = 4 * sub; k4 < n; k4 += 4 * kTpr) {
+                const float4 s4 = *reinterpret_cast<const float4*>(srow + k4);
+                const float sk[4] = {s4.x, s4.y, s4.z, s4.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = k4 + e;
+                    if (k >= n || sk[e] > thr) continue;
+                    const float d = dist32_rows(xrow, C + (lo + k) * kDim, nullptr);
+                    if (d < lbd || (d == lbd && k < lbk)) {
+                        lbd = d;
+                        lbk = k;
+                    }
                 }
             }
             unsigned long long key = lbk < n ? ((unsigned long long)__float_as_uint(lbd) << 32) | (unsigned)(lo + lbk)

@@ -83,15 +83,18 @@ def test_heavy_token_epoch_flush(ctx, n, route):
         check_assign(xs, seg_off, C, cent_off, a, d)
 
 
-def test_forced_certificate_fallback(ctx):
+@pytest.mark.parametrize("scale", [1.0, 1.0e12, 1.0e-12])
+def test_forced_certificate_fallback(ctx, scale):
     """Centroids nearly equidistant from every row defeat the screen's
-    certificate; the exhaustive canonical rescoring still returns the exact argmin."""
+    certificate; the fallback's rescoring still returns the exact argmin, also
+    with every vector scaled far up or down (the fallback's own screen bound at
+    large and small magnitudes)."""
     rng = np.random.default_rng(12)
     k = 700
     dirs = rng.standard_normal((k, 128))
     dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
-    C = (dirs * (1.0 + 1e-7 * rng.standard_normal((k, 1)))).astype(np.float32)
-    xs = (1e-7 * rng.standard_normal((300, 128))).astype(np.float32)
+    C = (scale * dirs * (1.0 + 1e-7 * rng.standard_normal((k, 1)))).astype(np.float32)
+    xs = (scale * 1e-7 * rng.standard_normal((300, 128))).astype(np.float32)
     seg_off = np.array([0, 300], np.int64)
     cent_off = np.array([0, k], np.int64)
     for prec in (0, 1, 2):
